@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Throughput benchmark: PRISM vs multislice STEM probe positions per second.
+
+Workload (fcc1024): 40 x 40 x 100 A Au FCC crystal (a = 4.08 A, 10,000
+atoms, 0.08 A seeded jitter), 1024^2 grid, 50 slices of 2 A, 200 keV,
+25 mrad probe, 256 x 256 scan at 0.15625 A, 16 radial bins to 200 mrad.
+
+One timed step = the whole PRISM path for one specimen: build the compact
+S-matrix (every beam through all 50 slices, quarter-size extraction) and
+compute the detector outputs of all 65,536 probe positions. ``value`` is
+65,536 / step time. The multislice baseline runs the same slice kernels on
+a seeded subset of probes in its own timed region (its rate per probe does
+not depend on the scan size) and is reported beside it with the speed-up.
+
+Per-kernel durations come from HIP events that the library records on the
+launch stream during the timed steps; the dominant kernel's roofline is
+derived from them. ``--no-cpu-baseline`` skips the FP64 oracle timing.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
+CONFIG = "fcc1024"
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--f", type=int, default=4, help="interpolation factor of the headline run")
+    ap.add_argument("--other-f", default="8,16", help="extra f values timed (comma list, '' none)")
+    ap.add_argument("--ms-probes", type=int, default=128, help="multislice probes timed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# algorithmic work per kernel (units summed over the launches of one step)
+
+def kernel_work(name, g):
+    """(kind, amount) of algorithmic work for all launches of ``name`` in one step."""
+    N, H, B, P, W, BA = g["N"], g["H"], g["B"], g["P"], g["W"], g["BA"]
+    state = 4.0 * N * N           # compact wave: N x N/2 complex64
+    if name == "row_pass":
+        # read + write the wave state, plus the slice's transmission once per launch
+        return "hbm", B * H * 2 * state + g["launches"] * 8.0 * N * N
+    if name == "col_pass":
+        return "hbm", B * H * 2 * state
+    if name == "extract":
+        return "hbm", B * (state / 2 + 2.0 * N * N)
+    if name == "beam_init":
+        return "hbm", B * state
+    if name == "contract":
+        return "mfma", 8.0 * BA * W * W * P
+    if name == "window_detect":
+        return "hbm", 8.0 * W * W * P + 8.0 * P * g["n_det"]
+    if name == "transmission":
+        return "hbm", H * N * N * (4.0 + 8.0)
+    return None, 0.0
+
+
+def roofline(prof, g, steps):
+    """Roofline entry for the kernel with the largest total time."""
+    name = max(prof, key=lambda k: prof[k]["total_ms"])
+    ent = dict(prof[name])
+    launches = ent["launches"] / steps
+    g = dict(g, launches=launches)
+    kind, amount = kernel_work(name, g)
+    per_launch_ms = ent["total_ms"] / ent["launches"]
+    per_launch_units = amount / launches
+    if kind == "mfma":
+        achieved = per_launch_units / (per_launch_ms * 1e-3) / 1e12
+        peak, unit = FP32_MFMA_PEAK_TFLOPS, "TFLOP/s"
+    else:
+        achieved = per_launch_units / (per_launch_ms * 1e-3) / 1e9
+        peak, unit = HBM_PEAK_GBS, "GB/s"
+    return name, {
+        "bound": kind, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+        "frac": round(achieved / peak, 4), "traffic": None,
+        "kernel": name, "launches_per_step": launches,
+        "avg_launch_ms": round(per_launch_ms, 4),
+        "algorithmic_per_launch": per_launch_units,
+    }
+
+
+# ---------------------------------------------------------------------------
+
+def cpu_baseline(d, f, amax, P_full):
+    """Time the FP64 oracle on a bounded sample and scale to probes/s."""
+    import oracle as O
+    cores = min(16, os.cpu_count() or 1)
+    F = O.ScipyFFT(workers=cores)
+    lam = O.wavelength(d["energy_keV"])
+    beams = O.beam_set(d["n"], d["cell"], lam, f, amax * 1e-3)
+    B = len(beams)
+    nb = 1
+    t0 = time.perf_counter()
+    _, S1 = O.smatrix(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax, fft=F,
+                      beams=beams[:nb])
+    t_beam = (time.perf_counter() - t0) / nb
+    S = np.repeat(S1, B, axis=0)                 # right shape for timing the probe step
+    npr = 16
+    t0 = time.perf_counter()
+    O.prism_outputs(S, beams, f, d["cell"], d["energy_keV"], d["optics"], d["probes"][:npr],
+                    d["edges"], fft=F)
+    t_probe = (time.perf_counter() - t0) / npr
+    del S
+    t0 = time.perf_counter()
+    O.multislice_stem(d["phase"], d["thickness"], d["cell"], d["energy_keV"], d["optics"],
+                      d["probes"][:1], d["edges"], fft=F)
+    t_ms = time.perf_counter() - t0
+    total = t_beam * B + t_probe * P_full
+    return {
+        "value": round(P_full / total, 3), "unit": "probes/s", "cores": cores, "kind": "oracle",
+        "sample": (f"FP64 oracle, f={f}: S-matrix of {nb} of {B} beams ({t_beam:.2f} s/beam) and "
+                   f"probe step of {npr} of {P_full} probes ({t_probe * 1e3:.1f} ms/probe), "
+                   f"scaled to the full build + scan"),
+        "multislice_probes_per_s": round(1.0 / t_ms, 4),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from synth import build_inputs
+    from paper_1702_01904_amd import Plan, tile_order, untile
+
+    dev = torch.device("cuda:0")
+    t_setup = time.perf_counter()
+    d = build_inputs(CONFIG, args.seed)
+    N, H, P = d["n"], d["phase"].shape[0], len(d["probes"])
+    log(f"inputs ready ({time.perf_counter() - t_setup:.1f} s): N={N} H={H} P={P}")
+    plan = Plan(N, d["cell"], d["energy_keV"], d["thickness"])
+    phase = torch.from_numpy(d["phase"]).to(dev)
+    plan.set_potential_slices(phase)
+    optics, edges = d["optics"], d["edges"]
+    n_det = edges.shape[0]
+
+    def setup_f(f):
+        amax = plan.alpha_max_default(optics["alpha_mrad"], f)
+        B = plan.beam_count(f, amax)
+        S = torch.empty((B, N // 2, N // 2), dtype=torch.complex64, device=dev)
+        wsb = torch.empty(plan.build_workspace_bytes(f, amax)[0], dtype=torch.uint8, device=dev)
+        wsp = torch.empty(plan.probe_workspace_bytes(f, amax, optics)[0], dtype=torch.uint8,
+                          device=dev)
+        _, tx, ty = plan.probe_group(f)
+        perm = tile_order(256, 256, tx, ty)
+        xy = torch.from_numpy(d["probes"][perm]).to(dev)
+        out = torch.empty((P, n_det), dtype=torch.float64, device=dev)
+        lam = plan.wavelength
+        ba = int(np.sum(lam * np.hypot(*(plan.beams(f, amax) * f).T) / d["cell"]
+                        <= optics["alpha_mrad"] * 1e-3))
+        return dict(f=f, amax=amax, B=B, BA=ba, S=S, wsb=wsb, wsp=wsp, perm=perm, xy=xy, out=out)
+
+    def step(c):
+        plan.build_smatrix(c["f"], c["amax"], c["S"], c["wsb"])
+        plan.probe_outputs(c["f"], c["amax"], c["S"], c["xy"], optics, edges, c["out"], c["wsp"])
+
+    def timed(c, steps, warmup, profile):
+        for i in range(warmup):
+            step(c)
+            torch.cuda.synchronize()
+            log(f"f={c['f']} warmup {i + 1}/{warmup} done")
+        if profile:
+            plan.profile(True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            step(c)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        prof = plan.profile_report() if profile else None
+        plan.profile(False)
+        ms = e0.elapsed_time(e1) / steps
+        log(f"f={c['f']} timed {steps} steps: {ms:.2f} ms/step (wall {wall:.2f} s)")
+        return ms, prof
+
+    main_c = setup_f(args.f)
+    ms, prof = timed(main_c, args.steps, args.warmup, True)
+    value = P / (ms * 1e-3)
+    geo = dict(N=N, H=H, B=main_c["B"], BA=main_c["BA"], P=P, W=N // (2 * args.f), n_det=n_det)
+    dom, roof = roofline(prof, geo, args.steps)
+    kernels = {k: round(v["total_ms"] / args.steps, 3) for k, v in prof.items()}
+    out_main = untile(main_c["out"].cpu().numpy(), main_c["perm"])
+    finite = bool(np.all(np.isfinite(out_main)))
+    del main_c
+
+    per_f = {}
+    for f in [int(x) for x in args.other_f.split(",") if x.strip()]:
+        c = setup_f(f)
+        msf, _ = timed(c, max(1, args.steps), 1, False)
+        per_f[str(f)] = {"ms_per_step": round(msf, 3), "probes_per_s": round(P / (msf * 1e-3), 1),
+                         "beams": c["B"], "active_beams": c["BA"]}
+        del c
+
+    # multislice baseline on the same GPU, seeded probe subset
+    rng = np.random.default_rng(args.seed + 7)
+    sub = d["probes"][rng.choice(P, args.ms_probes, replace=False)]
+    xy_ms = torch.from_numpy(sub).to(dev)
+    out_ms = torch.empty((len(sub), n_det), dtype=torch.float64, device=dev)
+    ws_ms = torch.empty(plan.multislice_workspace_bytes(n_det)[0], dtype=torch.uint8, device=dev)
+    plan.multislice_outputs(xy_ms[:8], optics, edges, out_ms, ws_ms)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    plan.multislice_outputs(xy_ms, optics, edges, out_ms, ws_ms)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_multi = e0.elapsed_time(e1)
+    multi_rate = len(sub) / (ms_multi * 1e-3)
+    log(f"multislice: {len(sub)} probes in {ms_multi:.1f} ms -> {multi_rate:.1f} probes/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a bounded sample ...")
+        cpu = cpu_baseline(d, args.f, plan.alpha_max_default(optics["alpha_mrad"], args.f), P)
+        log(f"oracle: {cpu['value']} probes/s on {cpu['cores']} cores")
+
+    rec = {
+        "metric": "STEM probe positions/s, PRISM vs multislice, 1 GPU, at stated rel. error",
+        "value": round(value, 1),
+        "unit": "probes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": f"{CONFIG}: Au FCC 40x40x100 A, 1024^2 grid, 50 slices, 200 keV, "
+                               f"25 mrad, 256x256 scan, 16 bins; PRISM f={args.f} "
+                               f"(S-matrix build + all probes)",
+                   "f": args.f, "grid": N, "slices": H, "probes": P,
+                   "beams": geo["B"], "active_beams": geo["BA"], "window": geo["W"],
+                   "tolerance": "eps_rel <= 1e-4 vs FP64 oracle (tests/test_parity_gpu.py)"},
+        "multislice_probes_per_s": round(multi_rate, 2),
+        "speedup_vs_gpu_multislice": round(value / multi_rate, 2),
+        "per_f": per_f,
+        "kernel_ms_per_step": kernels,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "outputs_finite": finite,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

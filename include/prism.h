@@ -1,0 +1,159 @@
+/*
+ * prism.h - C ABI of the MI355X PRISM / multislice STEM library (libprism).
+ *
+ * Method: C. Ophus, "A Fast Image Simulation Algorithm for Scanning
+ * Transmission Electron Microscopy" (arXiv:1702.01904).
+ *
+ * Conventions shared by every entry point
+ *   - Arrays are row-major and indexed [y][x]; pixel (i, j) of an n x n grid
+ *     sits at (i d/n, j d/n) for a square cell of side d (Angstrom).
+ *   - "dev" pointers are HIP device pointers owned by the caller; "host"
+ *     pointers are read during the call only (or copied into the plan).
+ *   - The library never allocates device memory. Every device buffer it
+ *     needs beyond inputs and outputs comes from a caller-supplied workspace
+ *     whose minimum size the *_workspace_bytes queries return.
+ *   - Compute entry points are asynchronous on the given HIP stream (pass a
+ *     hipStream_t cast to void*, or NULL for the default stream). Device
+ *     faults surface at the caller's next synchronisation.
+ *   - Every call returns PRISM_OK (0) or a negative status. All argument
+ *     checks run on the host before anything is enqueued. prism_last_error()
+ *     returns a thread-local message for the last failing call.
+ *   - Complex values are interleaved float pairs (re, im) ("c64").
+ *
+ * Limits of this implementation: n is a power of two in [128, 2048]; the
+ * PRISM window side W = n / (2 f) is a power of two in [8, 128]; at most
+ * PRISM_MAX_DET detector bins.
+ */
+#ifndef PRISM_H
+#define PRISM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PRISM_OK 0
+#define PRISM_EINVAL (-1)     /* bad argument, shape or unsupported size       */
+#define PRISM_ENOSPACE (-2)   /* workspace smaller than the minimum required   */
+#define PRISM_EHIP (-3)       /* HIP launch/API error (text in last_error)     */
+#define PRISM_ENOTREADY (-4)  /* potential slices not set                      */
+
+#define PRISM_MAX_DET 32
+
+typedef struct prism_plan prism_plan; /* opaque, host-side state only */
+
+/* Sampling of the specimen (Fig. 1a-b: slices and their projected
+ * potentials). slice_thickness_A is copied at plan creation. */
+typedef struct {
+  int n;                           /* grid side in pixels (fine grid)        */
+  double cell_A;                   /* square cell side d in Angstrom         */
+  double energy_keV;               /* beam kinetic energy                    */
+  int n_slices;                    /* H                                      */
+  const double* slice_thickness_A; /* host [n_slices], t_p in Angstrom       */
+} prism_geometry;
+
+/* Probe-forming optics: hard aperture of semi-angle alpha (aperture
+ * equation) and aberration phase chi = pi lambda q^2 C1 +
+ * (pi/2) lambda^3 q^4 C3 (chi equation). */
+typedef struct {
+  double alpha_mrad;
+  double C1_A;
+  double C3_A;
+} prism_optics;
+
+/* Virtual detectors (Fig. 1f): bin j collects the intensity at angles
+ * edges[2j] <= theta < edges[2j+1] (mrad), theta = lambda |q|. */
+typedef struct {
+  int n_det;                  /* 1 .. PRISM_MAX_DET                         */
+  const double* edges_mrad;   /* host [n_det][2]                            */
+} prism_detector;
+
+/* Create a plan for one grid/cell/energy/slicing. Returns PRISM_EINVAL for
+ * n outside the supported sizes, non-positive cell, energy or thickness. */
+int prism_plan_create(prism_plan** out, const prism_geometry* geometry);
+void prism_plan_destroy(prism_plan* plan);
+
+/* Relativistic electron wavelength (Angstrom) used by the plan. */
+int prism_wavelength(const prism_plan* plan, double* lambda_A);
+
+/* PRISM beam set (the plane-wave initial conditions): integer pairs (m, n)
+ * with sqrt(m^2+n^2) f lambda dq <= alpha_max and (m f)^2 + (n f)^2 <
+ * (n/4)^2 so that each survives the half-band anti-aliasing aperture, in
+ * lexicographic (m, n) order. alpha_max_mrad must be positive; the paper's
+ * rule alpha_max = alpha + f lambda dq (choice of alpha_max paragraph) is
+ * the caller's to apply. Requires n % (2 f) == 0. */
+int prism_beam_count(const prism_plan* plan, int f, double alpha_max_mrad, int* n_beams);
+/* Writes min(count, capacity) pairs to mn (host [capacity][2]). */
+int prism_beams(const prism_plan* plan, int f, double alpha_max_mrad, int32_t* mn, int capacity);
+
+/* Bytes of the compact S-matrix: c64 [B][n/2][n/2] (quarter-size storage
+ * enabled by the half-angle anti-aliasing aperture). */
+int prism_smatrix_bytes(const prism_plan* plan, int f, double alpha_max_mrad, size_t* bytes);
+
+/* Workspace sizes. *_min_bytes is the smallest accepted workspace; larger
+ * workspaces let the library process more beams / probes per launch up to
+ * the preferred size returned by *_workspace_bytes. */
+int prism_build_workspace_bytes(const prism_plan* plan, int f, double alpha_max_mrad,
+                                size_t* preferred, size_t* minimum);
+int prism_multislice_workspace_bytes(const prism_plan* plan, int n_det, size_t* preferred,
+                                     size_t* minimum);
+int prism_probe_workspace_bytes(const prism_plan* plan, int f, double alpha_max_mrad,
+                                const prism_optics* optics, size_t* preferred, size_t* minimum);
+
+/* Number of consecutive probes the PRISM probe step treats as one tile.
+ * Probes whose windows overlap (e.g. a gx x gy patch of a raster scan)
+ * should be adjacent in the probe list: a tile shares one union window, so
+ * scattered tiles cost more but still give the same results. */
+int prism_probe_group(const prism_plan* plan, int f, int* group, int* tile_x, int* tile_y);
+
+/* Record the projected phase sigma V_p of every slice (Eq. 4): device
+ * float32 [n_slices][n][n], radians. The pointer is BORROWED: it must stay
+ * valid and unchanged until the stream has passed the last build or
+ * multislice call that reads it. Nothing is copied. */
+int prism_set_potential_slices(prism_plan* plan, const float* phase_dev);
+
+/* Fig. 1c: multislice every beam of the set through all slices (Eq. 5 with
+ * the half-band aperture in the propagator) and store each exit wave at
+ * quarter size: smatrix_dev c64 [B][n/2][n/2], S(i', j') = psi_exit(2i', 2j').
+ * ws/ws_bytes: device workspace, at least the build minimum. */
+int prism_build_smatrix(prism_plan* plan, int f, double alpha_max_mrad, void* smatrix_dev,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* Fig. 1d-f: for each probe position r0 (probe_xy_dev float64 [P][2],
+ * Angstrom) sum the A = 1 beams of the S-matrix, weighted by
+ * alpha_{m,n}(r0) = A e^{-i chi} e^{-2 pi i q.r0} / (W sqrt(B_A)), over the
+ * W x W window of Eq. RegionBounds (centre pixel floor(x0/dx_S + 1/2),
+ * periodic wrap), Fourier transform, and integrate |Psi|^2 / W^2 over each
+ * detector bin: out_dev float64 [P][n_det]. The S-matrix must come from
+ * prism_build_smatrix with the same f and alpha_max_mrad. */
+int prism_probe_outputs(prism_plan* plan, int f, double alpha_max_mrad, const void* smatrix_dev,
+                        const double* probe_xy_dev, int n_probes, const prism_optics* optics,
+                        const prism_detector* detector, double* out_dev, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* Conventional multislice STEM (Eq. 5 run once per probe): incident probe
+ * iFFT[A e^{-i chi} e^{-2 pi i q.r0}] n / sqrt(N_A), H slice steps,
+ * I = |FFT psi_H|^2 / n^2 integrated per detector bin: out_dev float64
+ * [P][n_det]. */
+int prism_multislice_outputs(prism_plan* plan, const double* probe_xy_dev, int n_probes,
+                             const prism_optics* optics, const prism_detector* detector,
+                             double* out_dev, void* ws, size_t ws_bytes, void* stream);
+
+/* Per-kernel timing: while enabled, every kernel launch of this plan is
+ * bracketed by HIP events recorded on its stream. prism_profile_report
+ * waits for the recorded events, writes one line per kernel name
+ * "name launches total_ms min_ms max_ms\n" into buf (NUL-terminated;
+ * PRISM_ENOSPACE if buf_len is too small) and clears the records. */
+int prism_profile_enable(prism_plan* plan, int enable);
+int prism_profile_report(prism_plan* plan, char* buf, size_t buf_len);
+
+/* Thread-local description of the last non-zero status ("" if none). */
+const char* prism_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRISM_H */

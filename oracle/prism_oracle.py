@@ -31,7 +31,7 @@ __all__ = [
     "detector_sums", "ScipyFFT", "DftMatrix", "slice_step", "multislice",
     "entrance_probe", "multislice_stem", "default_alpha_max", "beam_set",
     "plane_wave", "smatrix", "window_origin", "window_indices",
-    "prism_coefficients", "prism_probe_wave", "prism_outputs",
+    "prism_coefficients", "prism_probe_wave", "prism_outputs", "prism_probe_direct",
     "t_multi", "t_prism", "time_ratio", "rel_l2", "one_minus_r2",
 ]
 
@@ -359,6 +359,41 @@ def prism_outputs(S, beams, f, cell, energy_keV, optics, probes, edges_mrad, fft
         if return_cbed:
             cbed[p] = I
     return (out, cbed) if return_cbed else out
+
+
+def prism_probe_direct(phase, thickness, cell, energy_keV, f, alpha_max_mrad, optics, x0, y0,
+                       edges_mrad, fft=None):
+    """PRISM output of one probe without forming the S-matrix.
+
+    By linearity of Eq. 5, the window sum of Eq. PRISMfinal equals the window
+    of the quarter-size exit wave of the periodised probe
+    psi0 = sum_b alpha_b exp(2 pi i q_b . r). One multislice run per probe
+    therefore gives PRISM's output exactly (identity checked against
+    ``prism_outputs``); this is how single probes of large grids are sampled.
+    Returns float64 [n_det].
+    """
+    F = _fft(fft)
+    phase = np.asarray(phase, dtype=np.float64)
+    n = phase.shape[-1]
+    lam = wavelength(energy_keV)
+    dq = 1.0 / cell
+    beams = beam_set(n, cell, lam, f, alpha_max_mrad * 1e-3)
+    ns = n // 2
+    w = ns // f
+    alpha, A = prism_coefficients(beams, f, cell, lam, optics, x0, y0)
+    coef = alpha / (w * math.sqrt(int(A.sum())))
+    psi0 = np.zeros((n, n), dtype=np.complex128)
+    for c, (m, nn) in zip(coef, beams):
+        if c != 0:
+            psi0 += c * plane_wave(n, m, nn, f)
+    exit_ = multislice(psi0, phase, thickness, lam, dq, True, F)[::2, ::2]
+    dxs = cell / ns
+    rows = window_indices(y0, ns, w, dxs)
+    cols = window_indices(x0, ns, w, dxs)
+    win = exit_[np.ix_(rows, cols)]
+    I = np.abs(F.fft2(win)) ** 2 / float(w * w)
+    theta = theta_of_k2(k2_grid(w, scale=f), lam, dq)
+    return detector_sums(I, theta, edges_mrad)
 
 
 # --------------------------------------------------------------------------

@@ -1,0 +1,221 @@
+"""MI355X PRISM / multislice STEM simulation (Ophus, arXiv:1702.01904).
+
+Thin Python layer over libprism (C ABI in include/prism.h). PyTorch is used
+only to own device memory and streams; every step of the simulation runs
+in the library's HIP kernels. Tensors passed in must already live on the
+GPU with the stated dtype and shape; nothing is copied implicitly.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _native
+from ._native import PrismError, PrismOptics, PrismDetector, PrismGeometry  # noqa: F401
+
+__all__ = ["Plan", "PrismError", "tile_order", "untile"]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _optics(optics):
+    return PrismOptics(float(optics["alpha_mrad"]), float(optics.get("C1_A", 0.0)),
+                       float(optics.get("C3_A", 0.0)))
+
+
+class _Det:
+    """Keeps the edges array alive while the C struct points at it."""
+
+    def __init__(self, edges_mrad):
+        self.edges = np.ascontiguousarray(np.asarray(edges_mrad, dtype=np.float64).reshape(-1, 2))
+        self.struct = PrismDetector(self.edges.shape[0],
+                                    self.edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+
+
+def _check_dev(t, dtype, numel=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+
+
+class Plan:
+    """One grid / cell / energy / slicing (prism_plan)."""
+
+    def __init__(self, n, cell_A, energy_keV, slice_thickness_A):
+        self._L = _native.lib()
+        th = np.ascontiguousarray(np.asarray(slice_thickness_A, dtype=np.float64))
+        g = PrismGeometry(int(n), float(cell_A), float(energy_keV), int(th.size),
+                          th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        h = ctypes.c_void_p()
+        _native.check(self._L.prism_plan_create(ctypes.byref(h), ctypes.byref(g)))
+        self._h = h
+        self.n = int(n)
+        self.cell = float(cell_A)
+        self.energy_keV = float(energy_keV)
+        self.n_slices = int(th.size)
+        self._phase = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.prism_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ host queries
+    @property
+    def wavelength(self):
+        v = ctypes.c_double()
+        _native.check(self._L.prism_wavelength(self._h, ctypes.byref(v)))
+        return v.value
+
+    def alpha_max_default(self, alpha_mrad, f):
+        """alpha + f lambda dq in mrad (choice of alpha_max in the paper)."""
+        return float(alpha_mrad) + f * (self.wavelength * (1.0 / self.cell)) * 1e3
+
+    def beam_count(self, f, alpha_max_mrad):
+        v = ctypes.c_int()
+        _native.check(self._L.prism_beam_count(self._h, int(f), float(alpha_max_mrad),
+                                               ctypes.byref(v)))
+        return v.value
+
+    def beams(self, f, alpha_max_mrad):
+        B = self.beam_count(f, alpha_max_mrad)
+        out = np.zeros((B, 2), dtype=np.int32)
+        _native.check(self._L.prism_beams(self._h, int(f), float(alpha_max_mrad),
+                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), B))
+        return out
+
+    def smatrix_bytes(self, f, alpha_max_mrad):
+        v = ctypes.c_size_t()
+        _native.check(self._L.prism_smatrix_bytes(self._h, int(f), float(alpha_max_mrad),
+                                                  ctypes.byref(v)))
+        return v.value
+
+    def build_workspace_bytes(self, f, alpha_max_mrad):
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        _native.check(self._L.prism_build_workspace_bytes(self._h, int(f), float(alpha_max_mrad),
+                                                          ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def multislice_workspace_bytes(self, n_det):
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        _native.check(self._L.prism_multislice_workspace_bytes(self._h, int(n_det),
+                                                               ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def probe_workspace_bytes(self, f, alpha_max_mrad, optics):
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        o = _optics(optics)
+        _native.check(self._L.prism_probe_workspace_bytes(self._h, int(f), float(alpha_max_mrad),
+                                                          ctypes.byref(o), ctypes.byref(a),
+                                                          ctypes.byref(b)))
+        return a.value, b.value
+
+    def probe_group(self, f):
+        g, tx, ty = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _native.check(self._L.prism_probe_group(self._h, int(f), ctypes.byref(g), ctypes.byref(tx),
+                                                ctypes.byref(ty)))
+        return g.value, tx.value, ty.value
+
+    # ------------------------------------------------------------ kernel timing
+    def profile(self, enable=True):
+        """Bracket every kernel launch of this plan with HIP events on its stream."""
+        _native.check(self._L.prism_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_report(self):
+        """{kernel: dict(launches, total_ms, min_ms, max_ms)}; waits for the events, clears them."""
+        buf = ctypes.create_string_buffer(1 << 16)
+        _native.check(self._L.prism_profile_report(self._h, buf, len(buf)))
+        out = {}
+        for line in buf.value.decode().splitlines():
+            name, cnt, tot, mn, mx = line.split()
+            out[name] = dict(launches=int(cnt), total_ms=float(tot), min_ms=float(mn),
+                             max_ms=float(mx))
+        return out
+
+    # ------------------------------------------------------------ device calls
+    def set_potential_slices(self, phase):
+        """phase: float32 device tensor [H][n][n] (radians); borrowed, kept referenced."""
+        import torch
+        _check_dev(phase, torch.float32, self.n_slices * self.n * self.n, "phase")
+        _native.check(self._L.prism_set_potential_slices(self._h, _ptr(phase)))
+        self._phase = phase
+
+    def build_smatrix(self, f, alpha_max_mrad, smatrix, workspace, stream=None):
+        """smatrix: complex64 device tensor [B][n/2][n/2]; workspace: uint8 device tensor."""
+        import torch
+        B = self.beam_count(f, alpha_max_mrad)
+        _check_dev(smatrix, torch.complex64, B * (self.n // 2) ** 2, "smatrix")
+        _check_dev(workspace, torch.uint8, None, "workspace")
+        _native.check(self._L.prism_build_smatrix(self._h, int(f), float(alpha_max_mrad),
+                                                  _ptr(smatrix), _ptr(workspace),
+                                                  workspace.numel(), _stream_ptr(stream)))
+
+    def probe_outputs(self, f, alpha_max_mrad, smatrix, probe_xy, optics, edges_mrad, out,
+                      workspace, stream=None):
+        """probe_xy: float64 device [P][2] (A); out: float64 device [P][n_det]."""
+        import torch
+        det = _Det(edges_mrad)
+        P = probe_xy.shape[0]
+        _check_dev(probe_xy, torch.float64, 2 * P, "probe_xy")
+        _check_dev(out, torch.float64, P * det.edges.shape[0], "out")
+        _check_dev(smatrix, torch.complex64, None, "smatrix")
+        _check_dev(workspace, torch.uint8, None, "workspace")
+        o = _optics(optics)
+        _native.check(self._L.prism_probe_outputs(
+            self._h, int(f), float(alpha_max_mrad), _ptr(smatrix), _ptr(probe_xy), int(P),
+            ctypes.byref(o), ctypes.byref(det.struct), _ptr(out), _ptr(workspace),
+            workspace.numel(), _stream_ptr(stream)))
+
+    def multislice_outputs(self, probe_xy, optics, edges_mrad, out, workspace, stream=None):
+        import torch
+        det = _Det(edges_mrad)
+        P = probe_xy.shape[0]
+        _check_dev(probe_xy, torch.float64, 2 * P, "probe_xy")
+        _check_dev(out, torch.float64, P * det.edges.shape[0], "out")
+        _check_dev(workspace, torch.uint8, None, "workspace")
+        o = _optics(optics)
+        _native.check(self._L.prism_multislice_outputs(
+            self._h, _ptr(probe_xy), int(P), ctypes.byref(o), ctypes.byref(det.struct), _ptr(out),
+            _ptr(workspace), workspace.numel(), _stream_ptr(stream)))
+
+
+def tile_order(nx, ny, tx, ty):
+    """Permutation putting a raster scan (x fastest) into tx x ty probe tiles.
+
+    Probes of one tile share their PRISM windows; pass ``probes[perm]`` to
+    the probe step and undo with ``untile``. Edge tiles may be partial.
+    """
+    idx = []
+    for by in range(0, ny, ty):
+        for bx in range(0, nx, tx):
+            for j in range(by, min(by + ty, ny)):
+                for i in range(bx, min(bx + tx, nx)):
+                    idx.append(j * nx + i)
+    return np.asarray(idx, dtype=np.int64)
+
+
+def untile(values, perm):
+    """Inverse of ``values = original[perm]`` along the first axis."""
+    out = np.empty_like(values)
+    out[perm] = values
+    return out

@@ -1,0 +1,102 @@
+"""ctypes binding of libprism (include/prism.h): argument marshalling only.
+
+Loading fails loudly when the library has not been built; there is no
+Python or CPU fallback for any compute entry point.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libprism.so")
+
+PRISM_OK = 0
+PRISM_EINVAL = -1
+PRISM_ENOSPACE = -2
+PRISM_EHIP = -3
+PRISM_ENOTREADY = -4
+PRISM_MAX_DET = 32
+
+EXPORTS = (
+    "prism_plan_create", "prism_plan_destroy", "prism_wavelength", "prism_beam_count",
+    "prism_beams", "prism_smatrix_bytes", "prism_build_workspace_bytes",
+    "prism_multislice_workspace_bytes", "prism_probe_workspace_bytes", "prism_probe_group",
+    "prism_set_potential_slices", "prism_build_smatrix", "prism_probe_outputs",
+    "prism_multislice_outputs", "prism_profile_enable", "prism_profile_report",
+    "prism_last_error",
+)
+
+
+class PrismGeometry(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("cell_A", ctypes.c_double), ("energy_keV", ctypes.c_double),
+                ("n_slices", ctypes.c_int), ("slice_thickness_A", ctypes.POINTER(ctypes.c_double))]
+
+
+class PrismOptics(ctypes.Structure):
+    _fields_ = [("alpha_mrad", ctypes.c_double), ("C1_A", ctypes.c_double),
+                ("C3_A", ctypes.c_double)]
+
+
+class PrismDetector(ctypes.Structure):
+    _fields_ = [("n_det", ctypes.c_int), ("edges_mrad", ctypes.POINTER(ctypes.c_double))]
+
+
+class PrismError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libprism status {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libprism.so once; raises ImportError if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not built; run `python -m paper_1702_01904_amd.build`")
+    # torch ships its own HIP runtime with the same soname (libamdhip64.so.7).
+    # Importing torch first makes libprism bind to that already-loaded copy,
+    # so the process holds one HIP/HSA runtime and shares torch's device
+    # memory and streams.
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    D = ctypes.c_double
+    SZ = ctypes.POINTER(ctypes.c_size_t)
+    sig = {
+        "prism_plan_create": (I, [ctypes.POINTER(P), ctypes.POINTER(PrismGeometry)]),
+        "prism_plan_destroy": (None, [P]),
+        "prism_wavelength": (I, [P, ctypes.POINTER(D)]),
+        "prism_beam_count": (I, [P, I, D, ctypes.POINTER(I)]),
+        "prism_beams": (I, [P, I, D, ctypes.POINTER(ctypes.c_int32), I]),
+        "prism_smatrix_bytes": (I, [P, I, D, SZ]),
+        "prism_build_workspace_bytes": (I, [P, I, D, SZ, SZ]),
+        "prism_multislice_workspace_bytes": (I, [P, I, SZ, SZ]),
+        "prism_probe_workspace_bytes": (I, [P, I, D, ctypes.POINTER(PrismOptics), SZ, SZ]),
+        "prism_probe_group": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "prism_set_potential_slices": (I, [P, P]),
+        "prism_build_smatrix": (I, [P, I, D, P, P, ctypes.c_size_t, P]),
+        "prism_probe_outputs": (I, [P, I, D, P, P, I, ctypes.POINTER(PrismOptics),
+                                    ctypes.POINTER(PrismDetector), P, P, ctypes.c_size_t, P]),
+        "prism_multislice_outputs": (I, [P, P, I, ctypes.POINTER(PrismOptics),
+                                         ctypes.POINTER(PrismDetector), P, P, ctypes.c_size_t, P]),
+        "prism_profile_enable": (I, [P, I]),
+        "prism_profile_report": (I, [P, ctypes.c_char_p, ctypes.c_size_t]),
+        "prism_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def check(code):
+    if code != PRISM_OK:
+        msg = lib().prism_last_error().decode(errors="replace")
+        raise PrismError(code, msg)
+    return code

@@ -1,0 +1,211 @@
+// LDS-resident batched FFTs for gfx950 (64-wide wavefronts).
+//
+// The multislice step (Eq. 5) needs a forward and an inverse 2D FFT per
+// slice; the PRISM probe step (Fig. 1f) needs one small 2D FFT per probe.
+// Both are done here as batches of 1D transforms held in LDS:
+//   * Stockham auto-sort formulation, radix-8 stages followed by one
+//     radix-4 or radix-2 stage, so the output is in natural order with no
+//     bit-reversal pass;
+//   * each stage reads every butterfly input into registers, barriers,
+//     then writes the outputs in place (one barrier pair per stage);
+//   * twiddles come from a per-length table of exp(-2 pi i k / L), rounded
+//     once from FP64, staged in LDS by the caller;
+//   * LDS addresses are padded by one complex every 16 (lpad) to spread
+//     the strided writes of early stages over the banks.
+//
+// A batch is described by compile-time strides: element e of sequence s is
+// at flat index (s / SPB) * BSTR + (s % SPB) * SSTR + e * ESTR (before
+// padding). SEQ_FAST picks whether consecutive threads walk sequences
+// (strided sequences, e.g. columns) or elements (contiguous sequences).
+// Forward transforms use exp(-2 pi i ...), inverse ones exp(+2 pi i ...);
+// neither is normalised.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace prism {
+
+constexpr int kPadShift = 4;
+
+__host__ __device__ constexpr int lds_padded(int n) { return n + (n >> kPadShift); }
+__device__ __forceinline__ int lpad(int i) { return i + (i >> kPadShift); }
+
+__host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 mul_mi(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(float2 (&v)[2]) {
+  const float2 t = v[0];
+  v[0] = cadd(t, v[1]);
+  v[1] = csub(t, v[1]);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4v(float2& a0, float2& a1, float2& a2, float2& a3) {
+  const float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  const float2 t2 = cadd(a1, a3), t3 = mul_mi<INV>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2 (&v)[4]) {
+  dft4v<INV>(v[0], v[1], v[2], v[3]);
+}
+
+// 8-point DFT as two 4-point DFTs (even/odd inputs) and a twiddled merge.
+template <bool INV>
+__device__ __forceinline__ void dft8(float2 (&v)[8]) {
+  float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4v<INV>(e0, e1, e2, e3);
+  dft4v<INV>(o0, o1, o2, o3);
+  const float r = 0.70710678118654752440f;
+  // o1 *= w^1, o2 *= w^2, o3 *= w^3 with w = exp(-+ 2 pi i / 8)
+  if (INV) {
+    o1 = make_float2(r * (o1.x - o1.y), r * (o1.x + o1.y));
+    o3 = make_float2(-r * (o3.x + o3.y), r * (o3.x - o3.y));
+  } else {
+    o1 = make_float2(r * (o1.x + o1.y), r * (o1.y - o1.x));
+    o3 = make_float2(r * (o3.y - o3.x), -r * (o3.x + o3.y));
+  }
+  o2 = mul_mi<INV>(o2);
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1);
+  v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3);
+  v[7] = csub(e3, o3);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2 (&v)[R]) {
+  if constexpr (R == 2) dft2<INV>(v);
+  else if constexpr (R == 4) dft4<INV>(v);
+  else dft8<INV>(v);
+}
+
+// Batch geometry of LDS-held sequences (see header comment).
+template <int L_, int NSEQ_, int SPB_, int BSTR_, int SSTR_, int ESTR_, bool SEQ_FAST_>
+struct Batch {
+  static constexpr int L = L_;
+  static constexpr int NSEQ = NSEQ_;
+  static constexpr int SPB = SPB_;
+  static constexpr int BSTR = BSTR_;
+  static constexpr int SSTR = SSTR_;
+  static constexpr int ESTR = ESTR_;
+  static constexpr bool SEQ_FAST = SEQ_FAST_;
+  __device__ __forceinline__ static int addr(int s, int e) {
+    return (s / SPB) * BSTR + (s % SPB) * SSTR + e * ESTR;
+  }
+};
+
+// Contiguous sequences [NSEQ][L].
+template <int L, int NSEQ>
+using RowBatch = Batch<L, NSEQ, NSEQ, 0, L, 1, false>;
+
+// One Stockham stage of radix R with current span Ns (product of the
+// radices already applied). tw: LDS table of exp(-2 pi i k / L), k < L.
+template <class B, int R, int NT, bool INV>
+__device__ __forceinline__ void fft_stage(float2* lds, const float2* tw, int Ns, int tid) {
+  constexpr int L = B::L;
+  constexpr int NB = L / R;
+  constexpr int TOT = B::NSEQ * NB;
+  constexpr int PER = (TOT + NT - 1) / NT;
+  constexpr bool GUARD = (TOT % NT) != 0;
+  float2 v[PER][R];
+  int sidx[PER], jidx[PER];
+  const int tws = L / (Ns * R);
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int b = tid + p * NT;
+    int s, j;
+    if constexpr (B::SEQ_FAST) {
+      s = b % B::NSEQ;
+      j = b / B::NSEQ;
+    } else {
+      j = b % NB;
+      s = b / NB;
+    }
+    sidx[p] = s;
+    jidx[p] = j;
+    if (!GUARD || b < TOT) {
+      const int k = j & (Ns - 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        float2 x = lds[lpad(B::addr(s, j + r * NB))];
+        if (r > 0) {
+          const float2 w = tw[r * k * tws];
+          x = INV ? cmulc(x, w) : cmul(x, w);
+        }
+        v[p][r] = x;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int b = tid + p * NT;
+    if (!GUARD || b < TOT) {
+      dft<R, INV>(v[p]);
+      const int j = jidx[p], s = sidx[p];
+      const int k = j & (Ns - 1);
+      const int o = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[lpad(B::addr(s, o + r * Ns))] = v[p][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full length-L transform of every sequence in the batch. The caller must
+// have synchronised after writing the data and the twiddle table; on
+// return the result is in LDS and visible to all threads.
+template <class B, int NT, bool INV>
+__device__ __forceinline__ void fft_lds(float2* lds, const float2* tw, int tid) {
+  constexpr int K = ilog2(B::L);
+  static_assert((1 << K) == B::L, "power-of-two lengths only");
+  int Ns = 1;
+#pragma unroll
+  for (int st = 0; st < K / 3; ++st) {
+    fft_stage<B, 8, NT, INV>(lds, tw, Ns, tid);
+    Ns *= 8;
+  }
+  if constexpr (K % 3 == 1) fft_stage<B, 2, NT, INV>(lds, tw, Ns, tid);
+  if constexpr (K % 3 == 2) fft_stage<B, 4, NT, INV>(lds, tw, Ns, tid);
+}
+
+// Copy a twiddle table from global memory into LDS (no barrier).
+template <int L, int NT>
+__device__ __forceinline__ void load_twiddles(float2* tw_lds, const float2* __restrict__ tw, int tid) {
+  for (int i = tid; i < L; i += NT) tw_lds[i] = tw[i];
+}
+
+// Wavefront sum of a double (64 lanes).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace prism

@@ -1,0 +1,84 @@
+// Launch interface between the host plan (plan.cpp) and the HIP kernels.
+//
+// Wave state layout used by both the S-matrix build and multislice STEM:
+// after the x-transform of a slice step, a wave is held as
+//     X(y, kx) = sum_x psi(x, y) exp(-2 pi i kx x / n)
+// for the n/2 columns |kx| < n/4 that survive the half-band aperture
+// (compact column jj in [0, n/2) holds kx = jj for jj < n/4, else jj - n/2,
+// i.e. n/2-point fftfreq order). Layout: c64 [wave][y][n/2]. Columns with
+// |kx| >= n/4 are identically zero after every propagator step, so they are
+// never stored; this halves the HBM traffic of each pass.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace prism {
+
+constexpr int kMaxDet = 32;
+
+// Detector bins as half-open integer ranges of full-grid |k|^2:
+// bin j holds lo[j] <= kx^2 + ky^2 < hi[j]. Decided on the host in FP64
+// from theta = (lambda dq) sqrt(k^2) so that the kernels only compare ints.
+struct DetBins {
+  int n;
+  int lo[kMaxDet];
+  int hi[kMaxDet];
+};
+
+// Per-probe optics for the GPU-side FP64 phase computations.
+struct ProbeOptics {
+  double lam;      // wavelength (A)
+  double dq;       // 1 / cell (1/A)
+  double C1, C3;   // aberrations (A)
+  double cell;     // cell side (A)
+  int k2_aperture; // largest full-grid |k|^2 inside the aperture
+  double norm;     // incident-wave normalisation factor
+};
+
+hipError_t launch_twiddles(float2* tw, int L, hipStream_t st);
+hipError_t launch_transmission(const float* phase, float2* trans, size_t count, float scale,
+                               hipStream_t st);
+// lut[p][i] = exp(-i pi lambda t_p (k dq)^2) for full-grid index i (k in fftfreq order).
+hipError_t launch_prop_lut(float2* lut, int n, int H, const double* thick_dev, double lam,
+                           double dq, hipStream_t st);
+
+hipError_t launch_beam_init(float2* state, const int32_t* beams_mn, int b0, int nb, int n, int f,
+                            const float2* twN, hipStream_t st);
+hipError_t launch_probe_init(float2* state, const double* probe_xy, int p0, int np, int n,
+                             const ProbeOptics& po, const float2* twN, hipStream_t st);
+hipError_t launch_row_pass(float2* state, int nwaves, int n, const float2* trans_p,
+                           const float2* twN, hipStream_t st);
+hipError_t launch_col_pass(float2* state, int nwaves, int n, const float2* prop_p,
+                           const float2* twN, hipStream_t st);
+// Last slice of multislice STEM: FFT_y, propagator, band limit, |Psi|^2/n^2
+// and per-column-tile detector partial sums (double [wave][tiles][n_det]).
+hipError_t launch_col_detect(const float2* state, int nwaves, int n, const float2* prop_p,
+                             const float2* twN, const DetBins& bins, double* partial,
+                             hipStream_t st);
+int col_tiles(int n);
+hipError_t launch_reduce_partials(const double* partial, int nwaves, int tiles, int n_det,
+                                  double* out, hipStream_t st);
+hipError_t launch_extract(const float2* state, int nwaves, int n, float2* smatrix,
+                          const float2* twH, hipStream_t st);
+
+// PRISM probe step.
+struct ActiveBeam {
+  int plane;  // index of the beam's plane in the S-matrix
+  int m, n;   // plane-wave indices
+};
+
+hipError_t launch_alpha(const double* probe_xy, int p0, int np, const ActiveBeam* act, int n_act,
+                        int f, int ns, int w, const ProbeOptics& po, float2* alpha,
+                        int2* origin, hipStream_t st);
+// Union-window complex contraction on MFMA: window[p][v][u] =
+// sum_a alpha[p][a] * S[act[a].plane][(oy_p + v) % ns][(ox_p + u) % ns].
+hipError_t launch_contract(const float2* smatrix, const ActiveBeam* act, int n_act,
+                           const float2* alpha, const int2* origin, int np, int ns, int w,
+                           int group, float2* window, hipStream_t st);
+int contract_group(int w);
+hipError_t launch_window_detect(const float2* window, int np, int w, int f, const float2* twW,
+                                const DetBins& bins, double* out, hipStream_t st);
+
+}  // namespace prism

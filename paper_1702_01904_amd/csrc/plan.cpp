@@ -1,0 +1,610 @@
+// Host side of libprism: plans, argument checks, workspace layout, chunked
+// launch sequences and the C ABI declared in include/prism.h.
+//
+// The plan holds only host state (grid, optics-independent constants,
+// cached beam sets). Every device buffer comes from the caller; each call
+// carves its workspace with a bump allocator that runs the same code for
+// the size queries and for the real calls.
+#include "prism.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(PRISM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+constexpr double kHcKeVA = 12.398419843320026;  // h c (keV A), CODATA 2018
+constexpr double kMec2KeV = 510.99895000;       // electron rest energy (keV)
+constexpr long long kK2Cap = 1LL << 30;
+
+uint64_t dbits(double x) {
+  uint64_t u;
+  std::memcpy(&u, &x, sizeof u);
+  return u;
+}
+
+bool is_pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Bump allocator over a caller workspace (base == nullptr: size query).
+struct Carve {
+  char* base;
+  size_t used = 0;
+  explicit Carve(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    used = (used + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+    used += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct ProfRecord {
+  const char* name;
+  hipEvent_t start, stop;
+};
+
+struct prism_plan {
+  // per-kernel timing (prism_profile_enable / prism_profile_report)
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<ProfRecord> prof;
+  hipEvent_t event() {
+    hipEvent_t e = nullptr;
+    if (!ev_pool.empty()) {
+      e = ev_pool.back();
+      ev_pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+  ~prism_plan() {
+    for (auto& r : prof) {
+      if (r.start) (void)hipEventDestroy(r.start);
+      if (r.stop) (void)hipEventDestroy(r.stop);
+    }
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
+  }
+
+  int n = 0;
+  double cell = 0, energy = 0, lam = 0, dq = 0;
+  int H = 0;
+  std::vector<double> thick;
+  const float* phase = nullptr;
+  std::map<std::pair<int, uint64_t>, std::vector<int32_t>> beams;  // (f, alpha_max) -> [B][2]
+  std::map<std::tuple<int, uint64_t, uint64_t>, std::vector<prism::ActiveBeam>> active;
+
+  // scattering angle (rad) of integer full-grid |k|^2
+  double theta(long long k2) const { return (lam * dq) * std::sqrt((double)k2); }
+
+  // smallest k2 >= 0 with theta(k2) >= ang
+  long long first_ge(double ang) const {
+    if (!(ang > 0.0)) return 0;
+    const double x = ang / (lam * dq);
+    if (x * x > (double)kK2Cap) return kK2Cap;
+    long long k = std::max(0LL, (long long)std::floor(x * x) - 4);
+    while (k > 0 && theta(k - 1) >= ang) --k;
+    while (theta(k) < ang) ++k;
+    return k;
+  }
+  // largest k2 with theta(k2) <= ang (-1 if none)
+  long long last_le(double ang) const {
+    if (ang < 0.0) return -1;
+    const double x = ang / (lam * dq);
+    if (x * x > (double)kK2Cap) return kK2Cap;
+    long long k = (long long)std::floor(x * x) + 4;
+    while (theta(k) > ang) --k;
+    while (theta(k + 1) <= ang) ++k;
+    return k;
+  }
+};
+
+namespace {
+
+int check_f(const prism_plan* p, int f) {
+  if (f < 1) return fail(PRISM_EINVAL, "interpolation factor f must be >= 1");
+  if (p->n % (2 * f) != 0) return fail(PRISM_EINVAL, "n must be divisible by 2 f");
+  return PRISM_OK;
+}
+
+const std::vector<int32_t>* get_beams(prism_plan* p, int f, double amax_mrad) {
+  const auto key = std::make_pair(f, dbits(amax_mrad));
+  auto it = p->beams.find(key);
+  if (it != p->beams.end()) return &it->second;
+  const double amax = amax_mrad * 1e-3;
+  const int lim = p->n / (4 * f) + 1;
+  std::vector<int32_t> mn;
+  for (int m = -lim; m <= lim; ++m)
+    for (int k = -lim; k <= lim; ++k) {
+      const long long k2 = (long long)(m * f) * (m * f) + (long long)(k * f) * (k * f);
+      if (16 * k2 >= (long long)p->n * p->n) continue;
+      if (p->theta(k2) <= amax) {
+        mn.push_back(m);
+        mn.push_back(k);
+      }
+    }
+  return &(p->beams[key] = std::move(mn));
+}
+
+int beams_checked(const prism_plan* cp, int f, double amax_mrad, const std::vector<int32_t>** out) {
+  prism_plan* p = const_cast<prism_plan*>(cp);
+  if (!p) return fail(PRISM_EINVAL, "null plan");
+  if (int r = check_f(p, f)) return r;
+  if (!(amax_mrad > 0.0) || !std::isfinite(amax_mrad))
+    return fail(PRISM_EINVAL, "alpha_max_mrad must be positive and finite");
+  *out = get_beams(p, f, amax_mrad);
+  if ((*out)->empty()) return fail(PRISM_EINVAL, "empty beam set");
+  return PRISM_OK;
+}
+
+int check_optics(const prism_plan* p, const prism_optics* o) {
+  if (!o) return fail(PRISM_EINVAL, "null optics");
+  if (!(o->alpha_mrad > 0.0) || !std::isfinite(o->alpha_mrad) || !std::isfinite(o->C1_A) ||
+      !std::isfinite(o->C3_A))
+    return fail(PRISM_EINVAL, "optics: alpha must be positive, C1/C3 finite");
+  const long long k2ap = p->last_le(o->alpha_mrad * 1e-3);
+  if (16 * k2ap >= (long long)p->n * p->n)
+    return fail(PRISM_EINVAL, "probe aperture must lie inside the half-band anti-aliasing limit");
+  return PRISM_OK;
+}
+
+int make_bins(const prism_plan* p, const prism_detector* d, prism::DetBins* b) {
+  if (!d || !d->edges_mrad) return fail(PRISM_EINVAL, "null detector");
+  if (d->n_det < 1 || d->n_det > PRISM_MAX_DET)
+    return fail(PRISM_EINVAL, "n_det must be in [1, PRISM_MAX_DET]");
+  std::memset(b, 0, sizeof *b);
+  b->n = d->n_det;
+  for (int j = 0; j < d->n_det; ++j) {
+    const double lo = d->edges_mrad[2 * j], hi = d->edges_mrad[2 * j + 1];
+    if (!std::isfinite(lo) || !std::isfinite(hi) || lo < 0.0 || hi < lo)
+      return fail(PRISM_EINVAL, "detector edges must satisfy 0 <= inner <= outer");
+    b->lo[j] = (int)p->first_ge(lo * 1e-3);
+    b->hi[j] = (int)p->first_ge(hi * 1e-3);
+  }
+  return PRISM_OK;
+}
+
+prism::ProbeOptics probe_optics(const prism_plan* p, const prism_optics* o) {
+  prism::ProbeOptics po{};
+  po.lam = p->lam;
+  po.dq = p->dq;
+  po.C1 = o->C1_A;
+  po.C3 = o->C3_A;
+  po.cell = p->cell;
+  po.k2_aperture = (int)p->last_le(o->alpha_mrad * 1e-3);
+  po.norm = 1.0;
+  return po;
+}
+
+long long aperture_pixels(const prism_plan* p, long long k2ap) {
+  const int n = p->n;
+  long long cnt = 0;
+  for (int ky = -n / 2; ky < n / 2; ++ky)
+    for (int kx = -n / 2; kx < n / 2; ++kx)
+      if ((long long)kx * kx + (long long)ky * ky <= k2ap) ++cnt;
+  return cnt;
+}
+
+const std::vector<prism::ActiveBeam>* get_active(prism_plan* p, int f, double amax_mrad,
+                                                 const std::vector<int32_t>& mn, double alpha_mrad) {
+  const auto key = std::make_tuple(f, dbits(amax_mrad), dbits(alpha_mrad));
+  auto it = p->active.find(key);
+  if (it != p->active.end()) return &it->second;
+  std::vector<prism::ActiveBeam> act;
+  const double a = alpha_mrad * 1e-3;
+  for (size_t b = 0; b < mn.size() / 2; ++b) {
+    const long long k2 = (long long)(mn[2 * b] * f) * (mn[2 * b] * f) +
+                         (long long)(mn[2 * b + 1] * f) * (mn[2 * b + 1] * f);
+    if (p->theta(k2) <= a) act.push_back(prism::ActiveBeam{(int)b, mn[2 * b], mn[2 * b + 1]});
+  }
+  return &(p->active[key] = std::move(act));
+}
+
+// ---------------------------------------------------------------- layouts
+
+constexpr size_t kChunkBytes = size_t(1) << 28;  // preferred wave-state size per chunk
+
+size_t state_bytes(int n) { return (size_t)n * (n / 2) * sizeof(float2); }
+
+int pref_wave_chunk(int n, int count) {
+  const int c = (int)std::max<size_t>(1, kChunkBytes / state_bytes(n));
+  return std::max(1, std::min(c, count));
+}
+
+struct SliceWs {
+  float2* twN;
+  float2* twH;
+  double* thick;
+  float2* prop;
+  float2* trans;
+  int32_t* mn;
+  float2* state;
+  double* partial;
+};
+
+size_t slice_layout(const prism_plan* p, int chunk, int n_beams, int n_det, SliceWs* w, void* base) {
+  Carve c(base);
+  const int n = p->n;
+  w->twN = c.take<float2>(n);
+  w->twH = c.take<float2>(n / 2);
+  w->thick = c.take<double>(p->H);
+  w->prop = c.take<float2>((size_t)p->H * n);
+  w->trans = c.take<float2>((size_t)p->H * n * n);
+  w->mn = c.take<int32_t>(2 * (size_t)std::max(n_beams, 0));
+  w->state = c.take<float2>((size_t)chunk * n * (n / 2));
+  w->partial = c.take<double>((size_t)chunk * prism::col_tiles(n) * std::max(n_det, 0));
+  return c.used + 256;
+}
+
+int choose_chunk(const prism_plan* p, int want, int n_beams, int n_det, size_t ws_bytes) {
+  SliceWs w;
+  for (int c = want; c >= 1; c = (c > 8 ? c * 3 / 4 : c - 1))
+    if (slice_layout(p, c, n_beams, n_det, &w, nullptr) <= ws_bytes) return c;
+  return 0;
+}
+
+struct ProbeWs {
+  float2* twW;
+  prism::ActiveBeam* act;
+  float2* alpha;
+  int2* origin;
+  float2* window;
+};
+
+size_t probe_layout(int w, int n_act, int chunk, ProbeWs* pw, void* base) {
+  Carve c(base);
+  pw->twW = c.take<float2>(w);
+  pw->act = c.take<prism::ActiveBeam>(n_act);
+  pw->alpha = c.take<float2>((size_t)chunk * n_act);
+  pw->origin = c.take<int2>(chunk);
+  pw->window = c.take<float2>((size_t)chunk * w * w);
+  return c.used + 256;
+}
+
+int pref_probe_chunk(int w, int group) {
+  const size_t per = (size_t)w * w * sizeof(float2);
+  int c = (int)std::min<size_t>(16384, std::max<size_t>(group, kChunkBytes / per));
+  return std::max(group, c / group * group);
+}
+
+void* aligned_base(void* ws) {
+  const uintptr_t u = reinterpret_cast<uintptr_t>(ws);
+  return reinterpret_cast<void*>((u + 255) & ~uintptr_t(255));
+}
+
+#define HIP_TRY(expr, where)                       \
+  do {                                             \
+    hipError_t _e = (expr);                        \
+    if (_e != hipSuccess) return hip_fail(_e, where); \
+  } while (0)
+
+// Kernel launch bracketed by HIP events on its stream when profiling is on.
+#define LAUNCH(plan, st, name, expr)                                      \
+  do {                                                                  \
+    hipEvent_t _a = nullptr, _b = nullptr;                              \
+    if ((plan)->prof_on) {                                              \
+      _a = (plan)->event();                                             \
+      _b = (plan)->event();                                             \
+      if (_a) (void)hipEventRecord(_a, st);                                   \
+    }                                                                   \
+    hipError_t _e = (expr);                                             \
+    if (_e != hipSuccess) return hip_fail(_e, name);                    \
+    if ((plan)->prof_on && _a && _b) {                                  \
+      (void)hipEventRecord(_b, st);                                     \
+      (plan)->prof.push_back(ProfRecord{name, _a, _b});                 \
+    }                                                                   \
+  } while (0)
+
+// Fill twiddles, propagator table and transmission functions of every slice.
+int prepare_slices(prism_plan* p, const SliceWs& w, hipStream_t st) {
+  const int n = p->n;
+  HIP_TRY(hipMemcpyAsync(w.thick, p->thick.data(), p->H * sizeof(double), hipMemcpyHostToDevice, st),
+          "copy slice thickness");
+  LAUNCH(p, st, "twiddles", prism::launch_twiddles(w.twN, n, st));
+  LAUNCH(p, st, "twiddles", prism::launch_twiddles(w.twH, n / 2, st));
+  LAUNCH(p, st, "prop_lut", prism::launch_prop_lut(w.prop, n, p->H, w.thick, p->lam, p->dq, st));
+  LAUNCH(p, st, "transmission", prism::launch_transmission(p->phase, w.trans, (size_t)p->H * n * n, 1.0f / (float)n, st));
+  return PRISM_OK;
+}
+
+}  // namespace
+
+// =========================================================================
+// C ABI
+// =========================================================================
+
+extern "C" {
+
+const char* prism_last_error(void) { return g_err.c_str(); }
+
+int prism_plan_create(prism_plan** out, const prism_geometry* g) {
+  if (!out || !g) return fail(PRISM_EINVAL, "null argument");
+  *out = nullptr;
+  if (!is_pow2(g->n) || g->n < 128 || g->n > 2048)
+    return fail(PRISM_EINVAL, "n must be a power of two in [128, 2048]");
+  if (!(g->cell_A > 0.0) || !std::isfinite(g->cell_A)) return fail(PRISM_EINVAL, "cell must be > 0");
+  if (!(g->energy_keV > 0.0) || !std::isfinite(g->energy_keV))
+    return fail(PRISM_EINVAL, "energy must be > 0");
+  if (g->n_slices < 1 || !g->slice_thickness_A) return fail(PRISM_EINVAL, "need >= 1 slice");
+  for (int i = 0; i < g->n_slices; ++i)
+    if (!(g->slice_thickness_A[i] > 0.0) || !std::isfinite(g->slice_thickness_A[i]))
+      return fail(PRISM_EINVAL, "slice thickness must be > 0");
+  auto* p = new prism_plan();
+  p->n = g->n;
+  p->cell = g->cell_A;
+  p->energy = g->energy_keV;
+  p->lam = kHcKeVA / std::sqrt(g->energy_keV * (g->energy_keV + 2.0 * kMec2KeV));
+  p->dq = 1.0 / g->cell_A;
+  p->H = g->n_slices;
+  p->thick.assign(g->slice_thickness_A, g->slice_thickness_A + g->n_slices);
+  *out = p;
+  return PRISM_OK;
+}
+
+void prism_plan_destroy(prism_plan* plan) { delete plan; }
+
+int prism_wavelength(const prism_plan* p, double* lam) {
+  if (!p || !lam) return fail(PRISM_EINVAL, "null argument");
+  *lam = p->lam;
+  return PRISM_OK;
+}
+
+int prism_beam_count(const prism_plan* p, int f, double amax_mrad, int* n_beams) {
+  if (!n_beams) return fail(PRISM_EINVAL, "null argument");
+  const std::vector<int32_t>* mn;
+  if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
+  *n_beams = (int)(mn->size() / 2);
+  return PRISM_OK;
+}
+
+int prism_beams(const prism_plan* p, int f, double amax_mrad, int32_t* out, int capacity) {
+  if (!out || capacity < 0) return fail(PRISM_EINVAL, "null argument");
+  const std::vector<int32_t>* mn;
+  if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
+  const size_t cnt = std::min(mn->size() / 2, (size_t)capacity);
+  std::memcpy(out, mn->data(), cnt * 2 * sizeof(int32_t));
+  return PRISM_OK;
+}
+
+int prism_smatrix_bytes(const prism_plan* p, int f, double amax_mrad, size_t* bytes) {
+  if (!bytes) return fail(PRISM_EINVAL, "null argument");
+  const std::vector<int32_t>* mn;
+  if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
+  *bytes = (mn->size() / 2) * (size_t)(p->n / 2) * (p->n / 2) * sizeof(float2);
+  return PRISM_OK;
+}
+
+int prism_build_workspace_bytes(const prism_plan* p, int f, double amax_mrad, size_t* pref,
+                                size_t* minimum) {
+  if (!pref || !minimum) return fail(PRISM_EINVAL, "null argument");
+  const std::vector<int32_t>* mn;
+  if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
+  const int B = (int)(mn->size() / 2);
+  SliceWs w;
+  *pref = slice_layout(p, pref_wave_chunk(p->n, B), B, 0, &w, nullptr);
+  *minimum = slice_layout(p, 1, B, 0, &w, nullptr);
+  return PRISM_OK;
+}
+
+int prism_multislice_workspace_bytes(const prism_plan* p, int n_det, size_t* pref,
+                                     size_t* minimum) {
+  if (!p || !pref || !minimum) return fail(PRISM_EINVAL, "null argument");
+  if (n_det < 1 || n_det > PRISM_MAX_DET) return fail(PRISM_EINVAL, "n_det out of range");
+  SliceWs w;
+  *pref = slice_layout(p, pref_wave_chunk(p->n, 1 << 20), 0, n_det, &w, nullptr);
+  *minimum = slice_layout(p, 1, 0, n_det, &w, nullptr);
+  return PRISM_OK;
+}
+
+int prism_probe_group(const prism_plan* p, int f, int* group, int* tx, int* ty) {
+  if (!p || !group || !tx || !ty) return fail(PRISM_EINVAL, "null argument");
+  if (int r = check_f(p, f)) return r;
+  const int w = p->n / (2 * f);
+  *group = prism::contract_group(w);
+  *tx = 8;
+  *ty = *group / 8;
+  if (*group == 16) *tx = *ty = 4;
+  return PRISM_OK;
+}
+
+int prism_probe_workspace_bytes(const prism_plan* cp, int f, double amax_mrad,
+                                const prism_optics* o, size_t* pref, size_t* minimum) {
+  if (!pref || !minimum) return fail(PRISM_EINVAL, "null argument");
+  prism_plan* p = const_cast<prism_plan*>(cp);
+  const std::vector<int32_t>* mn;
+  if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
+  if (int r = check_optics(p, o)) return r;
+  const int w = p->n / (2 * f);
+  if (!is_pow2(w) || w < 8 || w > 128) return fail(PRISM_EINVAL, "window side n/(2f) must be 8..128");
+  const auto* act = get_active(p, f, amax_mrad, *mn, o->alpha_mrad);
+  const int G = prism::contract_group(w);
+  ProbeWs pw;
+  *pref = probe_layout(w, (int)act->size(), pref_probe_chunk(w, G), &pw, nullptr);
+  *minimum = probe_layout(w, (int)act->size(), G, &pw, nullptr);
+  return PRISM_OK;
+}
+
+int prism_profile_enable(prism_plan* p, int enable) {
+  if (!p) return fail(PRISM_EINVAL, "null plan");
+  p->prof_on = enable != 0;
+  return PRISM_OK;
+}
+
+int prism_profile_report(prism_plan* p, char* buf, size_t len) {
+  if (!p || !buf || len == 0) return fail(PRISM_EINVAL, "null argument");
+  struct Acc {
+    int count = 0;
+    double total = 0, mn = 1e300, mx = 0;
+  };
+  std::map<std::string, Acc> acc;
+  int status = PRISM_OK;
+  for (auto& r : p->prof) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(r.stop);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.stop);
+    if (e != hipSuccess && status == PRISM_OK) status = hip_fail(e, "profile events");
+    Acc& a = acc[r.name];
+    a.count++;
+    a.total += ms;
+    a.mn = std::min(a.mn, (double)ms);
+    a.mx = std::max(a.mx, (double)ms);
+    p->ev_pool.push_back(r.start);
+    p->ev_pool.push_back(r.stop);
+  }
+  p->prof.clear();
+  std::string text;
+  char line[256];
+  for (auto& kv : acc) {
+    std::snprintf(line, sizeof line, "%s %d %.6f %.6f %.6f\n", kv.first.c_str(), kv.second.count,
+                  kv.second.total, kv.second.mn, kv.second.mx);
+    text += line;
+  }
+  if (text.size() + 1 > len) return fail(PRISM_ENOSPACE, "profile report buffer too small");
+  std::memcpy(buf, text.c_str(), text.size() + 1);
+  return status;
+}
+
+int prism_set_potential_slices(prism_plan* p, const float* phase_dev) {
+  if (!p || !phase_dev) return fail(PRISM_EINVAL, "null argument");
+  p->phase = phase_dev;
+  return PRISM_OK;
+}
+
+int prism_build_smatrix(prism_plan* p, int f, double amax_mrad, void* S, void* ws, size_t ws_bytes,
+                        void* stream) {
+  const std::vector<int32_t>* mn;
+  if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
+  if (!S || !ws) return fail(PRISM_EINVAL, "null device buffer");
+  if (!p->phase) return fail(PRISM_ENOTREADY, "potential slices not set");
+  const int n = p->n, B = (int)(mn->size() / 2);
+  void* base = aligned_base(ws);
+  const int chunk = choose_chunk(p, pref_wave_chunk(n, B), B, 0, ws_bytes);
+  if (chunk < 1) return fail(PRISM_ENOSPACE, "workspace smaller than the build minimum");
+  SliceWs w;
+  slice_layout(p, chunk, B, 0, &w, base);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int r = prepare_slices(p, w, st)) return r;
+  HIP_TRY(hipMemcpyAsync(w.mn, mn->data(), mn->size() * sizeof(int32_t), hipMemcpyHostToDevice, st),
+          "copy beam list");
+  float2* Sout = static_cast<float2*>(S);
+  const size_t splane = (size_t)(n / 2) * (n / 2);
+  for (int b0 = 0; b0 < B; b0 += chunk) {
+    const int nb = std::min(chunk, B - b0);
+    LAUNCH(p, st, "beam_init", prism::launch_beam_init(w.state, w.mn, b0, nb, n, f, w.twN, st));
+    for (int s = 0; s < p->H; ++s) {
+      LAUNCH(p, st, "row_pass", prism::launch_row_pass(w.state, nb, n, w.trans + (size_t)s * n * n, w.twN, st));
+      LAUNCH(p, st, "col_pass", prism::launch_col_pass(w.state, nb, n, w.prop + (size_t)s * n, w.twN, st));
+    }
+    LAUNCH(p, st, "extract", prism::launch_extract(w.state, nb, n, Sout + (size_t)b0 * splane, w.twH, st));
+  }
+  return PRISM_OK;
+}
+
+int prism_multislice_outputs(prism_plan* p, const double* xy, int P, const prism_optics* o,
+                             const prism_detector* d, double* out, void* ws, size_t ws_bytes,
+                             void* stream) {
+  if (!p) return fail(PRISM_EINVAL, "null plan");
+  if (P < 0) return fail(PRISM_EINVAL, "negative probe count");
+  if (int r = check_optics(p, o)) return r;
+  prism::DetBins bins;
+  if (int r = make_bins(p, d, &bins)) return r;
+  if (P == 0) return PRISM_OK;
+  if (!xy || !out || !ws) return fail(PRISM_EINVAL, "null device buffer");
+  if (!p->phase) return fail(PRISM_ENOTREADY, "potential slices not set");
+  const int n = p->n;
+  void* base = aligned_base(ws);
+  const int chunk = choose_chunk(p, pref_wave_chunk(n, P), 0, bins.n, ws_bytes);
+  if (chunk < 1) return fail(PRISM_ENOSPACE, "workspace smaller than the multislice minimum");
+  SliceWs w;
+  slice_layout(p, chunk, 0, bins.n, &w, base);
+  prism::ProbeOptics po = probe_optics(p, o);
+  po.norm = 1.0 / std::sqrt((double)aperture_pixels(p, po.k2_aperture));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int r = prepare_slices(p, w, st)) return r;
+  const int tiles = prism::col_tiles(n);
+  for (int p0 = 0; p0 < P; p0 += chunk) {
+    const int np = std::min(chunk, P - p0);
+    LAUNCH(p, st, "probe_init", prism::launch_probe_init(w.state, xy, p0, np, n, po, w.twN, st));
+    for (int s = 0; s < p->H; ++s) {
+      LAUNCH(p, st, "row_pass", prism::launch_row_pass(w.state, np, n, w.trans + (size_t)s * n * n, w.twN, st));
+      if (s + 1 < p->H) {
+        LAUNCH(p, st, "col_pass", prism::launch_col_pass(w.state, np, n, w.prop + (size_t)s * n, w.twN, st));
+      } else {
+        LAUNCH(p, st, "col_detect", prism::launch_col_detect(w.state, np, n, w.prop + (size_t)s * n, w.twN, bins,
+                                         w.partial, st));
+      }
+    }
+    LAUNCH(p, st, "reduce_partials", prism::launch_reduce_partials(w.partial, np, tiles, bins.n, out + (size_t)p0 * bins.n,
+                                          st));
+  }
+  return PRISM_OK;
+}
+
+int prism_probe_outputs(prism_plan* p, int f, double amax_mrad, const void* S, const double* xy,
+                        int P, const prism_optics* o, const prism_detector* d, double* out,
+                        void* ws, size_t ws_bytes, void* stream) {
+  const std::vector<int32_t>* mn;
+  if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
+  if (P < 0) return fail(PRISM_EINVAL, "negative probe count");
+  if (int r = check_optics(p, o)) return r;
+  prism::DetBins bins;
+  if (int r = make_bins(p, d, &bins)) return r;
+  const int n = p->n, ns = n / 2, w = n / (2 * f);
+  if (!is_pow2(w) || w < 8 || w > 128) return fail(PRISM_EINVAL, "window side n/(2f) must be 8..128");
+  const auto* act = get_active(p, f, amax_mrad, *mn, o->alpha_mrad);
+  const int n_act = (int)act->size();
+  if (n_act < 1) return fail(PRISM_EINVAL, "no beam of the set lies inside the probe aperture");
+  if (P == 0) return PRISM_OK;
+  if (!S || !xy || !out || !ws) return fail(PRISM_EINVAL, "null device buffer");
+  const int G = prism::contract_group(w);
+  void* base = aligned_base(ws);
+  const size_t avail = ws_bytes;  // layouts include 256 B of alignment slack
+  ProbeWs pw;
+  int chunk = std::min(pref_probe_chunk(w, G), (P + G - 1) / G * G);
+  while (chunk >= G && probe_layout(w, n_act, chunk, &pw, nullptr) > avail)
+    chunk = chunk > 8 * G ? (chunk * 3 / 4) / G * G : chunk - G;
+  if (chunk < G) return fail(PRISM_ENOSPACE, "workspace smaller than the probe-step minimum");
+  probe_layout(w, n_act, chunk, &pw, base);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  LAUNCH(p, st, "twiddles", prism::launch_twiddles(pw.twW, w, st));
+  HIP_TRY(hipMemcpyAsync(pw.act, act->data(), act->size() * sizeof(prism::ActiveBeam),
+                         hipMemcpyHostToDevice, st),
+          "copy active beams");
+  prism::ProbeOptics po = probe_optics(p, o);
+  po.norm = 1.0 / ((double)w * std::sqrt((double)n_act));
+  const float2* Sd = static_cast<const float2*>(S);
+  for (int p0 = 0; p0 < P; p0 += chunk) {
+    const int np = std::min(chunk, P - p0);
+    LAUNCH(p, st, "alpha", prism::launch_alpha(xy, p0, np, pw.act, n_act, f, ns, w, po, pw.alpha, pw.origin, st));
+    LAUNCH(p, st, "contract", prism::launch_contract(Sd, pw.act, n_act, pw.alpha, pw.origin, np, ns, w, G, pw.window,
+                                   st));
+    LAUNCH(p, st, "window_detect", prism::launch_window_detect(pw.window, np, w, f, pw.twW, bins,
+                                        out + (size_t)p0 * bins.n, st));
+  }
+  return PRISM_OK;
+}
+
+}  // extern "C"

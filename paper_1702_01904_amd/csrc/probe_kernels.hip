@@ -1,0 +1,337 @@
+// PRISM probe step (Fig. 1d-f): coefficients, window sum, FFT, detectors.
+//
+//   alpha_{m,n}(r0) = A(q) e^{-i chi(q)} e^{-2 pi i q.r0} / (W sqrt(B_A))
+//   psi(r, r0)      = sum_{m,n} S_{m,n}(r) alpha_{m,n}(r0)      (Eq. PRISMfinal)
+// inside the W x W window of Eq. RegionBounds, then |FFT_W psi|^2 / W^2
+// integrated per detector bin.
+//
+// The window sum is a complex GEMM when neighbouring probes share their
+// windows: for a group of G probes the union of their windows U is one
+// M = 2G (real/imag rows) x N = |U| pixels x K = 2 B_A product with
+//   A'[2g  ][2b] =  Re a_gb, A'[2g  ][2b+1] = -Im a_gb,
+//   A'[2g+1][2b] =  Im a_gb, A'[2g+1][2b+1] =  Re a_gb,
+//   B'[2b][x] = Re S_b(x),   B'[2b+1][x]   = Im S_b(x),
+// run on v_mfma_f32_16x16x4f32 with FP32 accumulation. Each output pixel
+// of the union is kept for the probes whose own window contains it.
+#include "fft_lds.hpp"
+#include "kernels.hpp"
+
+namespace prism {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int wrap_mod(long long v, int m) {
+  long long r = v % m;
+  return (int)(r < 0 ? r + m : r);
+}
+
+// One thread per (probe, active beam); also writes each probe's window
+// origin (first S pixel of the cut-out, periodic).
+__global__ void k_alpha(const double* __restrict__ probe_xy, int p0, int np,
+                        const ActiveBeam* __restrict__ act, int n_act, int f, int ns, int w,
+                        ProbeOptics po, float2* __restrict__ alpha, int2* __restrict__ origin) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)np * n_act) return;
+  const int p = (int)(i / n_act), a = (int)(i % n_act);
+  const double x0 = probe_xy[2 * (size_t)(p0 + p)], y0 = probe_xy[2 * (size_t)(p0 + p) + 1];
+  if (a == 0) {
+    const double dxs = po.cell / (double)ns;
+    const int cx = wrap_mod((long long)floor(x0 / dxs + 0.5), ns);
+    const int cy = wrap_mod((long long)floor(y0 / dxs + 0.5), ns);
+    origin[p] = make_int2(wrap_mod((long long)cx - w / 2, ns), wrap_mod((long long)cy - w / 2, ns));
+  }
+  const double kx = (double)act[a].m * f, ky = (double)act[a].n * f;
+  const double q2 = (kx * kx + ky * ky) * (po.dq * po.dq);
+  double t = -(0.5 * po.lam * q2 * po.C1 + 0.25 * po.lam * po.lam * po.lam * q2 * q2 * po.C3) -
+             (kx * x0 + ky * y0) * po.dq;
+  t -= floor(t);
+  double s, c;
+  sincospi(2.0 * t, &s, &c);
+  alpha[i] = make_float2((float)(c * po.norm), (float)(s * po.norm));
+}
+
+constexpr int kCNT = 256;    // threads per contraction workgroup (4 waves)
+constexpr int kCTile = 128;  // union pixels per workgroup (32 per wave)
+constexpr int kCKB = 16;     // beams per K block
+
+struct UnionGeom {
+  int y0, x0;  // first S pixel of the union (periodic)
+  int uy, ux;  // union extent
+};
+
+// Contract one 128-pixel tile of the union for all G probes of the group.
+// only < 0: write every probe whose window holds a pixel; only >= 0: write
+// that probe alone (scattered groups).
+template <int G>
+__device__ __forceinline__ void contract_tile(const float2* __restrict__ S,
+                                              const ActiveBeam* __restrict__ act, int n_act,
+                                              const float2* __restrict__ alpha, int p_base,
+                                              int gcount, int ns, int w, const UnionGeom& U,
+                                              int tile, const int* offx, const int* offy, int only,
+                                              float2 (*a_lds)[kCKB + 1], float2 (*s_lds)[kCTile],
+                                              float2* __restrict__ window) {
+  constexpr int RT = G / 8;  // 16-row MFMA tiles covering 2G real rows
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int npix = U.uy * U.ux;
+
+  // pixel this thread stages for the S block (fixed across K blocks)
+  const int n_ld = tid & (kCTile - 1);
+  const int up_ld = tile * kCTile + n_ld;
+  long long soff = -1;
+  if (up_ld < npix) {
+    const int a = up_ld / U.ux, b = up_ld - a * U.ux;
+    soff = (long long)((U.y0 + a) % ns) * ns + ((U.x0 + b) % ns);
+  }
+  const size_t plane = (size_t)ns * ns;
+
+  floatx4 acc[RT][2];
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  for (int kb = 0; kb < n_act; kb += kCKB) {
+    // alpha block [G][KB]
+#pragma unroll
+    for (int e = tid; e < G * kCKB; e += kCNT) {
+      const int g = e / kCKB, bl = e % kCKB;
+      float2 v = make_float2(0.f, 0.f);
+      if (g < gcount && kb + bl < n_act) v = alpha[(size_t)(p_base + g) * n_act + kb + bl];
+      a_lds[g][bl] = v;
+    }
+    // S block [KB][tile]
+#pragma unroll
+    for (int bl = tid / kCTile; bl < kCKB; bl += kCNT / kCTile) {
+      float2 v = make_float2(0.f, 0.f);
+      if (soff >= 0 && kb + bl < n_act) v = S[(size_t)act[kb + bl].plane * plane + soff];
+      s_lds[bl][n_ld] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kCKB / 2; ++ks) {
+      const int bl = 2 * ks + (lane >> 5);
+      const int ck = (lane >> 4) & 1;
+      float bv[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const float2 s = s_lds[bl][32 * wv + 16 * c + (lane & 15)];
+        bv[c] = ck ? s.y : s.x;
+      }
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        const int g = 8 * r + ((lane & 15) >> 1);
+        const float2 al = a_lds[g][bl];
+        const int cm = lane & 1;
+        const float av = cm ? (ck ? al.x : al.y) : (ck ? -al.y : al.x);
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[c], acc[r][c], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+
+  // epilogue: lane holds rows 4*(lane/16)+i of each 16x16 tile, column lane%16
+  const size_t w2 = (size_t)w * w;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int up = tile * kCTile + 32 * wv + 16 * c + (lane & 15);
+    if (up >= npix) continue;
+    const int a = up / U.ux, b = up - a * U.ux;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int g = 8 * r + 2 * (lane >> 4) + h;
+        if (g >= gcount || (only >= 0 && g != only)) continue;
+        const int v = a - offy[g], u = b - offx[g];
+        if (v < 0 || v >= w || u < 0 || u >= w) continue;
+        window[(size_t)(p_base + g) * w2 + (size_t)v * w + u] =
+            make_float2(acc[r][c][2 * h], acc[r][c][2 * h + 1]);
+      }
+    }
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(kCNT) void k_contract(const float2* __restrict__ S,
+                                                   const ActiveBeam* __restrict__ act, int n_act,
+                                                   const float2* __restrict__ alpha,
+                                                   const int2* __restrict__ origin, int np, int ns,
+                                                   int w, float2* __restrict__ window) {
+  __shared__ float2 a_lds[G][kCKB + 1];
+  __shared__ float2 s_lds[kCKB][kCTile];
+  __shared__ int offx[G], offy[G];
+  __shared__ int ginfo[6];
+  const int tid = threadIdx.x;
+  const int p_base = blockIdx.y * G;
+  const int gcount = min(G, np - p_base);
+  const int tile = blockIdx.x;
+  if (tid == 0) {
+    const int2 o0 = origin[p_base];
+    int minx = 0, maxx = 0, miny = 0, maxy = 0;
+    for (int g = 0; g < gcount; ++g) {
+      const int2 o = origin[p_base + g];
+      const int rx = wrap_mod((long long)o.x - o0.x + ns / 2, ns) - ns / 2;
+      const int ry = wrap_mod((long long)o.y - o0.y + ns / 2, ns) - ns / 2;
+      offx[g] = rx;
+      offy[g] = ry;
+      minx = min(minx, rx);
+      maxx = max(maxx, rx);
+      miny = min(miny, ry);
+      maxy = max(maxy, ry);
+    }
+    for (int g = 0; g < gcount; ++g) {
+      offx[g] -= minx;
+      offy[g] -= miny;
+    }
+    const int smax = w / 2;
+    ginfo[0] = (maxx - minx <= smax && maxy - miny <= smax) ? 0 : 1;
+    ginfo[1] = wrap_mod((long long)o0.y + miny, ns);
+    ginfo[2] = wrap_mod((long long)o0.x + minx, ns);
+    ginfo[3] = w + (maxy - miny);
+    ginfo[4] = w + (maxx - minx);
+  }
+  __syncthreads();
+  if (ginfo[0] == 0) {
+    UnionGeom U{ginfo[1], ginfo[2], ginfo[3], ginfo[4]};
+    if (tile * kCTile >= U.uy * U.ux) return;
+    contract_tile<G>(S, act, n_act, alpha, p_base, gcount, ns, w, U, tile, offx, offy, -1, a_lds,
+                     s_lds, window);
+  } else {
+    // windows too far apart to share: one probe at a time, its window alone
+    if (tile * kCTile >= w * w) return;
+    __shared__ int zero[G];
+    for (int g = tid; g < G; g += kCNT) zero[g] = 0;
+    __syncthreads();
+    for (int g = 0; g < gcount; ++g) {
+      const int2 o = origin[p_base + g];
+      UnionGeom U{o.y, o.x, w, w};
+      contract_tile<G>(S, act, n_act, alpha, p_base, gcount, ns, w, U, tile, zero, zero, g, a_lds,
+                       s_lds, window);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int wd_nt(int w) { return (w * w / 16) < 64 ? 64 : w * w / 16; }
+
+// One probe per workgroup: 2D FFT of the W x W window in LDS, then
+// I(kw) = |Psi(kw)|^2 / W^2 at full-grid frequency f kw, summed per bin in FP64.
+template <int W>
+__global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __restrict__ window,
+                                                            int f, const float2* __restrict__ twW,
+                                                            DetBins bins,
+                                                            double* __restrict__ out) {
+  constexpr int NT = wd_nt(W);
+  constexpr int NW = NT / 64;
+  using Rows = RowBatch<W, W>;
+  using Cols = Batch<W, W, W, 0, 1, W, true>;
+  __shared__ float2 lds[lds_padded(W * W)];
+  __shared__ float2 tw[W];
+  __shared__ double red[8][NW];
+  const int tid = threadIdx.x;
+  const size_t p = blockIdx.x;
+  const float2* src = window + p * W * W;
+  load_twiddles<W, NT>(tw, twW, tid);
+  for (int e = tid; e < W * W; e += NT) lds[lpad(e)] = src[e];
+  __syncthreads();
+  fft_lds<Rows, NT, false>(lds, tw, tid);
+  fft_lds<Cols, NT, false>(lds, tw, tid);
+  const double inv_w2 = 1.0 / ((double)W * (double)W);
+  const int f2 = f * f;
+  for (int j0 = 0; j0 < bins.n; j0 += 8) {
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (int e = tid; e < W * W; e += NT) {
+      const int v = e / W, u = e % W;
+      const int ky = v < W / 2 ? v : v - W, kx = u < W / 2 ? u : u - W;
+      const int k2 = f2 * (kx * kx + ky * ky);
+      const float2 z = lds[lpad(e)];
+      const double I = ((double)z.x * z.x + (double)z.y * z.y) * inv_w2;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = j0 + q;
+        if (j < bins.n && k2 >= bins.lo[j] && k2 < bins.hi[j]) acc[q] += I;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double s = wave_sum(acc[q]);
+      if ((tid & 63) == 0) red[q][tid >> 6] = s;
+    }
+    __syncthreads();
+    if (tid < 8 && j0 + tid < bins.n) {
+      double s = 0.0;
+      for (int wv = 0; wv < NW; ++wv) s += red[tid][wv];
+      out[p * bins.n + j0 + tid] = s;
+    }
+    __syncthreads();
+  }
+}
+
+inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+int contract_group(int w) { return w >= 128 ? 64 : (w >= 64 ? 32 : 16); }
+
+hipError_t launch_alpha(const double* probe_xy, int p0, int np, const ActiveBeam* act, int n_act,
+                        int f, int ns, int w, const ProbeOptics& po, float2* alpha,
+                        int2* origin, hipStream_t st) {
+  hipLaunchKernelGGL(k_alpha, dim3(blocks_for((size_t)np * n_act, 256)), dim3(256), 0, st,
+                     probe_xy, p0, np, act, n_act, f, ns, w, po, alpha, origin);
+  return hipGetLastError();
+}
+
+hipError_t launch_contract(const float2* smatrix, const ActiveBeam* act, int n_act,
+                           const float2* alpha, const int2* origin, int np, int ns, int w,
+                           int group, float2* window, hipStream_t st) {
+  const int smax = w / 2;
+  const int ext = w + smax;
+  const unsigned tiles = (unsigned)((ext * ext + kCTile - 1) / kCTile);
+  const unsigned groups = (unsigned)((np + group - 1) / group);
+  const dim3 grid(tiles, groups);
+  switch (group) {
+    case 16:
+      hipLaunchKernelGGL(k_contract<16>, grid, dim3(kCNT), 0, st, smatrix, act, n_act, alpha,
+                         origin, np, ns, w, window);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_contract<32>, grid, dim3(kCNT), 0, st, smatrix, act, n_act, alpha,
+                         origin, np, ns, w, window);
+      break;
+    case 64:
+      hipLaunchKernelGGL(k_contract<64>, grid, dim3(kCNT), 0, st, smatrix, act, n_act, alpha,
+                         origin, np, ns, w, window);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_window_detect(const float2* window, int np, int w, int f, const float2* twW,
+                                const DetBins& bins, double* out, hipStream_t st) {
+#define WD(WW)                                                                                   \
+  case WW:                                                                                       \
+    hipLaunchKernelGGL(k_window_detect<WW>, dim3((unsigned)np), dim3(wd_nt(WW)), 0, st, window, f, \
+                       twW, bins, out);                                                          \
+    break;
+  switch (w) {
+    WD(8)
+    WD(16)
+    WD(32)
+    WD(64)
+    WD(128)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef WD
+  return hipGetLastError();
+}
+
+}  // namespace prism

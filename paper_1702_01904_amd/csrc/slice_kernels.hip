@@ -1,0 +1,414 @@
+// Multislice kernels (Eqs. 3-5) shared by the PRISM S-matrix build (Fig. 1c)
+// and by conventional multislice STEM.
+//
+// One slice step psi <- iFFT2( FFT2(psi t_p) P_p M ) is split into two
+// HBM passes over the compact state X(y, kx) (layout in kernels.hpp):
+//   row pass    : X -> iFFT_x -> * t_p / n -> FFT_x -> keep |kx| < n/4 -> X'
+//   column pass : X' -> FFT_y -> * P_p(kx) P_p(ky) M / n -> iFFT_y -> X''
+// P_p is separable, so it comes from a 1D table per slice; M is the
+// half-band anti-aliasing aperture kx^2 + ky^2 < (n/4)^2. Each pass reads
+// and writes n^2/2 complex values per wave.
+#include "fft_lds.hpp"
+#include "kernels.hpp"
+
+namespace prism {
+
+namespace {
+
+constexpr int kRowNT = 256;
+
+__host__ __device__ constexpr int row_nseq(int n) { return 2048 / n > 0 ? 2048 / n : 1; }
+__host__ __device__ constexpr int col_tc(int n) { return n >= 2048 ? 4 : 8; }
+__host__ __device__ constexpr int col_nt(int n) {
+  return (col_tc(n) * n / 16) < 64 ? 64 : (col_tc(n) * n / 16 > 1024 ? 1024 : col_tc(n) * n / 16);
+}
+__host__ __device__ constexpr int ext_nseq(int n) { return 4096 / n; }
+
+// Map launch order onto tiles so that consecutive tiles run on the same
+// XCD (workgroups are dealt to the 8 XCDs round-robin) and share its L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+  if ((nb & 7) != 0) return bid;
+  return (bid & 7) * (nb >> 3) + (bid >> 3);
+}
+
+__device__ __forceinline__ int signed_k(int idx, int n) { return idx < n / 2 ? idx : idx - n; }
+
+// ---------------------------------------------------------------------------
+__global__ void k_twiddles(float2* tw, int L) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < L) {
+    double s, c;
+    sincospi(-2.0 * (double)i / (double)L, &s, &c);
+    tw[i] = make_float2((float)c, (float)s);
+  }
+}
+
+// t_p = exp(i phi_p) / n, the 1/n belonging to the row pass' inverse FFT.
+__global__ void k_transmission(const float* __restrict__ phase, float2* __restrict__ trans,
+                               size_t count, float scale) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) {
+    double s, c;
+    sincos((double)phase[i], &s, &c);
+    trans[i] = make_float2((float)(c * scale), (float)(s * scale));
+  }
+}
+
+__global__ void k_prop_lut(float2* lut, int n, int H, const double* __restrict__ thick, double lam,
+                           double dq) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * H) return;
+  const int p = i / n, idx = i % n;
+  const double k = (double)signed_k(idx, n);
+  double s, c;
+  sincospi(-lam * thick[p] * (k * dq) * (k * dq), &s, &c);
+  lut[i] = make_float2((float)c, (float)s);
+}
+
+// Tilted plane wave exp(2 pi i (m f x + n f y) / n) in compact form:
+// X(y, kx) = n exp(2 pi i ((n f y) mod n) / n) at kx = m f, zero elsewhere.
+__global__ void k_beam_init(float2* __restrict__ state, const int32_t* __restrict__ mn, int b0,
+                            int nb, int n, int f, const float2* __restrict__ twN) {
+  const int h2 = n / 2;
+  const size_t total = (size_t)nb * n * h2;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int w = (int)(i / ((size_t)n * h2));
+  const int rem = (int)(i % ((size_t)n * h2));
+  const int y = rem / h2, jj = rem % h2;
+  const int m = mn[2 * (b0 + w)], nn = mn[2 * (b0 + w) + 1];
+  const int kx = m * f;
+  const int jj0 = kx >= 0 ? kx : kx + h2;
+  float2 v = make_float2(0.f, 0.f);
+  if (jj == jj0) {
+    long long idx = ((long long)nn * f * y) % n;
+    if (idx < 0) idx += n;
+    const float2 t = twN[idx];  // exp(-2 pi i idx / n)
+    v = make_float2(t.x * (float)n, -t.y * (float)n);
+  }
+  state[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Row pass: NSEQ rows of length n per workgroup (2048 complex in LDS).
+template <int N>
+__global__ __launch_bounds__(kRowNT) void k_row_pass(float2* __restrict__ state,
+                                                     const float2* __restrict__ trans,
+                                                     const float2* __restrict__ twN) {
+  constexpr int NT = kRowNT;
+  constexpr int NSEQ = row_nseq(N);
+  constexpr int H2 = N / 2, Q = N / 4;
+  using B = RowBatch<N, NSEQ>;
+  __shared__ float2 lds[lds_padded(NSEQ * N)];
+  __shared__ float2 tw[N];
+  const int tid = threadIdx.x;
+  const size_t row0 = (size_t)blockIdx.x * NSEQ;
+  load_twiddles<N, NT>(tw, twN, tid);
+  for (int e = tid; e < NSEQ * H2; e += NT) {
+    const int s = e / H2, jj = e % H2;
+    const int full = jj < Q ? jj : jj + H2;
+    lds[lpad(s * N + full)] = state[(row0 + s) * H2 + jj];
+    lds[lpad(s * N + jj + Q)] = make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_lds<B, NT, true>(lds, tw, tid);
+  for (int e = tid; e < NSEQ * N; e += NT) {
+    const int s = e / N, x = e % N;
+    const int y = (int)((row0 + s) & (size_t)(N - 1));
+    lds[lpad(e)] = cmul(lds[lpad(e)], trans[(size_t)y * N + x]);
+  }
+  __syncthreads();
+  fft_lds<B, NT, false>(lds, tw, tid);
+  for (int e = tid; e < NSEQ * H2; e += NT) {
+    const int s = e / H2, jj = e % H2;
+    const int full = jj < Q ? jj : jj + H2;
+    state[(row0 + s) * H2 + jj] = lds[lpad(s * N + full)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass over a tile of TC adjacent compact columns, held [y][c].
+// DETECT: last multislice slice; instead of the inverse transform, form
+// I = |Psi|^2 / n^2 and write per-tile detector partial sums.
+template <int N, bool DETECT>
+__global__ __launch_bounds__(col_nt(N)) void k_col_pass(float2* __restrict__ state,
+                                                        const float2* __restrict__ prop,
+                                                        const float2* __restrict__ twN,
+                                                        DetBins bins, double* __restrict__ partial) {
+  constexpr int TC = col_tc(N), NT = col_nt(N);
+  constexpr int H2 = N / 2, Q = N / 4;
+  constexpr int TILES = H2 / TC;
+  constexpr int NW = NT / 64;
+  using B = Batch<N, TC, TC, 0, 1, TC, true>;
+  __shared__ float2 lds[lds_padded(TC * N)];
+  __shared__ float2 tw[N];
+  const int tid = threadIdx.x;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int w = tile / TILES, c0 = (tile % TILES) * TC;
+  float2* base = state + (size_t)w * N * H2 + c0;
+  load_twiddles<N, NT>(tw, twN, tid);
+  for (int e = tid; e < TC * N; e += NT) {
+    const int y = e / TC, c = e % TC;
+    lds[lpad(e)] = base[(size_t)y * H2 + c];
+  }
+  __syncthreads();
+  fft_lds<B, NT, false>(lds, tw, tid);
+  const float inv_n = 1.0f / (float)N;
+  for (int e = tid; e < TC * N; e += NT) {
+    const int y = e / TC, c = e % TC;
+    const int jj = c0 + c;
+    const int kx = jj < Q ? jj : jj - H2;
+    const int ky = signed_k(y, N);
+    const int k2 = kx * kx + ky * ky;
+    float2 v = lds[lpad(e)];
+    if (16 * k2 < N * N) {
+      v = cmul(cmul(v, prop[kx & (N - 1)]), prop[y]);
+      if (!DETECT) v = cscale(v, inv_n);
+    } else {
+      v = make_float2(0.f, 0.f);
+    }
+    lds[lpad(e)] = v;
+  }
+  __syncthreads();
+  if constexpr (!DETECT) {
+    fft_lds<B, NT, true>(lds, tw, tid);
+    for (int e = tid; e < TC * N; e += NT) {
+      const int y = e / TC, c = e % TC;
+      base[(size_t)y * H2 + c] = lds[lpad(e)];
+    }
+  } else {
+    __shared__ double red[8][NW];
+    const double inv_n2 = 1.0 / ((double)N * (double)N);
+    for (int j0 = 0; j0 < bins.n; j0 += 8) {
+      double acc[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+      for (int e = tid; e < TC * N; e += NT) {
+        const int y = e / TC, c = e % TC;
+        const int jj = c0 + c;
+        const int kx = jj < Q ? jj : jj - H2;
+        const int ky = signed_k(y, N);
+        const int k2 = kx * kx + ky * ky;
+        const float2 v = lds[lpad(e)];
+        const double I = ((double)v.x * v.x + (double)v.y * v.y) * inv_n2;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int j = j0 + q;
+          if (j < bins.n && k2 >= bins.lo[j] && k2 < bins.hi[j]) acc[q] += I;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double s = wave_sum(acc[q]);
+        if ((tid & 63) == 0) red[q][tid >> 6] = s;
+      }
+      __syncthreads();
+      if (tid < 8 && j0 + tid < bins.n) {
+        double s = 0.0;
+        for (int wv = 0; wv < NW; ++wv) s += red[tid][wv];
+        partial[((size_t)w * TILES + (tile % TILES)) * bins.n + j0 + tid] = s;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Incident multislice probe, built per compact column in Fourier space and
+// brought to X(y, kx) by an inverse FFT along y:
+//   X0(y, kx) = norm * sum_ky A e^{-i chi} e^{-2 pi i q.r0} e^{2 pi i ky y / n}
+// with norm = 1 / sqrt(N_A). Phases are evaluated in FP64.
+template <int N>
+__global__ __launch_bounds__(col_nt(N)) void k_probe_init(float2* __restrict__ state,
+                                                          const double* __restrict__ probe_xy,
+                                                          int p0, ProbeOptics po,
+                                                          const float2* __restrict__ twN) {
+  constexpr int TC = col_tc(N), NT = col_nt(N);
+  constexpr int H2 = N / 2, Q = N / 4;
+  constexpr int TILES = H2 / TC;
+  using B = Batch<N, TC, TC, 0, 1, TC, true>;
+  __shared__ float2 lds[lds_padded(TC * N)];
+  __shared__ float2 tw[N];
+  const int tid = threadIdx.x;
+  const int tile = blockIdx.x;
+  const int w = tile / TILES, c0 = (tile % TILES) * TC;
+  const double x0 = probe_xy[2 * (size_t)(p0 + w)], y0 = probe_xy[2 * (size_t)(p0 + w) + 1];
+  load_twiddles<N, NT>(tw, twN, tid);
+  const double dq2 = po.dq * po.dq;
+  for (int e = tid; e < TC * N; e += NT) {
+    const int y = e / TC, c = e % TC;
+    const int jj = c0 + c;
+    const int kx = jj < Q ? jj : jj - H2;
+    const int ky = signed_k(y, N);
+    const int k2 = kx * kx + ky * ky;
+    float2 v = make_float2(0.f, 0.f);
+    if (k2 <= po.k2_aperture) {
+      const double q2 = (double)k2 * dq2;
+      double t = -(0.5 * po.lam * q2 * po.C1 + 0.25 * po.lam * po.lam * po.lam * q2 * q2 * po.C3) -
+                 ((double)kx * x0 + (double)ky * y0) * po.dq;
+      t -= floor(t);
+      double s, co;
+      sincospi(2.0 * t, &s, &co);
+      v = make_float2((float)(co * po.norm), (float)(s * po.norm));
+    }
+    lds[lpad(e)] = v;
+  }
+  __syncthreads();
+  fft_lds<B, NT, true>(lds, tw, tid);
+  float2* base = state + (size_t)w * N * H2 + c0;
+  for (int e = tid; e < TC * N; e += NT) {
+    const int y = e / TC, c = e % TC;
+    base[(size_t)y * H2 + c] = lds[lpad(e)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Quarter-size exit wave: S(i', j') = psi_H(2 i', 2 j')
+//   = (1/n) sum_kx X(2 j', kx) exp(2 pi i kx i' / (n/2)),
+// an n/2-point inverse FFT of the even compact rows (already in n/2
+// fftfreq order).
+template <int N>
+__global__ __launch_bounds__(256) void k_extract(const float2* __restrict__ state,
+                                                 float2* __restrict__ S,
+                                                 const float2* __restrict__ twH) {
+  constexpr int NT = 256;
+  constexpr int H2 = N / 2;
+  constexpr int NSEQ = ext_nseq(N);
+  using B = RowBatch<H2, NSEQ>;
+  __shared__ float2 lds[lds_padded(NSEQ * H2)];
+  __shared__ float2 tw[H2];
+  const int tid = threadIdx.x;
+  const size_t g0 = (size_t)blockIdx.x * NSEQ;
+  load_twiddles<H2, NT>(tw, twH, tid);
+  for (int e = tid; e < NSEQ * H2; e += NT) {
+    const int s = e / H2, i = e % H2;
+    const size_t g = g0 + s;
+    const size_t w = g / H2, jp = g % H2;
+    lds[lpad(e)] = state[(w * N + 2 * jp) * H2 + i];
+  }
+  __syncthreads();
+  fft_lds<B, NT, true>(lds, tw, tid);
+  const float inv_n = 1.0f / (float)N;
+  for (int e = tid; e < NSEQ * H2; e += NT) {
+    const int s = e / H2, i = e % H2;
+    S[(g0 + s) * H2 + i] = cscale(lds[lpad(e)], inv_n);
+  }
+}
+
+__global__ void k_reduce_partials(const double* __restrict__ partial, int nwaves, int tiles,
+                                  int n_det, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nwaves * n_det) return;
+  const int w = i / n_det, j = i % n_det;
+  double s = 0.0;
+  for (int t = 0; t < tiles; ++t) s += partial[((size_t)w * tiles + t) * n_det + j];
+  out[i] = s;
+}
+
+inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers (sizes are validated by the host plan before any call).
+
+hipError_t launch_twiddles(float2* tw, int L, hipStream_t st) {
+  hipLaunchKernelGGL(k_twiddles, dim3(blocks_for(L, 256)), dim3(256), 0, st, tw, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_transmission(const float* phase, float2* trans, size_t count, float scale,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_transmission, dim3(blocks_for(count, 256)), dim3(256), 0, st, phase, trans,
+                     count, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_prop_lut(float2* lut, int n, int H, const double* thick_dev, double lam,
+                           double dq, hipStream_t st) {
+  hipLaunchKernelGGL(k_prop_lut, dim3(blocks_for((size_t)n * H, 256)), dim3(256), 0, st, lut, n,
+                     H, thick_dev, lam, dq);
+  return hipGetLastError();
+}
+
+hipError_t launch_beam_init(float2* state, const int32_t* beams_mn, int b0, int nb, int n, int f,
+                            const float2* twN, hipStream_t st) {
+  const size_t total = (size_t)nb * n * (n / 2);
+  hipLaunchKernelGGL(k_beam_init, dim3(blocks_for(total, 256)), dim3(256), 0, st, state, beams_mn,
+                     b0, nb, n, f, twN);
+  return hipGetLastError();
+}
+
+#define PRISM_DISPATCH_N(n, CALL) \
+  switch (n) {                    \
+    case 128: CALL(128); break;   \
+    case 256: CALL(256); break;   \
+    case 512: CALL(512); break;   \
+    case 1024: CALL(1024); break; \
+    case 2048: CALL(2048); break; \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_row_pass(float2* state, int nwaves, int n, const float2* trans_p,
+                           const float2* twN, hipStream_t st) {
+#define ROW(NN)                                                                                 \
+  hipLaunchKernelGGL(k_row_pass<NN>, dim3((unsigned)((size_t)nwaves * NN / row_nseq(NN))),     \
+                     dim3(kRowNT), 0, st, state, trans_p, twN)
+  PRISM_DISPATCH_N(n, ROW)
+#undef ROW
+  return hipGetLastError();
+}
+
+int col_tiles(int n) { return (n / 2) / col_tc(n); }
+
+hipError_t launch_col_pass(float2* state, int nwaves, int n, const float2* prop_p,
+                           const float2* twN, hipStream_t st) {
+  DetBins none{};
+#define COL(NN)                                                                                  \
+  hipLaunchKernelGGL((k_col_pass<NN, false>), dim3((unsigned)(nwaves * col_tiles(NN))),          \
+                     dim3(col_nt(NN)), 0, st, state, prop_p, twN, none, (double*)nullptr)
+  PRISM_DISPATCH_N(n, COL)
+#undef COL
+  return hipGetLastError();
+}
+
+hipError_t launch_col_detect(const float2* state, int nwaves, int n, const float2* prop_p,
+                             const float2* twN, const DetBins& bins, double* partial,
+                             hipStream_t st) {
+#define COLD(NN)                                                                                 \
+  hipLaunchKernelGGL((k_col_pass<NN, true>), dim3((unsigned)(nwaves * col_tiles(NN))),           \
+                     dim3(col_nt(NN)), 0, st, const_cast<float2*>(state), prop_p, twN, bins,    \
+                     partial)
+  PRISM_DISPATCH_N(n, COLD)
+#undef COLD
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_init(float2* state, const double* probe_xy, int p0, int np, int n,
+                             const ProbeOptics& po, const float2* twN, hipStream_t st) {
+#define PINIT(NN)                                                                                \
+  hipLaunchKernelGGL(k_probe_init<NN>, dim3((unsigned)(np * col_tiles(NN))), dim3(col_nt(NN)), 0, \
+                     st, state, probe_xy, p0, po, twN)
+  PRISM_DISPATCH_N(n, PINIT)
+#undef PINIT
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const double* partial, int nwaves, int tiles, int n_det,
+                                  double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for((size_t)nwaves * n_det, 256)), dim3(256),
+                     0, st, partial, nwaves, tiles, n_det, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract(const float2* state, int nwaves, int n, float2* smatrix,
+                          const float2* twH, hipStream_t st) {
+#define EXT(NN)                                                                                  \
+  hipLaunchKernelGGL(k_extract<NN>, dim3((unsigned)((size_t)nwaves * (NN / 2) / ext_nseq(NN))),  \
+                     dim3(256), 0, st, state, smatrix, twH)
+  PRISM_DISPATCH_N(n, EXT)
+#undef EXT
+  return hipGetLastError();
+}
+
+}  // namespace prism

@@ -252,6 +252,21 @@ def test_p7_prism_equals_cropped_multislice_of_periodised_probe(f):
         assert np.abs(I - cbed[p]).max() < 1e-12 * max(1.0, I.max())
 
 
+def test_p7_direct_single_probe_route_matches_prism_outputs():
+    d = build_inputs("tiny", 6)
+    cell, E, f = d["cell"], d["energy_keV"], 2
+    lam = O.wavelength(E)
+    optics = dict(alpha_mrad=20.0, C1_A=10.0, C3_A=2e4)
+    amax = O.default_alpha_max(0.020, f, lam, 1 / cell) * 1e3
+    beams, S = O.smatrix(d["phase"], d["thickness"], cell, E, f, amax)
+    pr = np.array([[0.4, 12.6], [6.3, 6.5]])
+    ref = O.prism_outputs(S, beams, f, cell, E, optics, pr, d["edges"])
+    for p, (x0, y0) in enumerate(pr):
+        got = O.prism_probe_direct(d["phase"], d["thickness"], cell, E, f, amax, optics, x0, y0,
+                                   d["edges"])
+        assert np.abs(got - ref[p]).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
 # ---------------------------------------------------------------- P8 translation
 
 def test_p8_multislice_one_pixel_shift():

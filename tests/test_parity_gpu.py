@@ -1,0 +1,273 @@
+"""GPU path (through the C ABI) against the FP64 oracle on the same inputs.
+
+Gate (FP32 path): eps_rel = ||D_gpu - D_ref||_2 / ||D_ref||_2 <= 1e-4 over
+the whole [P][n_det] output, and the same bound per S-matrix beam.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import build_inputs
+from paper_1702_01904_amd import tile_order, untile
+
+import _gpu as G
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def eps(a, ref):
+    a = np.asarray(a)
+    ref = np.asarray(ref)
+    assert np.all(np.isfinite(a))
+    return float(np.linalg.norm((a - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+
+def _amax(d, f, alpha_mrad=None):
+    lam = O.wavelength(d["energy_keV"])
+    a = (alpha_mrad if alpha_mrad is not None else d["optics"]["alpha_mrad"]) * 1e-3
+    return O.default_alpha_max(a, f, lam, 1.0 / d["cell"]) * 1e3
+
+
+# ------------------------------------------------------------------ tiny case
+
+@pytest.fixture(scope="module")
+def tiny():
+    d = build_inputs("tiny", 0)
+    plan = G.make_plan(d)
+    return d, plan
+
+
+def test_multislice_tiny(tiny):
+    d, plan = tiny
+    D = G.multislice_outputs(plan, d["probes"], d["optics"], d["edges"])
+    ref = O.multislice_stem(d["phase"], d["thickness"], d["cell"], d["energy_keV"], d["optics"],
+                            d["probes"], d["edges"])
+    e = eps(D, ref)
+    print(f"multislice tiny eps_rel={e:.3e}")
+    assert e <= TOL
+
+
+def test_multislice_tiny_aberrations_and_bins(tiny):
+    d, plan = tiny
+    optics = dict(alpha_mrad=18.0, C1_A=-35.0, C3_A=4.0e4)
+    edges = [(0.0, 9.0), (9.0, 18.0), (18.0, 40.0), (40.0, 80.0), (80.0, 105.0), (105.0, 300.0)]
+    pr = d["probes"][::7] + np.array([0.013, -0.021])
+    D = G.multislice_outputs(plan, pr, optics, edges)
+    ref = O.multislice_stem(d["phase"], d["thickness"], d["cell"], d["energy_keV"], optics, pr,
+                            edges)
+    assert eps(D, ref) <= TOL
+    assert np.abs(D[:, -1]).max() < 1e-12   # beyond the half-band limit
+
+
+@pytest.mark.parametrize("f", [1, 2])
+def test_smatrix_tiny(tiny, f):
+    d, plan = tiny
+    amax = _amax(d, f)
+    S = G.build_smatrix(plan, f, amax).cpu().numpy()
+    beams, Sref = O.smatrix(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax)
+    assert np.array_equal(plan.beams(f, amax), beams.astype(np.int32))
+    for b in range(len(beams)):
+        assert eps(S[b], Sref[b]) <= TOL, b
+
+
+@pytest.mark.parametrize("f", [1, 2])
+@pytest.mark.parametrize("order", ["raster", "tiles"])
+def test_prism_tiny(tiny, f, order):
+    d, plan = tiny
+    amax = _amax(d, f)
+    S = G.build_smatrix(plan, f, amax)
+    probes = d["probes"]
+    if order == "tiles":
+        _, tx, ty = plan.probe_group(f)
+        perm = tile_order(16, 16, tx, ty)
+        D = untile(G.probe_outputs(plan, f, amax, S, probes[perm], d["optics"], d["edges"]), perm)
+    else:
+        D = G.probe_outputs(plan, f, amax, S, probes, d["optics"], d["edges"])
+    beams, Sref = O.smatrix(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax)
+    ref = O.prism_outputs(Sref, beams, f, d["cell"], d["energy_keV"], d["optics"], probes,
+                          d["edges"])
+    e = eps(D, ref)
+    print(f"prism tiny f={f} {order} eps_rel={e:.3e}")
+    assert e <= TOL
+
+
+def test_prism_f1_equals_gpu_multislice(tiny):
+    # P6 re-run on GPU outputs only
+    d, plan = tiny
+    optics = dict(alpha_mrad=20.0, C1_A=25.0, C3_A=0.0)
+    amax = _amax(d, 1)
+    S = G.build_smatrix(plan, 1, amax)
+    pr = d["probes"][::5]
+    Dp = G.probe_outputs(plan, 1, amax, S, pr, optics, d["edges"])
+    Dm = G.multislice_outputs(plan, pr, optics, d["edges"])
+    assert eps(Dp, Dm) <= TOL
+
+
+def test_repeatable_bitwise(tiny):
+    d, plan = tiny
+    amax = _amax(d, 2)
+    S1 = G.build_smatrix(plan, 2, amax)
+    S2 = G.build_smatrix(plan, 2, amax)
+    assert bool((S1 == S2).all())
+    D1 = G.probe_outputs(plan, 2, amax, S1, d["probes"], d["optics"], d["edges"])
+    D2 = G.probe_outputs(plan, 2, amax, S1, d["probes"], d["optics"], d["edges"])
+    assert np.array_equal(D1, D2)
+    M1 = G.multislice_outputs(plan, d["probes"][:9], d["optics"], d["edges"])
+    M2 = G.multislice_outputs(plan, d["probes"][:9], d["optics"], d["edges"])
+    assert np.array_equal(M1, M2)
+
+
+def test_small_workspaces_give_same_results(tiny):
+    # minimum workspaces force one wave / one probe group per launch and
+    # ragged last chunks
+    d, plan = tiny
+    f = 2
+    amax = _amax(d, f)
+    S_pref = G.build_smatrix(plan, f, amax)
+    _, mn = plan.build_workspace_bytes(f, amax)
+    S_min = G.build_smatrix(plan, f, amax, ws_bytes=mn + 7 * 128 * 64 * 8)
+    assert eps(S_min.cpu().numpy(), S_pref.cpu().numpy()) <= 1e-6
+    pr = d["probes"][:77]
+    D_pref = G.probe_outputs(plan, f, amax, S_pref, pr, d["optics"], d["edges"])
+    _, mnp = plan.probe_workspace_bytes(f, amax, d["optics"])
+    D_min = G.probe_outputs(plan, f, amax, S_pref, pr, d["optics"], d["edges"], ws_bytes=mnp)
+    assert eps(D_min, D_pref) <= 1e-6
+    _, mnm = plan.multislice_workspace_bytes(1)
+    M_pref = G.multislice_outputs(plan, pr[:5], d["optics"], d["edges"])
+    M_min = G.multislice_outputs(plan, pr[:5], d["optics"], d["edges"], ws_bytes=mnm)
+    assert eps(M_min, M_pref) <= 1e-6
+
+
+def test_empty_cell_closed_forms_tiny():
+    d = build_inputs("tiny", 0)
+    d["phase"] = np.zeros_like(d["phase"])
+    plan = G.make_plan(d)
+    optics = dict(alpha_mrad=20.0, C1_A=40.0, C3_A=1e4)
+    edges = [(0.0, 10.0), (10.0, 21.0), (40.0, 150.0)]
+    pr = d["probes"][::9]
+    Dm = G.multislice_outputs(plan, pr, optics, edges)
+    ref_m = O.multislice_stem(d["phase"], d["thickness"], d["cell"], d["energy_keV"], optics, pr,
+                              edges)
+    assert eps(Dm, ref_m) <= TOL
+    assert np.allclose(Dm.sum(axis=1), 1.0, atol=1e-5)
+    for f in (1, 2, 4):
+        amax = _amax(d, f)
+        S = G.build_smatrix(plan, f, amax)
+        Dp = G.probe_outputs(plan, f, amax, S, pr, optics, edges)
+        beams = plan.beams(f, amax)
+        lam = plan.wavelength
+        th = lam * np.hypot(beams[:, 0] * f, beams[:, 1] * f) / d["cell"]
+        act = th <= 0.020
+        frac = [np.sum(act & (th < 0.010)) / act.sum(), np.sum(act & (th >= 0.010)) / act.sum(), 0]
+        assert eps(Dp, np.broadcast_to(frac, Dp.shape)) <= TOL
+
+
+# ------------------------------------------------------------------ mid-size case
+
+@pytest.fixture(scope="module")
+def mid():
+    d = build_inputs("mid256", 1)
+    plan = G.make_plan(d)
+    return d, plan
+
+
+def test_multislice_mid(mid):
+    d, plan = mid
+    pr = d["probes"][::3]
+    D = G.multislice_outputs(plan, pr, d["optics"], d["edges"])
+    ref = O.multislice_stem(d["phase"], d["thickness"], d["cell"], d["energy_keV"], d["optics"],
+                            pr, d["edges"])
+    assert eps(D, ref) <= TOL
+
+
+@pytest.mark.parametrize("f", [1, 2, 4])
+def test_prism_mid_ragged(mid, f):
+    d, plan = mid
+    amax = _amax(d, f)
+    S = G.build_smatrix(plan, f, amax)
+    beams, Sref = O.smatrix(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax)
+    Sg = S.cpu().numpy()
+    worst = max(eps(Sg[b], Sref[b]) for b in range(len(beams)))
+    assert worst <= TOL
+    D = G.probe_outputs(plan, f, amax, S, d["probes"], d["optics"], d["edges"])
+    ref = O.prism_outputs(Sref, beams, f, d["cell"], d["energy_keV"], d["optics"], d["probes"],
+                          d["edges"])
+    e = eps(D, ref)
+    print(f"prism mid f={f} P={len(d['probes'])} eps_rel={e:.3e} worst S eps={worst:.3e}")
+    assert e <= TOL
+
+
+# ------------------------------------------------------------------ full-size headline case
+
+@pytest.fixture(scope="module")
+def fcc():
+    d = build_inputs("fcc1024", 0)
+    plan = G.make_plan(d)
+    return d, plan
+
+
+def test_fcc1024_multislice_sampled(fcc):
+    d, plan = fcc
+    rng = np.random.default_rng(11)
+    pr = d["probes"][rng.choice(len(d["probes"]), 2, replace=False)]
+    D = G.multislice_outputs(plan, pr, d["optics"], d["edges"])
+    ref = O.multislice_stem(d["phase"], d["thickness"], d["cell"], d["energy_keV"], d["optics"],
+                            pr, d["edges"])
+    e = eps(D, ref)
+    print(f"fcc1024 multislice sampled eps_rel={e:.3e}")
+    assert e <= TOL
+
+
+def test_fcc1024_smatrix_sampled_beams(fcc):
+    d, plan = fcc
+    f = 16
+    amax = _amax(d, f)
+    S = G.build_smatrix(plan, f, amax)
+    beams = plan.beams(f, amax)
+    pick = [0, len(beams) // 2 + 3]
+    _, Sref = O.smatrix(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax,
+                        beams=beams[pick].astype(np.int64))
+    for i, b in enumerate(pick):
+        e = eps(S[b].cpu().numpy(), Sref[i])
+        print(f"fcc1024 S beam {b} eps_rel={e:.3e}")
+        assert e <= TOL
+
+
+@pytest.mark.parametrize("f", [4, 16])
+def test_fcc1024_prism_full_scan_sampled(fcc, f):
+    # the headline launch: whole 256 x 256 scan in tile order, then three
+    # probes checked against one-probe oracle runs
+    d, plan = fcc
+    amax = _amax(d, f)
+    S = G.build_smatrix(plan, f, amax)
+    _, tx, ty = plan.probe_group(f)
+    perm = tile_order(256, 256, tx, ty)
+    D = untile(G.probe_outputs(plan, f, amax, S, d["probes"][perm], d["optics"], d["edges"]), perm)
+    assert np.all(np.isfinite(D))
+    for p in (0, 40000, 65535):
+        x0, y0 = d["probes"][p]
+        ref = O.prism_probe_direct(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax,
+                                   d["optics"], x0, y0, d["edges"])
+        e = eps(D[p], ref)
+        print(f"fcc1024 prism f={f} probe {p} eps_rel={e:.3e}")
+        assert e <= TOL
+
+
+def test_fcc1024_empty_cell_prism_closed_form():
+    d = build_inputs("fcc1024", 0, n_slices=3)
+    d["phase"] = np.zeros_like(d["phase"])
+    plan = G.make_plan(d)
+    for f in (4, 8, 16):
+        amax = _amax(d, f)
+        S = G.build_smatrix(plan, f, amax)
+        _, tx, ty = plan.probe_group(f)
+        perm = tile_order(256, 256, tx, ty)[:4096]
+        Dp = G.probe_outputs(plan, f, amax, S, d["probes"][perm], d["optics"], d["edges"])
+        beams = plan.beams(f, amax)
+        th = plan.wavelength * np.hypot(beams[:, 0] * f, beams[:, 1] * f) / d["cell"]
+        act = th <= 0.025
+        edges = np.asarray(d["edges"]) * 1e-3
+        frac = [np.sum(act & (th >= lo) & (th < hi)) / act.sum() for lo, hi in edges]
+        assert eps(Dp, np.broadcast_to(frac, Dp.shape)) <= TOL
