@@ -124,58 +124,119 @@ struct Batch {
 template <int L, int NSEQ>
 using RowBatch = Batch<L, NSEQ, NSEQ, 0, L, 1, false>;
 
-// One Stockham stage of radix R with current span Ns (product of the
-// radices already applied). tw: LDS table of exp(-2 pi i k / L), k < L.
-template <class B, int R, int NT, bool INV>
-__device__ __forceinline__ void fft_stage(float2* lds, const float2* tw, int Ns, int tid) {
-  constexpr int L = B::L;
-  constexpr int NB = L / R;
-  constexpr int TOT = B::NSEQ * NB;
-  constexpr int PER = (TOT + NT - 1) / NT;
-  constexpr bool GUARD = (TOT % NT) != 0;
-  float2 v[PER][R];
-  int sidx[PER], jidx[PER];
-  const int tws = L / (Ns * R);
+// Butterfly numbering of a stage: butterfly b -> (sequence s, index j).
+template <class B, int NB>
+__device__ __forceinline__ void stage_coords(int b, int& s, int& j) {
+  if constexpr (B::SEQ_FAST) {
+    s = b % B::NSEQ;
+    j = b / B::NSEQ;
+  } else {
+    j = b % NB;
+    s = b / NB;
+  }
+}
+
+// Stockham stage of radix R with current span NS (product of the radices
+// already applied), split into its two halves so that callers can keep a
+// stage's inputs or outputs in registers:
+//   stage_in  reads the R inputs of each butterfly of this thread from LDS
+//             and applies the twiddles (none when NS == 1);
+//   stage_out applies the R-point DFTs and writes the outputs to LDS.
+// Butterfly j of sequence s reads elements j + r L/R and writes elements
+// (j - k) R + k + r NS with k = j mod NS. tw: exp(-2 pi i m / L), m < L.
+template <class B, int R, int NT>
+struct StageShape {
+  static constexpr int NB = B::L / R;
+  static constexpr int TOT = B::NSEQ * NB;
+  static constexpr int PER = (TOT + NT - 1) / NT;
+  static constexpr bool GUARD = (TOT % NT) != 0;
+};
+
+template <class B, int R, int NS, int NT, bool INV>
+__device__ __forceinline__ void stage_in(const float2* lds, const float2* tw, int tid,
+                                         float2 (&v)[StageShape<B, R, NT>::PER][R]) {
+  using SS = StageShape<B, R, NT>;
+  constexpr int TWS = B::L / (NS * R);
 #pragma unroll
-  for (int p = 0; p < PER; ++p) {
+  for (int p = 0; p < SS::PER; ++p) {
     const int b = tid + p * NT;
-    int s, j;
-    if constexpr (B::SEQ_FAST) {
-      s = b % B::NSEQ;
-      j = b / B::NSEQ;
-    } else {
-      j = b % NB;
-      s = b / NB;
-    }
-    sidx[p] = s;
-    jidx[p] = j;
-    if (!GUARD || b < TOT) {
-      const int k = j & (Ns - 1);
+    if (!SS::GUARD || b < SS::TOT) {
+      int s, j;
+      stage_coords<B, SS::NB>(b, s, j);
+      const int k = j & (NS - 1);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        float2 x = lds[lpad(B::addr(s, j + r * NB))];
-        if (r > 0) {
-          const float2 w = tw[r * k * tws];
+        float2 x = lds[lpad(B::addr(s, j + r * SS::NB))];
+        if (NS > 1 && r > 0) {
+          const float2 w = tw[r * k * TWS];
           x = INV ? cmulc(x, w) : cmul(x, w);
         }
         v[p][r] = x;
       }
     }
   }
-  __syncthreads();
+}
+
+template <class B, int R, int NS, int NT, bool INV>
+__device__ __forceinline__ void stage_out(float2* lds, int tid,
+                                          float2 (&v)[StageShape<B, R, NT>::PER][R]) {
+  using SS = StageShape<B, R, NT>;
 #pragma unroll
-  for (int p = 0; p < PER; ++p) {
+  for (int p = 0; p < SS::PER; ++p) {
     const int b = tid + p * NT;
-    if (!GUARD || b < TOT) {
+    if (!SS::GUARD || b < SS::TOT) {
+      int s, j;
+      stage_coords<B, SS::NB>(b, s, j);
       dft<R, INV>(v[p]);
-      const int j = jidx[p], s = sidx[p];
-      const int k = j & (Ns - 1);
+      const int k = j & (NS - 1);
       const int o = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[lpad(B::addr(s, o + r * Ns))] = v[p][r];
+      for (int r = 0; r < R; ++r) lds[lpad(B::addr(s, o + r * NS))] = v[p][r];
     }
   }
+}
+
+// One complete in-place stage (read, barrier, write, barrier).
+template <class B, int R, int NS, int NT, bool INV>
+__device__ __forceinline__ void fft_stage(float2* lds, const float2* tw, int tid) {
+  float2 v[StageShape<B, R, NT>::PER][R];
+  stage_in<B, R, NS, NT, INV>(lds, tw, tid, v);
   __syncthreads();
+  stage_out<B, R, NS, NT, INV>(lds, tid, v);
+  __syncthreads();
+}
+
+// COUNT consecutive radix-8 stages starting at span NS.
+template <class B, int NT, bool INV, int NS, int COUNT>
+__device__ __forceinline__ void fft_radix8_run(float2* lds, const float2* tw, int tid) {
+  if constexpr (COUNT > 0) {
+    fft_stage<B, 8, NS, NT, INV>(lds, tw, tid);
+    fft_radix8_run<B, NT, INV, NS * 8, COUNT - 1>(lds, tw, tid);
+  }
+}
+
+// Radix plan of a length-L transform split as 8 * 8^MID * RL (RL in 2, 4, 8):
+// the inverse runs 8, 8^MID, RL and the forward the reverse RL, 8^MID, 8, so
+// that the inverse's last stage and the forward's first stage pair up on
+// the same elements (j + r L/RL) and can stay in registers.
+template <int L>
+struct PairedPlan {
+  static constexpr int K = ilog2(L);
+  static constexpr int RL = (K % 3 == 1) ? 2 : ((K % 3 == 2) ? 4 : 8);
+  static constexpr int MID = (K - 3 - ilog2(RL)) / 3;
+};
+
+template <class B, int NT, bool INV, int NS>
+__device__ __forceinline__ void fft_from(float2* lds, const float2* tw, int tid) {
+  constexpr int REM = B::L / NS;  // product of the radices still to apply
+  if constexpr (REM >= 8) {
+    fft_stage<B, 8, NS, NT, INV>(lds, tw, tid);
+    fft_from<B, NT, INV, NS * 8>(lds, tw, tid);
+  } else if constexpr (REM == 4) {
+    fft_stage<B, 4, NS, NT, INV>(lds, tw, tid);
+  } else if constexpr (REM == 2) {
+    fft_stage<B, 2, NS, NT, INV>(lds, tw, tid);
+  }
 }
 
 // Full length-L transform of every sequence in the batch. The caller must
@@ -183,16 +244,8 @@ __device__ __forceinline__ void fft_stage(float2* lds, const float2* tw, int Ns,
 // return the result is in LDS and visible to all threads.
 template <class B, int NT, bool INV>
 __device__ __forceinline__ void fft_lds(float2* lds, const float2* tw, int tid) {
-  constexpr int K = ilog2(B::L);
-  static_assert((1 << K) == B::L, "power-of-two lengths only");
-  int Ns = 1;
-#pragma unroll
-  for (int st = 0; st < K / 3; ++st) {
-    fft_stage<B, 8, NT, INV>(lds, tw, Ns, tid);
-    Ns *= 8;
-  }
-  if constexpr (K % 3 == 1) fft_stage<B, 2, NT, INV>(lds, tw, Ns, tid);
-  if constexpr (K % 3 == 2) fft_stage<B, 4, NT, INV>(lds, tw, Ns, tid);
+  static_assert((1 << ilog2(B::L)) == B::L, "power-of-two lengths only");
+  fft_from<B, NT, INV, 1>(lds, tw, tid);
 }
 
 // Copy a twiddle table from global memory into LDS (no barrier).

@@ -15,12 +15,27 @@ namespace prism {
 
 namespace {
 
-constexpr int kRowNT = 256;
+// Launch shapes (tuned on MI355X; overridable at build time).
+#ifndef PRISM_ROW_ELEMS
+#define PRISM_ROW_ELEMS 2048   // complex values per row-pass workgroup
+#endif
+#ifndef PRISM_COL_E
+#define PRISM_COL_E 8          // complex values per column-pass thread
+#endif
+#ifndef PRISM_COL_WPE
+#define PRISM_COL_WPE 1        // minimum waves per SIMD for the column pass
+#endif
 
-__host__ __device__ constexpr int row_nseq(int n) { return 2048 / n > 0 ? 2048 / n : 1; }
+constexpr int kRowNT = PRISM_ROW_ELEMS / 8;
+
+__host__ __device__ constexpr int row_nseq(int n) {
+  return PRISM_ROW_ELEMS / n > 0 ? PRISM_ROW_ELEMS / n : 1;
+}
 __host__ __device__ constexpr int col_tc(int n) { return n >= 2048 ? 4 : 8; }
 __host__ __device__ constexpr int col_nt(int n) {
-  return (col_tc(n) * n / 16) < 64 ? 64 : (col_tc(n) * n / 16 > 1024 ? 1024 : col_tc(n) * n / 16);
+  return (col_tc(n) * n / PRISM_COL_E) < 64
+             ? 64
+             : (col_tc(n) * n / PRISM_COL_E > 1024 ? 1024 : col_tc(n) * n / PRISM_COL_E);
 }
 __host__ __device__ constexpr int ext_nseq(int n) { return 4096 / n; }
 
@@ -90,56 +105,100 @@ __global__ void k_beam_init(float2* __restrict__ state, const int32_t* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Row pass: NSEQ rows of length n per workgroup (2048 complex in LDS).
+// Row pass: NSEQ rows of length n per workgroup (PRISM_ROW_ELEMS complex in
+// LDS). The inverse x-transform runs 8, 8^MID, RL and the forward one
+// RL, 8^MID, 8 (PairedPlan): the inverse's first stage reads the compact row
+// straight from HBM (its inputs at |kx| >= n/4 are zero), its last stage
+// stays in registers, is multiplied by t_p / n and feeds the forward's first
+// stage, and the forward's last stage stores only the kept half band.
 template <int N>
 __global__ __launch_bounds__(kRowNT) void k_row_pass(float2* __restrict__ state,
                                                      const float2* __restrict__ trans,
                                                      const float2* __restrict__ twN) {
   constexpr int NT = kRowNT;
   constexpr int NSEQ = row_nseq(N);
-  constexpr int H2 = N / 2, Q = N / 4;
+  constexpr int H2 = N / 2, E8 = N / 8;
   using B = RowBatch<N, NSEQ>;
+  using PP = PairedPlan<N>;
+  constexpr int RL = PP::RL, NSL = N / PP::RL;
+  using S8 = StageShape<B, 8, NT>;
+  using SL = StageShape<B, RL, NT>;
   __shared__ float2 lds[lds_padded(NSEQ * N)];
   __shared__ float2 tw[N];
   const int tid = threadIdx.x;
   const size_t row0 = (size_t)blockIdx.x * NSEQ;
   load_twiddles<N, NT>(tw, twN, tid);
-  for (int e = tid; e < NSEQ * H2; e += NT) {
-    const int s = e / H2, jj = e % H2;
-    const int full = jj < Q ? jj : jj + H2;
-    lds[lpad(s * N + full)] = state[(row0 + s) * H2 + jj];
-    lds[lpad(s * N + jj + Q)] = make_float2(0.f, 0.f);
+  {
+    // inverse, first stage (span 1): inputs j + r n/8, nonzero for r in {0,1,6,7}
+    float2 v[S8::PER][8];
+#pragma unroll
+    for (int p = 0; p < S8::PER; ++p) {
+      int sq, j;
+      stage_coords<B, S8::NB>(tid + p * NT, sq, j);
+      const float2* src = state + (row0 + sq) * H2 + j;
+      v[p][0] = src[0];
+      v[p][1] = src[E8];
+      v[p][2] = v[p][3] = v[p][4] = v[p][5] = make_float2(0.f, 0.f);
+      v[p][6] = src[2 * E8];
+      v[p][7] = src[3 * E8];
+    }
+    stage_out<B, 8, 1, NT, true>(lds, tid, v);
   }
   __syncthreads();
-  fft_lds<B, NT, true>(lds, tw, tid);
-  for (int e = tid; e < NSEQ * N; e += NT) {
-    const int s = e / N, x = e % N;
-    const int y = (int)((row0 + s) & (size_t)(N - 1));
-    lds[lpad(e)] = cmul(lds[lpad(e)], trans[(size_t)y * N + x]);
+  fft_radix8_run<B, NT, true, 8, PP::MID>(lds, tw, tid);
+  float2 v[SL::PER][RL];
+  stage_in<B, RL, NSL, NT, true>(lds, tw, tid, v);
+#pragma unroll
+  for (int p = 0; p < SL::PER; ++p) {
+    int sq, j;
+    stage_coords<B, SL::NB>(tid + p * NT, sq, j);
+    dft<RL, true>(v[p]);
+    const float2* t = trans + (size_t)((row0 + sq) & (size_t)(N - 1)) * N + j;
+#pragma unroll
+    for (int r = 0; r < RL; ++r) v[p][r] = cmul(v[p][r], t[r * NSL]);
   }
   __syncthreads();
-  fft_lds<B, NT, false>(lds, tw, tid);
-  for (int e = tid; e < NSEQ * H2; e += NT) {
-    const int s = e / H2, jj = e % H2;
-    const int full = jj < Q ? jj : jj + H2;
-    state[(row0 + s) * H2 + jj] = lds[lpad(s * N + full)];
+  stage_out<B, RL, 1, NT, false>(lds, tid, v);
+  __syncthreads();
+  fft_radix8_run<B, NT, false, RL, PP::MID>(lds, tw, tid);
+  {
+    // forward, last stage (span n/8): outputs j + r n/8, kept for r in {0,1,6,7}
+    float2 w[S8::PER][8];
+    stage_in<B, 8, E8, NT, false>(lds, tw, tid, w);
+#pragma unroll
+    for (int p = 0; p < S8::PER; ++p) {
+      int sq, j;
+      stage_coords<B, S8::NB>(tid + p * NT, sq, j);
+      dft8<false>(w[p]);
+      float2* dst = state + (row0 + sq) * H2 + j;
+      dst[0] = w[p][0];
+      dst[E8] = w[p][1];
+      dst[2 * E8] = w[p][6];
+      dst[3 * E8] = w[p][7];
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Column pass over a tile of TC adjacent compact columns, held [y][c].
+// Column pass over a tile of TC adjacent compact columns, held [y][c]. The
+// forward y-transform reads straight from HBM, its last stage stays in
+// registers for the propagator and band limit, and the inverse's last stage
+// stores straight to HBM (PairedPlan order, as in the row pass).
 // DETECT: last multislice slice; instead of the inverse transform, form
 // I = |Psi|^2 / n^2 and write per-tile detector partial sums.
 template <int N, bool DETECT>
-__global__ __launch_bounds__(col_nt(N)) void k_col_pass(float2* __restrict__ state,
-                                                        const float2* __restrict__ prop,
-                                                        const float2* __restrict__ twN,
-                                                        DetBins bins, double* __restrict__ partial) {
+__global__ __launch_bounds__(col_nt(N)) __attribute__((amdgpu_waves_per_eu(PRISM_COL_WPE)))
+void k_col_pass(float2* __restrict__ state, const float2* __restrict__ prop,
+                const float2* __restrict__ twN, DetBins bins, double* __restrict__ partial) {
   constexpr int TC = col_tc(N), NT = col_nt(N);
-  constexpr int H2 = N / 2, Q = N / 4;
+  constexpr int H2 = N / 2, Q = N / 4, E8 = N / 8;
   constexpr int TILES = H2 / TC;
   constexpr int NW = NT / 64;
   using B = Batch<N, TC, TC, 0, 1, TC, true>;
+  using PP = PairedPlan<N>;
+  constexpr int RL = PP::RL, NSL = N / PP::RL;
+  using S8 = StageShape<B, 8, NT>;
+  using SL = StageShape<B, RL, NT>;
   __shared__ float2 lds[lds_padded(TC * N)];
   __shared__ float2 tw[N];
   const int tid = threadIdx.x;
@@ -147,34 +206,57 @@ __global__ __launch_bounds__(col_nt(N)) void k_col_pass(float2* __restrict__ sta
   const int w = tile / TILES, c0 = (tile % TILES) * TC;
   float2* base = state + (size_t)w * N * H2 + c0;
   load_twiddles<N, NT>(tw, twN, tid);
-  for (int e = tid; e < TC * N; e += NT) {
-    const int y = e / TC, c = e % TC;
-    lds[lpad(e)] = base[(size_t)y * H2 + c];
+  {
+    float2 v[S8::PER][8];
+#pragma unroll
+    for (int p = 0; p < S8::PER; ++p) {
+      int c, j;
+      stage_coords<B, S8::NB>(tid + p * NT, c, j);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[p][r] = base[(size_t)(j + r * E8) * H2 + c];
+    }
+    stage_out<B, 8, 1, NT, false>(lds, tid, v);
   }
   __syncthreads();
-  fft_lds<B, NT, false>(lds, tw, tid);
+  fft_radix8_run<B, NT, false, 8, PP::MID>(lds, tw, tid);
+  float2 v[SL::PER][RL];
+  stage_in<B, RL, NSL, NT, false>(lds, tw, tid, v);
   const float inv_n = 1.0f / (float)N;
-  for (int e = tid; e < TC * N; e += NT) {
-    const int y = e / TC, c = e % TC;
+#pragma unroll
+  for (int p = 0; p < SL::PER; ++p) {
+    int c, j;
+    stage_coords<B, SL::NB>(tid + p * NT, c, j);
+    dft<RL, false>(v[p]);
     const int jj = c0 + c;
     const int kx = jj < Q ? jj : jj - H2;
-    const int ky = signed_k(y, N);
-    const int k2 = kx * kx + ky * ky;
-    float2 v = lds[lpad(e)];
-    if (16 * k2 < N * N) {
-      v = cmul(cmul(v, prop[kx & (N - 1)]), prop[y]);
-      if (!DETECT) v = cscale(v, inv_n);
-    } else {
-      v = make_float2(0.f, 0.f);
+    const float2 px = prop[kx & (N - 1)];
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int yi = j + r * NSL;
+      const int ky = signed_k(yi, N);
+      const int k2 = kx * kx + ky * ky;
+      if (16 * k2 < N * N) {
+        float2 z = cmul(cmul(v[p][r], px), prop[yi]);
+        v[p][r] = DETECT ? z : cscale(z, inv_n);
+      } else {
+        v[p][r] = make_float2(0.f, 0.f);
+      }
     }
-    lds[lpad(e)] = v;
   }
-  __syncthreads();
   if constexpr (!DETECT) {
-    fft_lds<B, NT, true>(lds, tw, tid);
-    for (int e = tid; e < TC * N; e += NT) {
-      const int y = e / TC, c = e % TC;
-      base[(size_t)y * H2 + c] = lds[lpad(e)];
+    __syncthreads();
+    stage_out<B, RL, 1, NT, true>(lds, tid, v);
+    __syncthreads();
+    fft_radix8_run<B, NT, true, RL, PP::MID>(lds, tw, tid);
+    float2 u[S8::PER][8];
+    stage_in<B, 8, E8, NT, true>(lds, tw, tid, u);
+#pragma unroll
+    for (int p = 0; p < S8::PER; ++p) {
+      int c, j;
+      stage_coords<B, S8::NB>(tid + p * NT, c, j);
+      dft8<true>(u[p]);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) base[(size_t)(j + r * E8) * H2 + c] = u[p][r];
     }
   } else {
     __shared__ double red[8][NW];
@@ -183,30 +265,34 @@ __global__ __launch_bounds__(col_nt(N)) void k_col_pass(float2* __restrict__ sta
       double acc[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-      for (int e = tid; e < TC * N; e += NT) {
-        const int y = e / TC, c = e % TC;
+#pragma unroll
+      for (int p = 0; p < SL::PER; ++p) {
+        int c, j;
+        stage_coords<B, SL::NB>(tid + p * NT, c, j);
         const int jj = c0 + c;
         const int kx = jj < Q ? jj : jj - H2;
-        const int ky = signed_k(y, N);
-        const int k2 = kx * kx + ky * ky;
-        const float2 v = lds[lpad(e)];
-        const double I = ((double)v.x * v.x + (double)v.y * v.y) * inv_n2;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int j = j0 + q;
-          if (j < bins.n && k2 >= bins.lo[j] && k2 < bins.hi[j]) acc[q] += I;
+        for (int r = 0; r < RL; ++r) {
+          const int ky = signed_k(j + r * NSL, N);
+          const int k2 = kx * kx + ky * ky;
+          const double I = ((double)v[p][r].x * v[p][r].x + (double)v[p][r].y * v[p][r].y) * inv_n2;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int jb = j0 + q;
+            if (jb < bins.n && k2 >= bins.lo[jb] && k2 < bins.hi[jb]) acc[q] += I;
+          }
         }
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const double s = wave_sum(acc[q]);
-        if ((tid & 63) == 0) red[q][tid >> 6] = s;
+        const double sum = wave_sum(acc[q]);
+        if ((tid & 63) == 0) red[q][tid >> 6] = sum;
       }
       __syncthreads();
       if (tid < 8 && j0 + tid < bins.n) {
-        double s = 0.0;
-        for (int wv = 0; wv < NW; ++wv) s += red[tid][wv];
-        partial[((size_t)w * TILES + (tile % TILES)) * bins.n + j0 + tid] = s;
+        double sum = 0.0;
+        for (int wv = 0; wv < NW; ++wv) sum += red[tid][wv];
+        partial[((size_t)w * TILES + (tile % TILES)) * bins.n + j0 + tid] = sum;
       }
       __syncthreads();
     }
