@@ -78,7 +78,14 @@ hipError_t launch_contract(const float2* smatrix, const ActiveBeam* act, int n_a
                            const float2* alpha, const int2* origin, int np, int ns, int w,
                            int group, float2* window, hipStream_t st);
 int contract_group(int w);
-hipError_t launch_window_detect(const float2* window, int np, int w, int f, const float2* twW,
-                                const DetBins& bins, double* out, hipStream_t st);
+// Detector bins as lists of window pixels: bin j holds the pixel indices
+// pix[off[j] .. off[j+1]) (v * W + u) of the W x W window.
+struct BinLists {
+  int n;
+  int off[kMaxDet + 1];
+};
+hipError_t launch_window_detect(const float2* window, int np, int w, const float2* twW,
+                                const uint16_t* pix, const BinLists& lists, double* out,
+                                hipStream_t st);
 
 }  // namespace prism

@@ -96,6 +96,11 @@ struct prism_plan {
   const float* phase = nullptr;
   std::map<std::pair<int, uint64_t>, std::vector<int32_t>> beams;  // (f, alpha_max) -> [B][2]
   std::map<std::tuple<int, uint64_t, uint64_t>, std::vector<prism::ActiveBeam>> active;
+  struct PixLists {
+    std::vector<uint16_t> pix;
+    prism::BinLists lists;
+  };
+  std::map<std::string, PixLists> pixlists;  // window detector bin lists
 
   // scattering angle (rad) of integer full-grid |k|^2
   double theta(long long k2) const { return (lam * dq) * std::sqrt((double)k2); }
@@ -223,6 +228,31 @@ const std::vector<prism::ActiveBeam>* get_active(prism_plan* p, int f, double am
   return &(p->active[key] = std::move(act));
 }
 
+// Per-bin pixel lists of the W x W PRISM window: pixel (v, u) has full-grid
+// frequency f * (kx, ky) with (kx, ky) the window's fftfreq indices.
+const prism_plan::PixLists* get_pixlists(prism_plan* p, int w, int f, const prism::DetBins& b) {
+  std::string key = std::to_string(w) + ":" + std::to_string(f);
+  for (int j = 0; j < b.n; ++j) key += ":" + std::to_string(b.lo[j]) + "-" + std::to_string(b.hi[j]);
+  auto it = p->pixlists.find(key);
+  if (it != p->pixlists.end()) return &it->second;
+  prism_plan::PixLists pl;
+  std::memset(&pl.lists, 0, sizeof pl.lists);
+  pl.lists.n = b.n;
+  for (int j = 0; j < b.n; ++j) {
+    pl.lists.off[j] = (int)pl.pix.size();
+    for (int v = 0; v < w; ++v) {
+      const long long ky = v < w / 2 ? v : v - w;
+      for (int u = 0; u < w; ++u) {
+        const long long kx = u < w / 2 ? u : u - w;
+        const long long k2 = (long long)f * f * (kx * kx + ky * ky);
+        if (k2 >= b.lo[j] && k2 < b.hi[j]) pl.pix.push_back((uint16_t)(v * w + u));
+      }
+    }
+  }
+  pl.lists.off[b.n] = (int)pl.pix.size();
+  return &(p->pixlists[key] = std::move(pl));
+}
+
 // ---------------------------------------------------------------- layouts
 
 constexpr size_t kChunkBytes = size_t(1) << 28;  // preferred wave-state size per chunk
@@ -268,6 +298,7 @@ int choose_chunk(const prism_plan* p, int want, int n_beams, int n_det, size_t w
 
 struct ProbeWs {
   float2* twW;
+  uint16_t* pix;
   prism::ActiveBeam* act;
   float2* alpha;
   int2* origin;
@@ -277,6 +308,7 @@ struct ProbeWs {
 size_t probe_layout(int w, int n_act, int chunk, ProbeWs* pw, void* base) {
   Carve c(base);
   pw->twW = c.take<float2>(w);
+  pw->pix = c.take<uint16_t>((size_t)PRISM_MAX_DET * w * w);  // worst case: overlapping bins
   pw->act = c.take<prism::ActiveBeam>(n_act);
   pw->alpha = c.take<float2>((size_t)chunk * n_act);
   pw->origin = c.take<int2>(chunk);
@@ -590,6 +622,11 @@ int prism_probe_outputs(prism_plan* p, int f, double amax_mrad, const void* S, c
   probe_layout(w, n_act, chunk, &pw, base);
   hipStream_t st = static_cast<hipStream_t>(stream);
   LAUNCH(p, st, "twiddles", prism::launch_twiddles(pw.twW, w, st));
+  const auto* pl = get_pixlists(p, w, f, bins);
+  if (!pl->pix.empty())
+    HIP_TRY(hipMemcpyAsync(pw.pix, pl->pix.data(), pl->pix.size() * sizeof(uint16_t),
+                           hipMemcpyHostToDevice, st),
+            "copy detector pixel lists");
   HIP_TRY(hipMemcpyAsync(pw.act, act->data(), act->size() * sizeof(prism::ActiveBeam),
                          hipMemcpyHostToDevice, st),
           "copy active beams");
@@ -601,8 +638,9 @@ int prism_probe_outputs(prism_plan* p, int f, double amax_mrad, const void* S, c
     LAUNCH(p, st, "alpha", prism::launch_alpha(xy, p0, np, pw.act, n_act, f, ns, w, po, pw.alpha, pw.origin, st));
     LAUNCH(p, st, "contract", prism::launch_contract(Sd, pw.act, n_act, pw.alpha, pw.origin, np, ns, w, G, pw.window,
                                    st));
-    LAUNCH(p, st, "window_detect", prism::launch_window_detect(pw.window, np, w, f, pw.twW, bins,
-                                        out + (size_t)p0 * bins.n, st));
+    LAUNCH(p, st, "window_detect",
+           prism::launch_window_detect(pw.window, np, w, pw.twW, pw.pix, pl->lists,
+                                       out + (size_t)p0 * bins.n, st));
   }
   return PRISM_OK;
 }

@@ -52,9 +52,20 @@ __global__ void k_alpha(const double* __restrict__ probe_xy, int p0, int np,
   alpha[i] = make_float2((float)(c * po.norm), (float)(s * po.norm));
 }
 
-constexpr int kCNT = 256;    // threads per contraction workgroup (4 waves)
-constexpr int kCTile = 128;  // union pixels per workgroup (32 per wave)
-constexpr int kCKB = 16;     // beams per K block
+// Contraction tile shape (tuned on MI355X; overridable at build time).
+#ifndef PRISM_CKB
+#define PRISM_CKB 16   // beams per K block
+#endif
+#ifndef PRISM_CCT
+#define PRISM_CCT 2    // 16-pixel MFMA column tiles per wave
+#endif
+#ifndef PRISM_CG128
+#define PRISM_CG128 64 // probes per group for W >= 128
+#endif
+constexpr int kCNT = 256;                 // threads per contraction workgroup (4 waves)
+constexpr int kCCT = PRISM_CCT;
+constexpr int kCTile = 4 * 16 * kCCT;     // union pixels per workgroup
+constexpr int kCKB = PRISM_CKB;
 
 struct UnionGeom {
   int y0, x0;  // first S pixel of the union (periodic)
@@ -63,21 +74,38 @@ struct UnionGeom {
 
 // Contract one 128-pixel tile of the union for all G probes of the group.
 // only < 0: write every probe whose window holds a pixel; only >= 0: write
-// that probe alone (scattered groups).
+// that probe alone (scattered groups). The K loop is double buffered: the
+// next 16-beam block of alpha and S is fetched into registers while the
+// MFMAs consume the current block from LDS.
+template <int G>
+struct ContractLds {
+  static constexpr int AROW = 2 * G + 16;        // A'[k'][m'] row pitch (floats)
+  static constexpr int BROW = kCTile + 16;       // B'[k'][n] row pitch (floats)
+  static constexpr int ABUF = 2 * kCKB * AROW;   // floats per A' buffer
+  static constexpr int BBUF = 2 * kCKB * BROW;   // floats per B' buffer
+  static constexpr int FLOATS = 2 * (ABUF + BBUF);
+};
+
 template <int G>
 __device__ __forceinline__ void contract_tile(const float2* __restrict__ S,
                                               const ActiveBeam* __restrict__ act, int n_act,
                                               const float2* __restrict__ alpha, int p_base,
                                               int gcount, int ns, int w, const UnionGeom& U,
                                               int tile, const int* offx, const int* offy, int only,
-                                              float2 (*a_lds)[kCKB + 1], float2 (*s_lds)[kCTile],
+                                              float* __restrict__ smem,
                                               float2* __restrict__ window) {
-  constexpr int RT = G / 8;  // 16-row MFMA tiles covering 2G real rows
+  using CL = ContractLds<G>;
+  constexpr int RT = G / 8;                 // 16-row MFMA tiles covering 2G real rows
+  constexpr int NA = G * kCKB / kCNT;       // alpha values staged per thread
+  constexpr int NSV = kCKB * kCTile / kCNT; // S values staged per thread
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int npix = U.uy * U.ux;
 
   // pixel this thread stages for the S block (fixed across K blocks)
   const int n_ld = tid & (kCTile - 1);
+  // beam row of the S block this wave stages: uniform per wave, so the
+  // plane lookups below become scalar loads
+  const int bl0 = __builtin_amdgcn_readfirstlane(tid / kCTile);
   const int up_ld = tile * kCTile + n_ld;
   long long soff = -1;
   if (up_ld < npix) {
@@ -86,58 +114,80 @@ __device__ __forceinline__ void contract_tile(const float2* __restrict__ S,
   }
   const size_t plane = (size_t)ns * ns;
 
-  floatx4 acc[RT][2];
+  float2 ra[NA], rs[NSV];
+  auto fetch = [&](int kb) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + i * kCNT;
+      const int g = e / kCKB, bl = e % kCKB;
+      ra[i] = (g < gcount && kb + bl < n_act) ? alpha[(size_t)(p_base + g) * n_act + kb + bl]
+                                              : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < NSV; ++i) {
+      const int bl = bl0 + i * (kCNT / kCTile);
+      rs[i] = (soff >= 0 && kb + bl < n_act) ? S[(size_t)act[kb + bl].plane * plane + soff]
+                                             : make_float2(0.f, 0.f);
+    }
+  };
+  // Stage one K block in the real MFMA operand layout:
+  //   A'[2b][2g] = Re a, A'[2b+1][2g] = -Im a, A'[2b][2g+1] = Im a, A'[2b+1][2g+1] = Re a
+  //   B'[2b][n]  = Re S, B'[2b+1][n] = Im S
+  auto stash = [&](int buf) {
+    float* A = smem + buf * CL::ABUF;
+    float* Bm = smem + 2 * CL::ABUF + buf * CL::BBUF;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int e = tid + i * kCNT;
+      const int g = e / kCKB, bl = e % kCKB;
+      *reinterpret_cast<float2*>(A + (2 * bl) * CL::AROW + 2 * g) = ra[i];
+      *reinterpret_cast<float2*>(A + (2 * bl + 1) * CL::AROW + 2 * g) =
+          make_float2(-ra[i].y, ra[i].x);
+    }
+#pragma unroll
+    for (int i = 0; i < NSV; ++i) {
+      const int bl = bl0 + i * (kCNT / kCTile);
+      Bm[(2 * bl) * CL::BROW + n_ld] = rs[i].x;
+      Bm[(2 * bl + 1) * CL::BROW + n_ld] = rs[i].y;
+    }
+  };
+
+  floatx4 acc[RT][kCCT];
 #pragma unroll
   for (int r = 0; r < RT; ++r)
 #pragma unroll
-    for (int c = 0; c < 2; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < kCCT; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  for (int kb = 0; kb < n_act; kb += kCKB) {
-    // alpha block [G][KB]
-#pragma unroll
-    for (int e = tid; e < G * kCKB; e += kCNT) {
-      const int g = e / kCKB, bl = e % kCKB;
-      float2 v = make_float2(0.f, 0.f);
-      if (g < gcount && kb + bl < n_act) v = alpha[(size_t)(p_base + g) * n_act + kb + bl];
-      a_lds[g][bl] = v;
-    }
-    // S block [KB][tile]
-#pragma unroll
-    for (int bl = tid / kCTile; bl < kCKB; bl += kCNT / kCTile) {
-      float2 v = make_float2(0.f, 0.f);
-      if (soff >= 0 && kb + bl < n_act) v = S[(size_t)act[kb + bl].plane * plane + soff];
-      s_lds[bl][n_ld] = v;
-    }
+  const int krow = lane >> 4, mcol = lane & 15;
+  fetch(0);
+  int buf = 0;
+  for (int kb = 0; kb < n_act; kb += kCKB, buf ^= 1) {
+    stash(buf);
     __syncthreads();
+    if (kb + kCKB < n_act) fetch(kb + kCKB);
+    const float* A = smem + buf * CL::ABUF + krow * CL::AROW + mcol;
+    const float* Bm = smem + 2 * CL::ABUF + buf * CL::BBUF + krow * CL::BROW + 16 * kCCT * wv + mcol;
 #pragma unroll
     for (int ks = 0; ks < kCKB / 2; ++ks) {
-      const int bl = 2 * ks + (lane >> 5);
-      const int ck = (lane >> 4) & 1;
-      float bv[2];
+      float bv[kCCT];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const float2 s = s_lds[bl][32 * wv + 16 * c + (lane & 15)];
-        bv[c] = ck ? s.y : s.x;
-      }
+      for (int c = 0; c < kCCT; ++c) bv[c] = Bm[4 * ks * CL::BROW + 16 * c];
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
-        const int g = 8 * r + ((lane & 15) >> 1);
-        const float2 al = a_lds[g][bl];
-        const int cm = lane & 1;
-        const float av = cm ? (ck ? al.x : al.y) : (ck ? -al.y : al.x);
+        const float av = A[4 * ks * CL::AROW + 16 * r];
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < kCCT; ++c)
           acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[c], acc[r][c], 0, 0, 0);
       }
     }
-    __syncthreads();
   }
+  __syncthreads();  // LDS buffers free for a following tile
 
   // epilogue: lane holds rows 4*(lane/16)+i of each 16x16 tile, column lane%16
   const size_t w2 = (size_t)w * w;
 #pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const int up = tile * kCTile + 32 * wv + 16 * c + (lane & 15);
+  for (int c = 0; c < kCCT; ++c) {
+    const int up = tile * kCTile + 16 * kCCT * wv + 16 * c + (lane & 15);
     if (up >= npix) continue;
     const int a = up / U.ux, b = up - a * U.ux;
 #pragma unroll
@@ -161,8 +211,7 @@ __global__ __launch_bounds__(kCNT) void k_contract(const float2* __restrict__ S,
                                                    const float2* __restrict__ alpha,
                                                    const int2* __restrict__ origin, int np, int ns,
                                                    int w, float2* __restrict__ window) {
-  __shared__ float2 a_lds[G][kCKB + 1];
-  __shared__ float2 s_lds[kCKB][kCTile];
+  __shared__ float smem[ContractLds<G>::FLOATS];  // two A' and two B' buffers
   __shared__ int offx[G], offy[G];
   __shared__ int ginfo[6];
   const int tid = threadIdx.x;
@@ -198,8 +247,8 @@ __global__ __launch_bounds__(kCNT) void k_contract(const float2* __restrict__ S,
   if (ginfo[0] == 0) {
     UnionGeom U{ginfo[1], ginfo[2], ginfo[3], ginfo[4]};
     if (tile * kCTile >= U.uy * U.ux) return;
-    contract_tile<G>(S, act, n_act, alpha, p_base, gcount, ns, w, U, tile, offx, offy, -1, a_lds,
-                     s_lds, window);
+    contract_tile<G>(S, act, n_act, alpha, p_base, gcount, ns, w, U, tile, offx, offy, -1, smem,
+                     window);
   } else {
     // windows too far apart to share: one probe at a time, its window alone
     if (tile * kCTile >= w * w) return;
@@ -209,8 +258,8 @@ __global__ __launch_bounds__(kCNT) void k_contract(const float2* __restrict__ S,
     for (int g = 0; g < gcount; ++g) {
       const int2 o = origin[p_base + g];
       UnionGeom U{o.y, o.x, w, w};
-      contract_tile<G>(S, act, n_act, alpha, p_base, gcount, ns, w, U, tile, zero, zero, g, a_lds,
-                       s_lds, window);
+      contract_tile<G>(S, act, n_act, alpha, p_base, gcount, ns, w, U, tile, zero, zero, g, smem,
+                       window);
     }
   }
 }
@@ -219,16 +268,20 @@ __global__ __launch_bounds__(kCNT) void k_contract(const float2* __restrict__ S,
 __host__ __device__ constexpr int wd_nt(int w) { return (w * w / 16) < 64 ? 64 : w * w / 16; }
 
 // One probe per workgroup: 2D FFT of the W x W window in LDS, then
-// I(kw) = |Psi(kw)|^2 / W^2 at full-grid frequency f kw, summed per bin in FP64.
+// I(kw) = |Psi(kw)|^2 / W^2 summed over each bin's pixel list in FP64
+// (the lists encode the angle test at full-grid frequency f kw). The first
+// row stage reads the window straight from HBM.
 template <int W>
 __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __restrict__ window,
-                                                            int f, const float2* __restrict__ twW,
-                                                            DetBins bins,
+                                                            const float2* __restrict__ twW,
+                                                            const uint16_t* __restrict__ pix,
+                                                            BinLists lists,
                                                             double* __restrict__ out) {
   constexpr int NT = wd_nt(W);
   constexpr int NW = NT / 64;
   using Rows = RowBatch<W, W>;
   using Cols = Batch<W, W, W, 0, 1, W, true>;
+  using S8 = StageShape<Rows, 8, NT>;
   __shared__ float2 lds[lds_padded(W * W)];
   __shared__ float2 tw[W];
   __shared__ double red[8][NW];
@@ -236,26 +289,35 @@ __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __rest
   const size_t p = blockIdx.x;
   const float2* src = window + p * W * W;
   load_twiddles<W, NT>(tw, twW, tid);
-  for (int e = tid; e < W * W; e += NT) lds[lpad(e)] = src[e];
+  {
+    float2 v[S8::PER][8];
+#pragma unroll
+    for (int q = 0; q < S8::PER; ++q) {
+      const int b = tid + q * NT;
+      if (!S8::GUARD || b < S8::TOT) {
+        int row, j;
+        stage_coords<Rows, S8::NB>(b, row, j);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[q][r] = src[row * W + j + r * (W / 8)];
+      }
+    }
+    stage_out<Rows, 8, 1, NT, false>(lds, tid, v);
+  }
   __syncthreads();
-  fft_lds<Rows, NT, false>(lds, tw, tid);
+  fft_from<Rows, NT, false, 8>(lds, tw, tid);
   fft_lds<Cols, NT, false>(lds, tw, tid);
   const double inv_w2 = 1.0 / ((double)W * (double)W);
-  const int f2 = f * f;
-  for (int j0 = 0; j0 < bins.n; j0 += 8) {
+  for (int j0 = 0; j0 < lists.n; j0 += 8) {
     double acc[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    for (int e = tid; e < W * W; e += NT) {
-      const int v = e / W, u = e % W;
-      const int ky = v < W / 2 ? v : v - W, kx = u < W / 2 ? u : u - W;
-      const int k2 = f2 * (kx * kx + ky * ky);
-      const float2 z = lds[lpad(e)];
-      const double I = ((double)z.x * z.x + (double)z.y * z.y) * inv_w2;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int j = j0 + q;
-        if (j < bins.n && k2 >= bins.lo[j] && k2 < bins.hi[j]) acc[q] += I;
+    for (int q = 0; q < 8; ++q) {
+      acc[q] = 0.0;
+      const int j = j0 + q;
+      if (j < lists.n) {
+        for (int i = lists.off[j] + tid; i < lists.off[j + 1]; i += NT) {
+          const float2 z = lds[lpad(pix[i])];
+          acc[q] += (double)z.x * z.x + (double)z.y * z.y;
+        }
       }
     }
 #pragma unroll
@@ -264,10 +326,10 @@ __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __rest
       if ((tid & 63) == 0) red[q][tid >> 6] = s;
     }
     __syncthreads();
-    if (tid < 8 && j0 + tid < bins.n) {
+    if (tid < 8 && j0 + tid < lists.n) {
       double s = 0.0;
       for (int wv = 0; wv < NW; ++wv) s += red[tid][wv];
-      out[p * bins.n + j0 + tid] = s;
+      out[p * lists.n + j0 + tid] = s * inv_w2;
     }
     __syncthreads();
   }
@@ -277,7 +339,7 @@ inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 
 
 }  // namespace
 
-int contract_group(int w) { return w >= 128 ? 64 : (w >= 64 ? 32 : 16); }
+int contract_group(int w) { return w >= 128 ? PRISM_CG128 : (w >= 64 ? 32 : 16); }
 
 hipError_t launch_alpha(const double* probe_xy, int p0, int np, const ActiveBeam* act, int n_act,
                         int f, int ns, int w, const ProbeOptics& po, float2* alpha,
@@ -314,12 +376,13 @@ hipError_t launch_contract(const float2* smatrix, const ActiveBeam* act, int n_a
   return hipGetLastError();
 }
 
-hipError_t launch_window_detect(const float2* window, int np, int w, int f, const float2* twW,
-                                const DetBins& bins, double* out, hipStream_t st) {
+hipError_t launch_window_detect(const float2* window, int np, int w, const float2* twW,
+                                const uint16_t* pix, const BinLists& lists, double* out,
+                                hipStream_t st) {
 #define WD(WW)                                                                                   \
   case WW:                                                                                       \
-    hipLaunchKernelGGL(k_window_detect<WW>, dim3((unsigned)np), dim3(wd_nt(WW)), 0, st, window, f, \
-                       twW, bins, out);                                                          \
+    hipLaunchKernelGGL(k_window_detect<WW>, dim3((unsigned)np), dim3(wd_nt(WW)), 0, st, window,   \
+                       twW, pix, lists, out);                                                    \
     break;
   switch (w) {
     WD(8)
