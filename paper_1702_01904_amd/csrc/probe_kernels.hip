@@ -27,14 +27,16 @@ __device__ __forceinline__ int wrap_mod(long long v, int m) {
   return (int)(r < 0 ? r + m : r);
 }
 
-// One thread per (probe, active beam); also writes each probe's window
-// origin (first S pixel of the cut-out, periodic).
+// One thread per (active beam, probe); alpha is stored beam-major
+// [n_act][np] so that a probe group's coefficients for one beam are
+// contiguous. Also writes each probe's window origin (first S pixel of the
+// cut-out, periodic).
 __global__ void k_alpha(const double* __restrict__ probe_xy, int p0, int np,
                         const ActiveBeam* __restrict__ act, int n_act, int f, int ns, int w,
                         ProbeOptics po, float2* __restrict__ alpha, int2* __restrict__ origin) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (size_t)np * n_act) return;
-  const int p = (int)(i / n_act), a = (int)(i % n_act);
+  const int a = (int)(i / np), p = (int)(i % np);
   const double x0 = probe_xy[2 * (size_t)(p0 + p)], y0 = probe_xy[2 * (size_t)(p0 + p) + 1];
   if (a == 0) {
     const double dxs = po.cell / (double)ns;
@@ -89,8 +91,9 @@ struct ContractLds {
 template <int G>
 __device__ __forceinline__ void contract_tile(const float2* __restrict__ S,
                                               const ActiveBeam* __restrict__ act, int n_act,
-                                              const float2* __restrict__ alpha, int p_base,
-                                              int gcount, int ns, int w, const UnionGeom& U,
+                                              const float2* __restrict__ alpha, int np,
+                                              int p_base, int gcount, int ns, int w,
+                                              const UnionGeom& U,
                                               int tile, const int* offx, const int* offy, int only,
                                               float* __restrict__ smem,
                                               float2* __restrict__ window) {
@@ -114,41 +117,48 @@ __device__ __forceinline__ void contract_tile(const float2* __restrict__ S,
   }
   const size_t plane = (size_t)ns * ns;
 
-  float2 ra[NA], rs[NSV];
-  auto fetch = [&](int kb) {
+  // Two register sets: the block after next is in flight while a block is
+  // computed. Loads are issued unconditionally from clamped (in-bounds)
+  // indices and out-of-range entries are zeroed when staged, so the number
+  // of loads in flight is the same on every path and each wait covers only
+  // the older set.
+  float2 ra[2][NA], rs[2][NSV];
+  const long long soff_c = soff < 0 ? 0 : soff;
+  auto fetch = [&](int set, int kb) {
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int e = tid + i * kCNT;
-      const int g = e / kCKB, bl = e % kCKB;
-      ra[i] = (g < gcount && kb + bl < n_act) ? alpha[(size_t)(p_base + g) * n_act + kb + bl]
-                                              : make_float2(0.f, 0.f);
+      const int g = e % G, bl = e / G;
+      const int b = min(kb + bl, n_act - 1), pidx = min(p_base + g, np - 1);
+      ra[set][i] = alpha[(size_t)b * np + pidx];
     }
 #pragma unroll
     for (int i = 0; i < NSV; ++i) {
       const int bl = bl0 + i * (kCNT / kCTile);
-      rs[i] = (soff >= 0 && kb + bl < n_act) ? S[(size_t)act[kb + bl].plane * plane + soff]
-                                             : make_float2(0.f, 0.f);
+      rs[set][i] = S[(size_t)act[min(kb + bl, n_act - 1)].plane * plane + soff_c];
     }
   };
   // Stage one K block in the real MFMA operand layout:
   //   A'[2b][2g] = Re a, A'[2b+1][2g] = -Im a, A'[2b][2g+1] = Im a, A'[2b+1][2g+1] = Re a
   //   B'[2b][n]  = Re S, B'[2b+1][n] = Im S
-  auto stash = [&](int buf) {
-    float* A = smem + buf * CL::ABUF;
-    float* Bm = smem + 2 * CL::ABUF + buf * CL::BBUF;
+  auto stash = [&](int set, int kb) {  // register set s goes to LDS buffer s
+    float* A = smem + set * CL::ABUF;
+    float* Bm = smem + 2 * CL::ABUF + set * CL::BBUF;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int e = tid + i * kCNT;
-      const int g = e / kCKB, bl = e % kCKB;
-      *reinterpret_cast<float2*>(A + (2 * bl) * CL::AROW + 2 * g) = ra[i];
-      *reinterpret_cast<float2*>(A + (2 * bl + 1) * CL::AROW + 2 * g) =
-          make_float2(-ra[i].y, ra[i].x);
+      const int g = e % G, bl = e / G;
+      const bool ok = g < gcount && kb + bl < n_act;
+      const float2 a = ok ? ra[set][i] : make_float2(0.f, 0.f);
+      *reinterpret_cast<float2*>(A + (2 * bl) * CL::AROW + 2 * g) = a;
+      *reinterpret_cast<float2*>(A + (2 * bl + 1) * CL::AROW + 2 * g) = make_float2(-a.y, a.x);
     }
 #pragma unroll
     for (int i = 0; i < NSV; ++i) {
       const int bl = bl0 + i * (kCNT / kCTile);
-      Bm[(2 * bl) * CL::BROW + n_ld] = rs[i].x;
-      Bm[(2 * bl + 1) * CL::BROW + n_ld] = rs[i].y;
+      const bool ok = soff >= 0 && kb + bl < n_act;
+      Bm[(2 * bl) * CL::BROW + n_ld] = ok ? rs[set][i].x : 0.f;
+      Bm[(2 * bl + 1) * CL::BROW + n_ld] = ok ? rs[set][i].y : 0.f;
     }
   };
 
@@ -159,27 +169,49 @@ __device__ __forceinline__ void contract_tile(const float2* __restrict__ S,
     for (int c = 0; c < kCCT; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   const int krow = lane >> 4, mcol = lane & 15;
-  fetch(0);
-  int buf = 0;
-  for (int kb = 0; kb < n_act; kb += kCKB, buf ^= 1) {
-    stash(buf);
-    __syncthreads();
-    if (kb + kCKB < n_act) fetch(kb + kCKB);
+  auto compute = [&](int buf) {
     const float* A = smem + buf * CL::ABUF + krow * CL::AROW + mcol;
-    const float* Bm = smem + 2 * CL::ABUF + buf * CL::BBUF + krow * CL::BROW + 16 * kCCT * wv + mcol;
+    const float* Bm =
+        smem + 2 * CL::ABUF + buf * CL::BBUF + krow * CL::BROW + 16 * kCCT * wv + mcol;
+    // operands of K step ks+1 are read while the MFMAs of step ks run
+    float av[2][RT], bv[2][kCCT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) av[0][r] = A[16 * r];
+#pragma unroll
+    for (int c = 0; c < kCCT; ++c) bv[0][c] = Bm[16 * c];
 #pragma unroll
     for (int ks = 0; ks < kCKB / 2; ++ks) {
-      float bv[kCCT];
+      const int cur = ks & 1, nxt = cur ^ 1;
+      if (ks + 1 < kCKB / 2) {
 #pragma unroll
-      for (int c = 0; c < kCCT; ++c) bv[c] = Bm[4 * ks * CL::BROW + 16 * c];
+        for (int r = 0; r < RT; ++r) av[nxt][r] = A[4 * (ks + 1) * CL::AROW + 16 * r];
 #pragma unroll
-      for (int r = 0; r < RT; ++r) {
-        const float av = A[4 * ks * CL::AROW + 16 * r];
+        for (int c = 0; c < kCCT; ++c) bv[nxt][c] = Bm[4 * (ks + 1) * CL::BROW + 16 * c];
+      }
+      __builtin_amdgcn_sched_barrier(0);  // keep those reads ahead of this step's MFMAs
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
 #pragma unroll
         for (int c = 0; c < kCCT; ++c)
-          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[c], acc[r][c], 0, 0, 0);
-      }
+          acc[r][c] =
+              __builtin_amdgcn_mfma_f32_16x16x4f32(av[cur][r], bv[cur][c], acc[r][c], 0, 0, 0);
     }
+  };
+  // K blocks alternate between register set / LDS buffer 0 and 1, in pairs;
+  // an odd last block is paired with a zero-weight block.
+  const int npair = (n_act + 2 * kCKB - 1) / (2 * kCKB);
+  fetch(0, 0);
+  fetch(1, kCKB);
+  for (int pr = 0; pr < npair; ++pr) {
+    const int kb = 2 * kCKB * pr;
+    stash(0, kb);
+    __syncthreads();
+    fetch(0, kb + 2 * kCKB);
+    compute(0);
+    stash(1, kb + kCKB);
+    __syncthreads();
+    fetch(1, kb + 3 * kCKB);
+    compute(1);
   }
   __syncthreads();  // LDS buffers free for a following tile
 
@@ -206,7 +238,7 @@ __device__ __forceinline__ void contract_tile(const float2* __restrict__ S,
 }
 
 template <int G>
-__global__ __launch_bounds__(kCNT) void k_contract(const float2* __restrict__ S,
+__global__ __launch_bounds__(kCNT) __attribute__((amdgpu_waves_per_eu(2))) void k_contract(const float2* __restrict__ S,
                                                    const ActiveBeam* __restrict__ act, int n_act,
                                                    const float2* __restrict__ alpha,
                                                    const int2* __restrict__ origin, int np, int ns,
@@ -247,8 +279,8 @@ __global__ __launch_bounds__(kCNT) void k_contract(const float2* __restrict__ S,
   if (ginfo[0] == 0) {
     UnionGeom U{ginfo[1], ginfo[2], ginfo[3], ginfo[4]};
     if (tile * kCTile >= U.uy * U.ux) return;
-    contract_tile<G>(S, act, n_act, alpha, p_base, gcount, ns, w, U, tile, offx, offy, -1, smem,
-                     window);
+    contract_tile<G>(S, act, n_act, alpha, np, p_base, gcount, ns, w, U, tile, offx, offy, -1,
+                     smem, window);
   } else {
     // windows too far apart to share: one probe at a time, its window alone
     if (tile * kCTile >= w * w) return;
@@ -258,8 +290,8 @@ __global__ __launch_bounds__(kCNT) void k_contract(const float2* __restrict__ S,
     for (int g = 0; g < gcount; ++g) {
       const int2 o = origin[p_base + g];
       UnionGeom U{o.y, o.x, w, w};
-      contract_tile<G>(S, act, n_act, alpha, p_base, gcount, ns, w, U, tile, zero, zero, g, smem,
-                       window);
+      contract_tile<G>(S, act, n_act, alpha, np, p_base, gcount, ns, w, U, tile, zero, zero, g,
+                       smem, window);
     }
   }
 }
