@@ -31,7 +31,23 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
+F16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 / FP16 matrix
 CONFIG = "fcc1024"
+
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE on this
+# workload (f = 4), calibrated with a 256 MiB device copy (fetch x2.0,
+# write x1.0); see profiles/fcc1024_prism_f4_hbm_traffic.md. Valid only for
+# the kernel sources with this hash; reported as null otherwise.
+TRAFFIC_SRC_SHA = "3828e37b5fedfc69"
+TRAFFIC_BYTES = {"row_pass": 530019928, "col_pass": 525991183, "contract": 1754190034,
+                 "window_detect": 270041376}
+
+
+def kernel_source_sha():
+    import glob
+    import hashlib
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1702_01904_amd", "csrc", "*")))
+    return hashlib.sha256("".join(open(p).read() for p in files).encode()).hexdigest()[:16]
 
 
 def parse():
@@ -42,8 +58,12 @@ def parse():
     ap.add_argument("--f", type=int, default=4, help="interpolation factor of the headline run")
     ap.add_argument("--other-f", default="8,16", help="extra f values timed (comma list, '' none)")
     ap.add_argument("--ms-probes", type=int, default=128, help="multislice probes timed")
+    ap.add_argument("--precisions", default="bf16,fp16",
+                    help="16-bit window-sum variants timed at the headline f ('' none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="first run a plain 256 MiB device copy (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -67,7 +87,7 @@ def kernel_work(name, g):
         return "hbm", B * (state / 2 + 2.0 * N * N)
     if name == "beam_init":
         return "hbm", B * state
-    if name == "contract":
+    if name in ("contract", "contract16"):
         return "mfma", 8.0 * BA * W * W * P
     if name == "window_detect":
         return "hbm", 8.0 * W * W * P + 8.0 * P * g["n_det"]
@@ -76,9 +96,10 @@ def kernel_work(name, g):
     return None, 0.0
 
 
-def roofline(prof, g, steps):
-    """Roofline entry for the kernel with the largest total time."""
-    name = max(prof, key=lambda k: prof[k]["total_ms"])
+def roofline(prof, g, steps, name=None):
+    """Roofline entry for ``name`` (default: the kernel with the largest total time)."""
+    if name is None:
+        name = max(prof, key=lambda k: prof[k]["total_ms"])
     ent = dict(prof[name])
     launches = ent["launches"] / steps
     g = dict(g, launches=launches)
@@ -87,13 +108,17 @@ def roofline(prof, g, steps):
     per_launch_units = amount / launches
     if kind == "mfma":
         achieved = per_launch_units / (per_launch_ms * 1e-3) / 1e12
-        peak, unit = FP32_MFMA_PEAK_TFLOPS, "TFLOP/s"
+        peak = F16_MFMA_PEAK_TFLOPS if name.endswith("16") else FP32_MFMA_PEAK_TFLOPS
+        unit = "TFLOP/s"
     else:
         achieved = per_launch_units / (per_launch_ms * 1e-3) / 1e9
         peak, unit = HBM_PEAK_GBS, "GB/s"
+    traffic = None
+    if name in TRAFFIC_BYTES and kernel_source_sha() == TRAFFIC_SRC_SHA:
+        traffic = TRAFFIC_BYTES[name]
     return name, {
         "bound": kind, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
-        "frac": round(achieved / peak, 4), "traffic": None,
+        "frac": round(achieved / peak, 4), "traffic": traffic,
         "kernel": name, "launches_per_step": launches,
         "avg_launch_ms": round(per_launch_ms, 4),
         "algorithmic_per_launch": per_launch_units,
@@ -147,6 +172,14 @@ def main():
     from paper_1702_01904_amd import Plan, tile_order, untile
 
     dev = torch.device("cuda:0")
+    if args.calibration_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 256 MiB read + 256 MiB written")
+        del src, dst
     t_setup = time.perf_counter()
     d = build_inputs(CONFIG, args.seed)
     N, H, P = d["n"], d["phase"].shape[0], len(d["probes"])
@@ -209,6 +242,21 @@ def main():
     finite = bool(np.all(np.isfinite(out_main)))
     del main_c
 
+    # 16-bit window sums at the headline f (tolerance eps_rel <= 1e-2)
+    variants = {}
+    for prec in [x.strip() for x in args.precisions.split(",") if x.strip()]:
+        plan.set_probe_precision(prec)
+        c = setup_f(args.f)
+        msv, pv = timed(c, args.steps, 1, True)
+        _, rv = roofline(pv, geo, args.steps, "contract16")
+        variants[prec] = {"ms_per_step": round(msv, 3), "probes_per_s": round(P / (msv * 1e-3), 1),
+                          "kernel_ms_per_step": {k: round(v["total_ms"] / args.steps, 3)
+                                                 for k, v in pv.items()},
+                          "contract16_roofline": rv,
+                          "tolerance": "eps_rel <= 1e-2 vs FP64 oracle"}
+        plan.set_probe_precision("fp32")
+        del c
+
     per_f = {}
     for f in [int(x) for x in args.other_f.split(",") if x.strip()]:
         c = setup_f(f)
@@ -262,6 +310,7 @@ def main():
         "multislice_probes_per_s": round(multi_rate, 2),
         "speedup_vs_gpu_multislice": round(value / multi_rate, 2),
         "per_f": per_f,
+        "precision_variants": variants,
         "kernel_ms_per_step": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,

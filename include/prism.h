@@ -42,6 +42,11 @@ extern "C" {
 
 #define PRISM_MAX_DET 32
 
+/* Operand precision of the PRISM window sum (Eq. PRISMfinal). */
+#define PRISM_PREC_FP32 0 /* FP32 operands, FP32 accumulation (default)        */
+#define PRISM_PREC_BF16 1 /* bfloat16 S-matrix and coefficients, FP32 accumulation */
+#define PRISM_PREC_FP16 2 /* float16 S-matrix and coefficients, FP32 accumulation  */
+
 typedef struct prism_plan prism_plan; /* opaque, host-side state only */
 
 /* Sampling of the specimen (Fig. 1a-b: slices and their projected
@@ -107,6 +112,18 @@ int prism_probe_workspace_bytes(const prism_plan* plan, int f, double alpha_max_
  * should be adjacent in the probe list: a tile shares one union window, so
  * scattered tiles cost more but still give the same results. */
 int prism_probe_group(const prism_plan* plan, int f, int* group, int* tile_x, int* tile_y);
+
+/* Select the operand precision of prism_probe_outputs for this plan
+ * (PRISM_PREC_*; PRISM_EINVAL otherwise). With BF16/FP16 each call first
+ * packs the active beams of the S-matrix into a pixel-major 16-bit copy in
+ * the workspace (each beam scaled by an exact power of two so that its
+ * largest component is below 1, the coefficient divided by the same factor)
+ * and runs the window sum on 16-bit matrix cores with FP32 accumulation;
+ * everything after the window sum stays FP32/FP64. The workspace sizes
+ * returned by prism_probe_workspace_bytes follow the plan's precision, so
+ * query them after this call. Setting the precision is not stream-ordered:
+ * do it between calls. */
+int prism_set_probe_precision(prism_plan* plan, int precision);
 
 /* Record the projected phase sigma V_p of every slice (Eq. 4): device
  * float32 [n_slices][n][n], radians. The pointer is BORROWED: it must stay

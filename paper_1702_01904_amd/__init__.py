@@ -152,6 +152,15 @@ class Plan:
                              max_ms=float(mx))
         return out
 
+    PRECISIONS = {"fp32": _native.PRISM_PREC_FP32, "bf16": _native.PRISM_PREC_BF16,
+                  "fp16": _native.PRISM_PREC_FP16}
+
+    def set_probe_precision(self, precision):
+        """Operand precision of the probe-step window sum: "fp32", "bf16" or "fp16"."""
+        if precision not in self.PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(self.PRECISIONS)}")
+        _native.check(self._L.prism_set_probe_precision(self._h, self.PRECISIONS[precision]))
+
     # ------------------------------------------------------------ device calls
     def set_potential_slices(self, phase):
         """phase: float32 device tensor [H][n][n] (radians); borrowed, kept referenced."""

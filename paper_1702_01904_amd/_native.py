@@ -15,12 +15,15 @@ PRISM_ENOSPACE = -2
 PRISM_EHIP = -3
 PRISM_ENOTREADY = -4
 PRISM_MAX_DET = 32
+PRISM_PREC_FP32 = 0
+PRISM_PREC_BF16 = 1
+PRISM_PREC_FP16 = 2
 
 EXPORTS = (
     "prism_plan_create", "prism_plan_destroy", "prism_wavelength", "prism_beam_count",
     "prism_beams", "prism_smatrix_bytes", "prism_build_workspace_bytes",
     "prism_multislice_workspace_bytes", "prism_probe_workspace_bytes", "prism_probe_group",
-    "prism_set_potential_slices", "prism_build_smatrix", "prism_probe_outputs",
+    "prism_set_probe_precision", "prism_set_potential_slices", "prism_build_smatrix", "prism_probe_outputs",
     "prism_multislice_outputs", "prism_profile_enable", "prism_profile_report",
     "prism_last_error",
 )
@@ -77,6 +80,7 @@ def lib():
         "prism_multislice_workspace_bytes": (I, [P, I, SZ, SZ]),
         "prism_probe_workspace_bytes": (I, [P, I, D, ctypes.POINTER(PrismOptics), SZ, SZ]),
         "prism_probe_group": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "prism_set_probe_precision": (I, [P, I]),
         "prism_set_potential_slices": (I, [P, P]),
         "prism_build_smatrix": (I, [P, I, D, P, P, ctypes.c_size_t, P]),
         "prism_probe_outputs": (I, [P, I, D, P, P, I, ctypes.POINTER(PrismOptics),

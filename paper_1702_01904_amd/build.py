@@ -21,7 +21,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INC}", f"-I{SRC}", "-Wall", "-Wno-u
 # device code: gfx950 only, packed FP32 instructions disabled
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
-SOURCES = ["slice_kernels.hip", "probe_kernels.hip", "plan.cpp"]
+SOURCES = ["slice_kernels.hip", "probe_kernels.hip", "probe16_kernels.hip", "plan.cpp"]
 
 
 def _cmd(src, obj):

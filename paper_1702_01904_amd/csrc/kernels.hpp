@@ -78,6 +78,28 @@ hipError_t launch_contract(const float2* smatrix, const ActiveBeam* act, int n_a
                            const float2* alpha, const int2* origin, int np, int ns, int w,
                            int group, float2* window, hipStream_t st);
 int contract_group(int w);
+
+// Low-precision probe step (BF16 or FP16 operands, FP32 accumulation).
+enum class Prec { kBF16 = 1, kFP16 = 2 };
+constexpr int kC16KB = 32;  // beams per K block of the 16-bit contraction
+// Beam rows of the packed 16-bit S-matrix are padded to a multiple of this.
+constexpr int kC16BeamPad = 2 * kC16KB;
+// scale[a] = 2^-e with e the smallest integer such that every |Re|, |Im| of
+// active beam a's plane is < 2^e (1 for an all-zero plane).
+hipError_t launch_s16_scale(const float2* smatrix, const ActiveBeam* act, int n_act, int ns,
+                            float* scale, hipStream_t st);
+// s16 [ns*ns][n_actp][2] 16-bit: (Re, Im) of scale[a] * S_a(pixel); zero for a >= n_act.
+hipError_t launch_s16_pack(const float2* smatrix, const ActiveBeam* act, int n_act, int n_actp,
+                           int ns, const float* scale, void* s16, Prec prec, hipStream_t st);
+// a16: per probe group and 32-beam block, the real-ified A' block [2G][64] in
+// 16 bits of alpha'' = exp(i phase) / scale[a]; also the window origins.
+hipError_t launch_alpha16(const double* probe_xy, int p0, int np, const ActiveBeam* act,
+                          int n_act, int n_actp, int f, int ns, int w, const ProbeOptics& po,
+                          const float* scale, int group, void* a16, int2* origin, Prec prec,
+                          hipStream_t st);
+hipError_t launch_contract16(const void* s16, int n_actp, const void* a16, const int2* origin,
+                             int np, int ns, int w, int group, float out_scale, float2* window,
+                             Prec prec, hipStream_t st);
 // Detector bins as lists of window pixels: bin j holds the pixel indices
 // pix[off[j] .. off[j+1]) (v * W + u) of the W x W window.
 struct BinLists {

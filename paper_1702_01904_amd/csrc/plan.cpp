@@ -90,6 +90,7 @@ struct prism_plan {
   }
 
   int n = 0;
+  int prec = PRISM_PREC_FP32;  // operand precision of the probe-step window sum
   double cell = 0, energy = 0, lam = 0, dq = 0;
   int H = 0;
   std::vector<double> thick;
@@ -300,17 +301,35 @@ struct ProbeWs {
   float2* twW;
   uint16_t* pix;
   prism::ActiveBeam* act;
-  float2* alpha;
+  float2* alpha;    // FP32: [n_act][chunk]
+  float* scale;     // 16-bit: [n_act] power-of-two beam scales
+  uint32_t* s16;    // 16-bit: [ns^2][n_actp] (re, im) pairs
+  uint32_t* a16;    // 16-bit: [chunk / G][n_actp / 32][2G][32] (pairs)
   int2* origin;
   float2* window;
 };
 
-size_t probe_layout(int w, int n_act, int chunk, ProbeWs* pw, void* base) {
+// Active beams padded to whole pairs of 16-bit K blocks.
+int padded_beams(int n_act) {
+  return (n_act + prism::kC16BeamPad - 1) / prism::kC16BeamPad * prism::kC16BeamPad;
+}
+
+size_t probe_layout(int w, int ns, int n_act, int chunk, int prec, ProbeWs* pw, void* base) {
   Carve c(base);
   pw->twW = c.take<float2>(w);
   pw->pix = c.take<uint16_t>((size_t)PRISM_MAX_DET * w * w);  // worst case: overlapping bins
   pw->act = c.take<prism::ActiveBeam>(n_act);
-  pw->alpha = c.take<float2>((size_t)chunk * n_act);
+  if (prec == PRISM_PREC_FP32) {
+    pw->alpha = c.take<float2>((size_t)chunk * n_act);
+    pw->scale = nullptr;
+    pw->s16 = pw->a16 = nullptr;
+  } else {
+    const int n_actp = padded_beams(n_act);
+    pw->alpha = nullptr;
+    pw->scale = c.take<float>(n_act);
+    pw->s16 = c.take<uint32_t>((size_t)ns * ns * n_actp);
+    pw->a16 = c.take<uint32_t>((size_t)chunk * n_actp * 2);
+  }
   pw->origin = c.take<int2>(chunk);
   pw->window = c.take<float2>((size_t)chunk * w * w);
   return c.used + 256;
@@ -474,8 +493,9 @@ int prism_probe_workspace_bytes(const prism_plan* cp, int f, double amax_mrad,
   const auto* act = get_active(p, f, amax_mrad, *mn, o->alpha_mrad);
   const int G = prism::contract_group(w);
   ProbeWs pw;
-  *pref = probe_layout(w, (int)act->size(), pref_probe_chunk(w, G), &pw, nullptr);
-  *minimum = probe_layout(w, (int)act->size(), G, &pw, nullptr);
+  const int ns = p->n / 2;
+  *pref = probe_layout(w, ns, (int)act->size(), pref_probe_chunk(w, G), p->prec, &pw, nullptr);
+  *minimum = probe_layout(w, ns, (int)act->size(), G, p->prec, &pw, nullptr);
   return PRISM_OK;
 }
 
@@ -517,6 +537,14 @@ int prism_profile_report(prism_plan* p, char* buf, size_t len) {
   if (text.size() + 1 > len) return fail(PRISM_ENOSPACE, "profile report buffer too small");
   std::memcpy(buf, text.c_str(), text.size() + 1);
   return status;
+}
+
+int prism_set_probe_precision(prism_plan* p, int precision) {
+  if (!p) return fail(PRISM_EINVAL, "null plan");
+  if (precision != PRISM_PREC_FP32 && precision != PRISM_PREC_BF16 && precision != PRISM_PREC_FP16)
+    return fail(PRISM_EINVAL, "precision must be PRISM_PREC_FP32, _BF16 or _FP16");
+  p->prec = precision;
+  return PRISM_OK;
 }
 
 int prism_set_potential_slices(prism_plan* p, const float* phase_dev) {
@@ -616,10 +644,11 @@ int prism_probe_outputs(prism_plan* p, int f, double amax_mrad, const void* S, c
   const size_t avail = ws_bytes;  // layouts include 256 B of alignment slack
   ProbeWs pw;
   int chunk = std::min(pref_probe_chunk(w, G), (P + G - 1) / G * G);
-  while (chunk >= G && probe_layout(w, n_act, chunk, &pw, nullptr) > avail)
+  const int prec = p->prec;
+  while (chunk >= G && probe_layout(w, ns, n_act, chunk, prec, &pw, nullptr) > avail)
     chunk = chunk > 8 * G ? (chunk * 3 / 4) / G * G : chunk - G;
   if (chunk < G) return fail(PRISM_ENOSPACE, "workspace smaller than the probe-step minimum");
-  probe_layout(w, n_act, chunk, &pw, base);
+  probe_layout(w, ns, n_act, chunk, prec, &pw, base);
   hipStream_t st = static_cast<hipStream_t>(stream);
   LAUNCH(p, st, "twiddles", prism::launch_twiddles(pw.twW, w, st));
   const auto* pl = get_pixlists(p, w, f, bins);
@@ -633,6 +662,27 @@ int prism_probe_outputs(prism_plan* p, int f, double amax_mrad, const void* S, c
   prism::ProbeOptics po = probe_optics(p, o);
   po.norm = 1.0 / ((double)w * std::sqrt((double)n_act));
   const float2* Sd = static_cast<const float2*>(S);
+  if (prec != PRISM_PREC_FP32) {
+    const prism::Prec pr = prec == PRISM_PREC_BF16 ? prism::Prec::kBF16 : prism::Prec::kFP16;
+    const int n_actp = padded_beams(n_act);
+    const float out_scale = (float)po.norm;
+    po.norm = 1.0;
+    LAUNCH(p, st, "s16_scale", prism::launch_s16_scale(Sd, pw.act, n_act, ns, pw.scale, st));
+    LAUNCH(p, st, "s16_pack", prism::launch_s16_pack(Sd, pw.act, n_act, n_actp, ns, pw.scale, pw.s16, pr, st));
+    for (int p0 = 0; p0 < P; p0 += chunk) {
+      const int np = std::min(chunk, P - p0);
+      LAUNCH(p, st, "alpha16",
+             prism::launch_alpha16(xy, p0, np, pw.act, n_act, n_actp, f, ns, w, po, pw.scale, G,
+                                   pw.a16, pw.origin, pr, st));
+      LAUNCH(p, st, "contract16",
+             prism::launch_contract16(pw.s16, n_actp, pw.a16, pw.origin, np, ns, w, G, out_scale,
+                                      pw.window, pr, st));
+      LAUNCH(p, st, "window_detect",
+             prism::launch_window_detect(pw.window, np, w, pw.twW, pw.pix, pl->lists,
+                                         out + (size_t)p0 * bins.n, st));
+    }
+    return PRISM_OK;
+  }
   for (int p0 = 0; p0 < P; p0 += chunk) {
     const int np = std::min(chunk, P - p0);
     LAUNCH(p, st, "alpha", prism::launch_alpha(xy, p0, np, pw.act, n_act, f, ns, w, po, pw.alpha, pw.origin, st));

@@ -1,0 +1,420 @@
+// PRISM probe step with 16-bit (BF16 or FP16) MFMA operands and FP32
+// accumulation: the same window sum as probe_kernels.hip (Eq. PRISMfinal
+// over the window of Eq. RegionBounds), for callers that accept the
+// rounding of the operands to 16 bits.
+//
+//  * Every active beam plane S_a is multiplied by an exact power of two
+//    scale[a] that brings its largest component below 1, and alpha_a is
+//    divided by the same factor, so the product is unchanged in exact
+//    arithmetic and FP16 stays in range.
+//  * S is packed once per call into a pixel-major 16-bit copy
+//    s16[pixel][beam] = (Re, Im), beam rows padded to 64 entries, so that
+//    one 32-beam K block of a pixel is 128 contiguous bytes.
+//  * alpha is written by k_alpha16 directly in the real-ified MFMA A layout
+//    (rows 2g: (Re, -Im), rows 2g+1: (Im, Re)) per probe group and K block.
+//  * v_mfma_f32_16x16x32_{bf16,f16}: lane l holds A[l%16][8(l/16)+j],
+//    B[8(l/16)+j][l%16] (j < 8) and D[4(l/16)+i][l%16] (i < 4).
+//  * The 1 / (W sqrt(B_A)) normalisation is applied in FP32 at the end.
+#include "fft_lds.hpp"
+#include "kernels.hpp"
+
+namespace prism {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int wrap_mod16(long long v, int m) {
+  long long r = v % m;
+  return (int)(r < 0 ? r + m : r);
+}
+
+template <Prec P>
+__device__ __forceinline__ uint32_t pack16(float lo, float hi) {
+  uint16_t a, b;
+  if constexpr (P == Prec::kBF16) {
+    a = __builtin_bit_cast(uint16_t, (__bf16)lo);
+    b = __builtin_bit_cast(uint16_t, (__bf16)hi);
+  } else {
+    a = __builtin_bit_cast(uint16_t, (_Float16)lo);
+    b = __builtin_bit_cast(uint16_t, (_Float16)hi);
+  }
+  return (uint32_t)a | ((uint32_t)b << 16);
+}
+
+template <Prec P>
+__device__ __forceinline__ floatx4 mfma16(u32x4 a, u32x4 b, floatx4 c) {
+  if constexpr (P == Prec::kBF16) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  } else {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(halfx8, a),
+                                                  __builtin_bit_cast(halfx8, b), c, 0, 0, 0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_s16_scale(const float2* __restrict__ S,
+                                                   const ActiveBeam* __restrict__ act, int ns,
+                                                   float* __restrict__ scale) {
+  const int a = blockIdx.x, tid = threadIdx.x;
+  const float2* pl = S + (size_t)act[a].plane * ns * ns;
+  float m = 0.f;
+  for (size_t i = tid; i < (size_t)ns * ns; i += 256) {
+    const float2 v = pl[i];
+    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  __shared__ float red[4];
+  if ((tid & 63) == 0) red[tid >> 6] = m;
+  __syncthreads();
+  if (tid == 0) {
+    const float mm = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    float sc = 1.f;
+    if (mm > 0.f) {
+      int e;
+      frexpf(mm, &e);  // mm = fr * 2^e with fr in [0.5, 1), so mm < 2^e
+      sc = ldexpf(1.f, -e);
+    }
+    scale[a] = sc;
+  }
+}
+
+// 32 beams x 64 pixels per workgroup, transposed through LDS.
+template <Prec P>
+__global__ __launch_bounds__(256) void k_s16_pack(const float2* __restrict__ S,
+                                                  const ActiveBeam* __restrict__ act, int n_act,
+                                                  int n_actp, int ns, const float* __restrict__ scale,
+                                                  uint32_t* __restrict__ s16) {
+  __shared__ uint32_t tile[64][33];
+  const int tid = threadIdx.x;
+  const size_t pix0 = (size_t)blockIdx.x * 64;
+  const int a0 = blockIdx.y * 32;
+  const size_t npix = (size_t)ns * ns;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int idx = tid + 256 * i;
+    const int j = idx / 64, px = idx % 64;
+    const int a = a0 + j;
+    uint32_t v = 0u;
+    if (a < n_act) {
+      const float2 z = S[(size_t)act[a].plane * npix + pix0 + px];
+      const float sc = scale[a];
+      v = pack16<P>(z.x * sc, z.y * sc);
+    }
+    tile[px][j] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int idx = tid + 256 * i;
+    const int px = idx / 32, j = idx % 32;
+    s16[(pix0 + px) * n_actp + a0 + j] = tile[px][j];
+  }
+}
+
+// One thread per (probe group, K block, probe g, beam bl): the A' entries of
+// alpha'' = exp(i phase) / scale[a], zero outside the probe / beam range.
+template <Prec P>
+__global__ void k_alpha16(const double* __restrict__ probe_xy, int p0, int np,
+                          const ActiveBeam* __restrict__ act, int n_act, int f, int ns, int w,
+                          ProbeOptics po, const float* __restrict__ scale, int group, int nblk,
+                          size_t total, uint32_t* __restrict__ a16, int2* __restrict__ origin) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int bl = (int)(i % kC16KB);
+  const int g = (int)((i / kC16KB) % group);
+  const int blk = (int)((i / ((size_t)kC16KB * group)) % nblk);
+  const size_t grp = i / ((size_t)kC16KB * group * nblk);
+  const size_t p = grp * group + g;
+  const int a = blk * kC16KB + bl;
+  uint32_t row_re = 0u, row_im = 0u;
+  if (p < (size_t)np && a < n_act) {
+    const double x0 = probe_xy[2 * (p0 + p)], y0 = probe_xy[2 * (p0 + p) + 1];
+    if (a == 0) {
+      const double dxs = po.cell / (double)ns;
+      const int cx = wrap_mod16((long long)floor(x0 / dxs + 0.5), ns);
+      const int cy = wrap_mod16((long long)floor(y0 / dxs + 0.5), ns);
+      origin[p] = make_int2(wrap_mod16((long long)cx - w / 2, ns),
+                            wrap_mod16((long long)cy - w / 2, ns));
+    }
+    const double kx = (double)act[a].m * f, ky = (double)act[a].n * f;
+    const double q2 = (kx * kx + ky * ky) * (po.dq * po.dq);
+    double t = -(0.5 * po.lam * q2 * po.C1 + 0.25 * po.lam * po.lam * po.lam * q2 * q2 * po.C3) -
+               (kx * x0 + ky * y0) * po.dq;
+    t -= floor(t);
+    double s, c;
+    sincospi(2.0 * t, &s, &c);
+    const double inv = 1.0 / (double)scale[a];
+    const float re = (float)(c * inv), im = (float)(s * inv);
+    row_re = pack16<P>(re, -im);
+    row_im = pack16<P>(im, re);
+  }
+  const size_t base = (grp * nblk + blk) * (size_t)(2 * group) * (kC16KB);
+  a16[base + (size_t)(2 * g) * kC16KB + bl] = row_re;
+  a16[base + (size_t)(2 * g + 1) * kC16KB + bl] = row_im;
+}
+
+constexpr int kNT16 = 256;
+constexpr int kCT16 = 2;                 // 16-pixel column tiles per wave
+constexpr int kTile16 = 4 * 16 * kCT16;  // union pixels per workgroup
+constexpr int kPitch16 = 36;             // uint32 per LDS row (32 + 4 pad)
+
+struct UnionGeom16 {
+  int y0, x0, uy, ux;
+};
+
+template <int G, Prec P>
+__device__ __forceinline__ void contract16_tile(const uint32_t* __restrict__ s16, int n_actp,
+                                                const uint32_t* __restrict__ a16g, int np,
+                                                int p_base, int gcount, int ns, int w,
+                                                const UnionGeom16& U, int tile, const int* offx,
+                                                const int* offy, int only, float out_scale,
+                                                uint32_t* __restrict__ smem,
+                                                float2* __restrict__ window) {
+  constexpr int RT = G / 8;
+  constexpr int AROWS = 2 * G;
+  constexpr int ABUF = AROWS * kPitch16, BBUF = kTile16 * kPitch16;
+  constexpr int NAQ = AROWS * 8 / kNT16;     // u32x4 of the A block per thread
+  constexpr int NBQ = kTile16 * 8 / kNT16;   // u32x4 of the B block per thread
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int npix = U.uy * U.ux;
+  const int nblk = n_actp / kC16KB;
+
+  // S pixels this thread stages: tile column (tid + 256 i) / 8. Columns
+  // past the union read pixel 0 instead; their outputs are never stored,
+  // and a B column only reaches its own output column, so nothing needs
+  // clearing. Rows of absent probes and beams are zero in the packed A.
+  int spix[NBQ];
+#pragma unroll
+  for (int i = 0; i < NBQ; ++i) {
+    const int up = tile * kTile16 + ((tid + kNT16 * i) >> 3);
+    int off = 0;
+    if (up < npix) {
+      const int a = up / U.ux, b = up - a * U.ux;
+      off = ((U.y0 + a) % ns) * ns + ((U.x0 + b) % ns);
+    }
+    spix[i] = off;
+  }
+  const uint32_t* s16q = s16 + 4 * (tid & 7);
+
+  u32x4 ga[2][NAQ], gb[2][NBQ];
+  auto fetch = [&](int set, int blk) {
+    const u32x4* ab = reinterpret_cast<const u32x4*>(a16g + (size_t)blk * AROWS * kC16KB);
+#pragma unroll
+    for (int i = 0; i < NAQ; ++i) ga[set][i] = ab[tid + kNT16 * i];
+#pragma unroll
+    for (int i = 0; i < NBQ; ++i)
+      gb[set][i] = *reinterpret_cast<const u32x4*>(s16q + (size_t)spix[i] * n_actp + blk * kC16KB);
+  };
+  auto stash = [&](int set) {
+    uint32_t* A = smem + set * ABUF;
+    uint32_t* Bm = smem + 2 * ABUF + set * BBUF;
+#pragma unroll
+    for (int i = 0; i < NAQ; ++i) {
+      const int idx = tid + kNT16 * i;
+      *reinterpret_cast<u32x4*>(A + (idx >> 3) * kPitch16 + 4 * (idx & 7)) = ga[set][i];
+    }
+#pragma unroll
+    for (int i = 0; i < NBQ; ++i) {
+      const int idx = tid + kNT16 * i;
+      *reinterpret_cast<u32x4*>(Bm + (idx >> 3) * kPitch16 + 4 * (idx & 7)) = gb[set][i];
+    }
+  };
+
+  floatx4 acc[RT][kCT16];
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int c = 0; c < kCT16; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int krow = lane >> 4, mcol = lane & 15;
+  auto compute = [&](int buf) {
+    const uint32_t* A = smem + buf * ABUF + mcol * kPitch16 + 4 * krow;
+    const uint32_t* Bm = smem + 2 * ABUF + buf * BBUF + (16 * kCT16 * wv + mcol) * kPitch16 + 4 * krow;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      u32x4 av[RT], bv[kCT16];
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+        av[r] = *reinterpret_cast<const u32x4*>(A + 16 * r * kPitch16 + 16 * ks);
+#pragma unroll
+      for (int c = 0; c < kCT16; ++c)
+        bv[c] = *reinterpret_cast<const u32x4*>(Bm + 16 * c * kPitch16 + 16 * ks);
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int c = 0; c < kCT16; ++c) acc[r][c] = mfma16<P>(av[r], bv[c], acc[r][c]);
+    }
+  };
+
+  // n_actp is a multiple of 2 K blocks, so blocks always come in pairs
+  fetch(0, 0);
+  fetch(1, 1);
+  for (int blk = 0; blk < nblk; blk += 2) {
+    stash(0);
+    __syncthreads();
+    fetch(0, min(blk + 2, nblk - 2));
+    compute(0);
+    stash(1);
+    __syncthreads();
+    fetch(1, min(blk + 3, nblk - 1));
+    compute(1);
+  }
+  __syncthreads();
+
+  const size_t w2 = (size_t)w * w;
+#pragma unroll
+  for (int c = 0; c < kCT16; ++c) {
+    const int up = tile * kTile16 + 16 * kCT16 * wv + 16 * c + (lane & 15);
+    if (up >= npix) continue;
+    const int a = up / U.ux, b = up - a * U.ux;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int g = 8 * r + 2 * (lane >> 4) + h;
+        if (g >= gcount || (only >= 0 && g != only)) continue;
+        const int v = a - offy[g], u = b - offx[g];
+        if (v < 0 || v >= w || u < 0 || u >= w) continue;
+        window[(size_t)(p_base + g) * w2 + (size_t)v * w + u] =
+            make_float2(acc[r][c][2 * h] * out_scale, acc[r][c][2 * h + 1] * out_scale);
+      }
+    }
+  }
+}
+
+template <int G, Prec P>
+__global__ __launch_bounds__(kNT16) __attribute__((amdgpu_waves_per_eu(2))) void k_contract16(
+    const uint32_t* __restrict__ s16, int n_actp, const uint32_t* __restrict__ a16,
+    const int2* __restrict__ origin, int np, int ns, int w, float out_scale,
+    float2* __restrict__ window) {
+  constexpr int LDS = 2 * (2 * G * kPitch16) + 2 * (kTile16 * kPitch16);
+  __shared__ uint32_t smem[LDS];
+  __shared__ int offx[G], offy[G];
+  __shared__ int zero[G];
+  __shared__ int ginfo[6];
+  const int tid = threadIdx.x;
+  const int p_base = blockIdx.y * G;
+  const int gcount = min(G, np - p_base);
+  const int tile = blockIdx.x;
+  const int nblk = n_actp / kC16KB;
+  const uint32_t* a16g = a16 + (size_t)blockIdx.y * nblk * (2 * G) * kC16KB;
+  if (tid == 0) {
+    const int2 o0 = origin[p_base];
+    int minx = 0, maxx = 0, miny = 0, maxy = 0;
+    for (int g = 0; g < gcount; ++g) {
+      const int2 o = origin[p_base + g];
+      const int rx = wrap_mod16((long long)o.x - o0.x + ns / 2, ns) - ns / 2;
+      const int ry = wrap_mod16((long long)o.y - o0.y + ns / 2, ns) - ns / 2;
+      offx[g] = rx;
+      offy[g] = ry;
+      minx = min(minx, rx);
+      maxx = max(maxx, rx);
+      miny = min(miny, ry);
+      maxy = max(maxy, ry);
+    }
+    for (int g = 0; g < gcount; ++g) {
+      offx[g] -= minx;
+      offy[g] -= miny;
+    }
+    const int smax = w / 2;
+    ginfo[0] = (maxx - minx <= smax && maxy - miny <= smax) ? 0 : 1;
+    ginfo[1] = wrap_mod16((long long)o0.y + miny, ns);
+    ginfo[2] = wrap_mod16((long long)o0.x + minx, ns);
+    ginfo[3] = w + (maxy - miny);
+    ginfo[4] = w + (maxx - minx);
+  }
+  for (int g = tid; g < G; g += kNT16) zero[g] = 0;
+  __syncthreads();
+  if (ginfo[0] == 0) {
+    const UnionGeom16 U{ginfo[1], ginfo[2], ginfo[3], ginfo[4]};
+    if (tile * kTile16 >= U.uy * U.ux) return;
+    contract16_tile<G, P>(s16, n_actp, a16g, np, p_base, gcount, ns, w, U, tile, offx, offy, -1,
+                          out_scale, smem, window);
+  } else {
+    if (tile * kTile16 >= w * w) return;
+    for (int g = 0; g < gcount; ++g) {
+      const int2 o = origin[p_base + g];
+      const UnionGeom16 U{o.y, o.x, w, w};
+      contract16_tile<G, P>(s16, n_actp, a16g, np, p_base, gcount, ns, w, U, tile, zero, zero, g,
+                            out_scale, smem, window);
+    }
+  }
+}
+
+inline unsigned blocks16(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_s16_scale(const float2* smatrix, const ActiveBeam* act, int n_act, int ns,
+                            float* scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_s16_scale, dim3((unsigned)n_act), dim3(256), 0, st, smatrix, act, ns, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_s16_pack(const float2* smatrix, const ActiveBeam* act, int n_act, int n_actp,
+                           int ns, const float* scale, void* s16, Prec prec, hipStream_t st) {
+  const dim3 grid((unsigned)((size_t)ns * ns / 64), (unsigned)(n_actp / 32));
+  if (prec == Prec::kBF16)
+    hipLaunchKernelGGL(k_s16_pack<Prec::kBF16>, grid, dim3(256), 0, st, smatrix, act, n_act,
+                       n_actp, ns, scale, static_cast<uint32_t*>(s16));
+  else
+    hipLaunchKernelGGL(k_s16_pack<Prec::kFP16>, grid, dim3(256), 0, st, smatrix, act, n_act,
+                       n_actp, ns, scale, static_cast<uint32_t*>(s16));
+  return hipGetLastError();
+}
+
+hipError_t launch_alpha16(const double* probe_xy, int p0, int np, const ActiveBeam* act,
+                          int n_act, int n_actp, int f, int ns, int w, const ProbeOptics& po,
+                          const float* scale, int group, void* a16, int2* origin, Prec prec,
+                          hipStream_t st) {
+  const int ngrp = (np + group - 1) / group;
+  const int nblk = n_actp / kC16KB;
+  const size_t total = (size_t)ngrp * nblk * group * kC16KB;
+  if (prec == Prec::kBF16)
+    hipLaunchKernelGGL(k_alpha16<Prec::kBF16>, dim3(blocks16(total, 256)), dim3(256), 0, st,
+                       probe_xy, p0, np, act, n_act, f, ns, w, po, scale, group, nblk, total,
+                       static_cast<uint32_t*>(a16), origin);
+  else
+    hipLaunchKernelGGL(k_alpha16<Prec::kFP16>, dim3(blocks16(total, 256)), dim3(256), 0, st,
+                       probe_xy, p0, np, act, n_act, f, ns, w, po, scale, group, nblk, total,
+                       static_cast<uint32_t*>(a16), origin);
+  return hipGetLastError();
+}
+
+hipError_t launch_contract16(const void* s16, int n_actp, const void* a16, const int2* origin,
+                             int np, int ns, int w, int group, float out_scale, float2* window,
+                             Prec prec, hipStream_t st) {
+  const int ext = w + w / 2;
+  const dim3 grid((unsigned)((ext * ext + kTile16 - 1) / kTile16),
+                  (unsigned)((np + group - 1) / group));
+  const uint32_t* s = static_cast<const uint32_t*>(s16);
+  const uint32_t* a = static_cast<const uint32_t*>(a16);
+#define C16(GG, PP)                                                                          \
+  hipLaunchKernelGGL((k_contract16<GG, PP>), grid, dim3(kNT16), 0, st, s, n_actp, a, origin, np, \
+                     ns, w, out_scale, window)
+  if (prec == Prec::kBF16) {
+    switch (group) {
+      case 16: C16(16, Prec::kBF16); break;
+      case 32: C16(32, Prec::kBF16); break;
+      case 64: C16(64, Prec::kBF16); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (group) {
+      case 16: C16(16, Prec::kFP16); break;
+      case 32: C16(32, Prec::kFP16); break;
+      case 64: C16(64, Prec::kFP16); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef C16
+  return hipGetLastError();
+}
+
+}  // namespace prism

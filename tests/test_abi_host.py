@@ -115,6 +115,30 @@ def test_workspace_queries_are_consistent():
         p.multislice_workspace_bytes(33)
 
 
+def test_probe_precision_setting_and_workspace():
+    p = _plan(256, 25.6, 80.0, 8)
+    amax = p.alpha_max_default(20.0, 2)
+    optics = dict(alpha_mrad=20.0, C1_A=0.0, C3_A=0.0)
+    pref32, mn32 = p.probe_workspace_bytes(2, amax, optics)
+    L, h = _raw(p)
+    for bad in (-1, 3, 99):
+        assert L.prism_set_probe_precision(h, bad) == _native.PRISM_EINVAL
+    assert L.prism_set_probe_precision(None, 1) == _native.PRISM_EINVAL
+    with pytest.raises(ValueError):
+        p.set_probe_precision("fp8")
+    n_act = int(np.sum(np.hypot(*p.beams(2, amax).T.astype(float)) * 2 * p.wavelength / 25.6
+                       <= 20e-3))
+    n_actp = -(-n_act // 64) * 64
+    for prec in ("bf16", "fp16"):
+        p.set_probe_precision(prec)
+        pref, mn = p.probe_workspace_bytes(2, amax, optics)
+        # the packed 16-bit S-matrix copy is part of every 16-bit workspace
+        assert mn >= 128 * 128 * n_actp * 4
+        assert 0 < mn <= pref
+    p.set_probe_precision("fp32")
+    assert p.probe_workspace_bytes(2, amax, optics) == (pref32, mn32)
+
+
 def test_probe_group_shapes():
     p = Plan(1024, 40.0, 200.0, [2.0])
     assert p.probe_group(4) == (64, 8, 8)
