@@ -18,8 +18,10 @@ LIB = os.path.join(HERE, "libprism.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INC}", f"-I{SRC}", "-Wall", "-Wno-unused-function"]
-# device code: gfx950 only, packed FP32 instructions disabled
-DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# device code: gfx950 only, packed FP32 instructions disabled; the sign of
+# zero carries no meaning in these kernels, so x + 0 may fold (pruned FFTs)
+DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-fno-signed-zeros"]
 
 SOURCES = ["slice_kernels.hip", "probe_kernels.hip", "probe16_kernels.hip", "plan.cpp"]
 

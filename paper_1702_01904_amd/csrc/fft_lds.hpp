@@ -32,32 +32,32 @@ __device__ __forceinline__ int lpad(int i) { return i + (i >> kPadShift); }
 
 __host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
 
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+__host__ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 // a * conj(b)
-__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+__host__ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
   return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
-__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__host__ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
 // multiply by -i (forward) or +i (inverse)
 template <bool INV>
-__device__ __forceinline__ float2 mul_mi(float2 a) {
+__host__ __device__ __forceinline__ float2 mul_mi(float2 a) {
   return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
 }
 
 template <bool INV>
-__device__ __forceinline__ void dft2(float2 (&v)[2]) {
+__host__ __device__ __forceinline__ void dft2(float2 (&v)[2]) {
   const float2 t = v[0];
   v[0] = cadd(t, v[1]);
   v[1] = csub(t, v[1]);
 }
 
 template <bool INV>
-__device__ __forceinline__ void dft4v(float2& a0, float2& a1, float2& a2, float2& a3) {
+__host__ __device__ __forceinline__ void dft4v(float2& a0, float2& a1, float2& a2, float2& a3) {
   const float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
   const float2 t2 = cadd(a1, a3), t3 = mul_mi<INV>(csub(a1, a3));
   a0 = cadd(t0, t2);
@@ -67,13 +67,13 @@ __device__ __forceinline__ void dft4v(float2& a0, float2& a1, float2& a2, float2
 }
 
 template <bool INV>
-__device__ __forceinline__ void dft4(float2 (&v)[4]) {
+__host__ __device__ __forceinline__ void dft4(float2 (&v)[4]) {
   dft4v<INV>(v[0], v[1], v[2], v[3]);
 }
 
 // 8-point DFT as two 4-point DFTs (even/odd inputs) and a twiddled merge.
 template <bool INV>
-__device__ __forceinline__ void dft8(float2 (&v)[8]) {
+__host__ __device__ __forceinline__ void dft8(float2 (&v)[8]) {
   float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
   float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
   dft4v<INV>(e0, e1, e2, e3);
@@ -99,7 +99,7 @@ __device__ __forceinline__ void dft8(float2 (&v)[8]) {
 }
 
 template <int R, bool INV>
-__device__ __forceinline__ void dft(float2 (&v)[R]) {
+__host__ __device__ __forceinline__ void dft(float2 (&v)[R]) {
   if constexpr (R == 2) dft2<INV>(v);
   else if constexpr (R == 4) dft4<INV>(v);
   else dft8<INV>(v);

@@ -48,10 +48,14 @@ hipError_t launch_beam_init(float2* state, const int32_t* beams_mn, int b0, int 
                             const float2* twN, hipStream_t st);
 hipError_t launch_probe_init(float2* state, const double* probe_xy, int p0, int np, int n,
                              const ProbeOptics& po, const float2* twN, hipStream_t st);
+// Four-step slice passes (n = R^2): R, or 0 where the Stockham kernels run.
+int four_step_radix(int n);
+// tw2[m][j] = exp(-2 pi i j m / n), j, m < R (n entries; nothing for R = 0).
+hipError_t launch_twiddles2(float2* tw2, int n, hipStream_t st);
 hipError_t launch_row_pass(float2* state, int nwaves, int n, const float2* trans_p,
-                           const float2* twN, hipStream_t st);
+                           const float2* twN, const float2* tw2, hipStream_t st);
 hipError_t launch_col_pass(float2* state, int nwaves, int n, const float2* prop_p,
-                           const float2* twN, hipStream_t st);
+                           const float2* twN, const float2* tw2, hipStream_t st);
 // Last slice of multislice STEM: FFT_y, propagator, band limit, |Psi|^2/n^2
 // and per-column-tile detector partial sums (double [wave][tiles][n_det]).
 hipError_t launch_col_detect(const float2* state, int nwaves, int n, const float2* prop_p,

@@ -256,18 +256,23 @@ const prism_plan::PixLists* get_pixlists(prism_plan* p, int w, int f, const pris
 
 // ---------------------------------------------------------------- layouts
 
-constexpr size_t kChunkBytes = size_t(1) << 28;  // preferred wave-state size per chunk
+constexpr size_t kChunkBytes = size_t(1) << 28;  // preferred probe-window bytes per chunk
+#ifndef PRISM_WAVE_CHUNK_SHIFT
+#define PRISM_WAVE_CHUNK_SHIFT 28
+#endif
+constexpr size_t kWaveChunkBytes = size_t(1) << PRISM_WAVE_CHUNK_SHIFT;  // wave states per chunk
 
 size_t state_bytes(int n) { return (size_t)n * (n / 2) * sizeof(float2); }
 
 int pref_wave_chunk(int n, int count) {
-  const int c = (int)std::max<size_t>(1, kChunkBytes / state_bytes(n));
+  const int c = (int)std::max<size_t>(1, kWaveChunkBytes / state_bytes(n));
   return std::max(1, std::min(c, count));
 }
 
 struct SliceWs {
   float2* twN;
   float2* twH;
+  float2* tw2;
   double* thick;
   float2* prop;
   float2* trans;
@@ -281,6 +286,7 @@ size_t slice_layout(const prism_plan* p, int chunk, int n_beams, int n_det, Slic
   const int n = p->n;
   w->twN = c.take<float2>(n);
   w->twH = c.take<float2>(n / 2);
+  w->tw2 = c.take<float2>(n);
   w->thick = c.take<double>(p->H);
   w->prop = c.take<float2>((size_t)p->H * n);
   w->trans = c.take<float2>((size_t)p->H * n * n);
@@ -376,6 +382,7 @@ int prepare_slices(prism_plan* p, const SliceWs& w, hipStream_t st) {
           "copy slice thickness");
   LAUNCH(p, st, "twiddles", prism::launch_twiddles(w.twN, n, st));
   LAUNCH(p, st, "twiddles", prism::launch_twiddles(w.twH, n / 2, st));
+  LAUNCH(p, st, "twiddles", prism::launch_twiddles2(w.tw2, n, st));
   LAUNCH(p, st, "prop_lut", prism::launch_prop_lut(w.prop, n, p->H, w.thick, p->lam, p->dq, st));
   LAUNCH(p, st, "transmission", prism::launch_transmission(p->phase, w.trans, (size_t)p->H * n * n, 1.0f / (float)n, st));
   return PRISM_OK;
@@ -575,8 +582,8 @@ int prism_build_smatrix(prism_plan* p, int f, double amax_mrad, void* S, void* w
     const int nb = std::min(chunk, B - b0);
     LAUNCH(p, st, "beam_init", prism::launch_beam_init(w.state, w.mn, b0, nb, n, f, w.twN, st));
     for (int s = 0; s < p->H; ++s) {
-      LAUNCH(p, st, "row_pass", prism::launch_row_pass(w.state, nb, n, w.trans + (size_t)s * n * n, w.twN, st));
-      LAUNCH(p, st, "col_pass", prism::launch_col_pass(w.state, nb, n, w.prop + (size_t)s * n, w.twN, st));
+      LAUNCH(p, st, "row_pass", prism::launch_row_pass(w.state, nb, n, w.trans + (size_t)s * n * n, w.twN, w.tw2, st));
+      LAUNCH(p, st, "col_pass", prism::launch_col_pass(w.state, nb, n, w.prop + (size_t)s * n, w.twN, w.tw2, st));
     }
     LAUNCH(p, st, "extract", prism::launch_extract(w.state, nb, n, Sout + (size_t)b0 * splane, w.twH, st));
   }
@@ -609,9 +616,9 @@ int prism_multislice_outputs(prism_plan* p, const double* xy, int P, const prism
     const int np = std::min(chunk, P - p0);
     LAUNCH(p, st, "probe_init", prism::launch_probe_init(w.state, xy, p0, np, n, po, w.twN, st));
     for (int s = 0; s < p->H; ++s) {
-      LAUNCH(p, st, "row_pass", prism::launch_row_pass(w.state, np, n, w.trans + (size_t)s * n * n, w.twN, st));
+      LAUNCH(p, st, "row_pass", prism::launch_row_pass(w.state, np, n, w.trans + (size_t)s * n * n, w.twN, w.tw2, st));
       if (s + 1 < p->H) {
-        LAUNCH(p, st, "col_pass", prism::launch_col_pass(w.state, np, n, w.prop + (size_t)s * n, w.twN, st));
+        LAUNCH(p, st, "col_pass", prism::launch_col_pass(w.state, np, n, w.prop + (size_t)s * n, w.twN, w.tw2, st));
       } else {
         LAUNCH(p, st, "col_detect", prism::launch_col_detect(w.state, np, n, w.prop + (size_t)s * n, w.twN, bins,
                                          w.partial, st));

@@ -8,7 +8,10 @@
 // P_p is separable, so it comes from a 1D table per slice; M is the
 // half-band anti-aliasing aperture kx^2 + ky^2 < (n/4)^2. Each pass reads
 // and writes n^2/2 complex values per wave.
+#include <algorithm>
+
 #include "fft_lds.hpp"
+#include "fft_reg.hpp"
 #include "kernels.hpp"
 
 namespace prism {
@@ -55,6 +58,17 @@ __global__ void k_twiddles(float2* tw, int L) {
     double s, c;
     sincospi(-2.0 * (double)i / (double)L, &s, &c);
     tw[i] = make_float2((float)c, (float)s);
+  }
+}
+
+// tw2[m][j] = exp(-2 pi i j m / n) for j, m < R, n = R^2 (four-step passes).
+__global__ void k_twiddles2(float2* tw2, int R) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < R * R) {
+    const int m = i / R, j = i % R;
+    double s, c;
+    sincospi(-2.0 * (double)(j * m) / (double)(R * R), &s, &c);
+    tw2[i] = make_float2((float)c, (float)s);
   }
 }
 
@@ -176,6 +190,228 @@ __global__ __launch_bounds__(kRowNT) void k_row_pass(float2* __restrict__ state,
       dst[2 * E8] = w[p][6];
       dst[3 * E8] = w[p][7];
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Four-step row pass for n = R^2 (R = 16, 32). Row element x = R a + b sits
+// with lane b (R lanes per row, 64 / R rows per wave):
+//   inverse: lane b transforms over a (only a < R/4 and a >= 3R/4 are
+//            nonzero: the compact half band), twiddles by w_n^{-bc}, one LDS
+//            transpose, lane c transforms over b -> psi(c + R d);
+//   t_p / n multiplies psi in registers;
+//   forward: lane c transforms over d (the same registers), twiddles by
+//            w_n^{ce}, one LDS transpose, lane e transforms over c and
+//            stores the outputs e + R g with |kx| < n/4.
+// Each wave owns its LDS rows, so the transposes need only wave-level
+// ordering. A workgroup walks `iters` row groups; each wave loads the next
+// row's inputs and the current row's t_p while it computes.
+#ifndef PRISM_ROW4_ITER
+#define PRISM_ROW4_ITER 16   // most row groups per workgroup
+#endif
+constexpr int kRow4Iter = PRISM_ROW4_ITER;
+
+// Raw buffer resource over count complex values at p (gfx9 word 3), and
+// 8-byte loads / stores at vector offset voff + scalar offset soff (bytes).
+// Accesses past the resource read zero / are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t wave_rsrc(const float2* p, int count) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(p), 0, count * 8, 0x00020000);
+}
+typedef int int2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff,
+                                          float2 v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(int2v, v), r, voff, soff, 0);
+}
+
+// Orders LDS accesses of one wave (compiler barrier; LDS executes a wave's
+// instructions in order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_row_pass4(float2* __restrict__ state,
+                                                   const float2* __restrict__ trans,
+                                                   const float2* __restrict__ tw2, int iters) {
+  constexpr int N = R * R, H2 = N / 2, Q = R / 4, LS = R + 1;
+  constexpr int RPW = 64 / R;             // rows per wave
+  constexpr int RS = R * LS + 8;          // LDS row stride (float2)
+  constexpr int GROUP = 4 * RPW;          // rows per workgroup iteration
+  __shared__ float2 twl[R * R];
+  __shared__ float2 lds[4 * RPW * RS];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int j = lane % R, rw = lane / R;
+  for (int i = tid; i < R * R; i += 256) twl[i] = tw2[i];
+  __syncthreads();
+  float2* L = lds + (wv * RPW + rw) * RS;
+  const float2* twj = twl + j;
+  const size_t row_base = (size_t)blockIdx.x * (GROUP * iters) + wv * RPW + rw;
+
+  float2 s[2 * Q];  // compact inputs of the next row: a < Q, then a >= R - Q
+  auto load_src = [&](size_t row) {
+    const float2* src = state + row * H2 + j;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) s[a] = src[R * a];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) s[Q + a] = src[R * (R - Q + a) - H2];
+  };
+  load_src(row_base);
+  // wait here for the first row (s_waitcnt vmcnt(0)) so that the loop head
+  // carries no pending load and never waits for the previous row's stores
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+#pragma unroll 1
+  for (int it = 0; it < iters; ++it) {
+    const size_t row = row_base + (size_t)it * GROUP;
+    float2 v[R];
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+      v[a] = a < Q ? s[a] : (a >= R - Q ? s[a - (R - 2 * Q)] : make_float2(0.f, 0.f));
+    // Next row's inputs first, then this row's t_p: both are waited for
+    // together at the t_p product, after the inverse transform, so no load
+    // is still pending (and no store waited for) at the top of the loop.
+    // The last iteration re-reads its own row (L2-resident) to keep the
+    // load count uniform.
+    load_src(row_base + (size_t)min(it + 1, iters - 1) * GROUP);
+    float2 tt[R];
+    {
+      const float2* t = trans + (row & (size_t)(N - 1)) * N + j;
+#pragma unroll
+      for (int d = 0; d < R; ++d) tt[d] = t[R * d];
+    }
+    dft_reg<R, true>(v);
+#pragma unroll
+    for (int c = 0; c < R; ++c) L[c * LS + j] = c ? cmulc(v[c], twj[c * R]) : v[c];
+    wave_sync();
+#pragma unroll
+    for (int b = 0; b < R; ++b) v[b] = L[j * LS + b];
+    dft_reg<R, true>(v);
+#pragma unroll
+    for (int d = 0; d < R; ++d) v[d] = cmul(v[d], tt[d]);
+    dft_reg<R, false>(v);
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < R; ++e) L[e * LS + j] = e ? cmul(v[e], twj[e * R]) : v[e];
+    wave_sync();
+#pragma unroll
+    for (int c = 0; c < R; ++c) v[c] = L[j * LS + c];
+    dft_reg<R, false>(v);
+    float2* dst = state + row * H2 + j;
+#pragma unroll
+    for (int g = 0; g < R; ++g) {
+      if (g < Q) dst[R * g] = v[g];
+      else if (g >= R - Q) dst[R * g - H2] = v[g];
+    }
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Four-step column pass for n = R^2 over tiles of TC adjacent compact
+// columns (TC R threads); lane (b, c) = (tid / TC, tid % TC), so each load or
+// store instruction covers TC contiguous columns of 64 / TC rows.
+//   forward : lane (b, c) transforms y = R a + b over a, twiddles by
+//             w_n^{b k1}, LDS transpose, lane (k1, c) transforms over b and
+//             keeps ky = k1 + R k2 with |ky| < n/4 (the rest is cut by M);
+//   P_p(kx) P_p(ky) M / n in registers;
+//   inverse : lane (k1, c) transforms over k2 (inputs outside the half band
+//             are zero), twiddles by w_n^{-k1 m1}, LDS transpose, lane
+//             (m1, c) transforms over k1 and stores y = m1 + R m2.
+// A workgroup walks `iters` tiles, loading the next tile while it
+// computes the current one.
+#ifndef PRISM_COL4_ITER
+#define PRISM_COL4_ITER 8    // most tiles per workgroup
+#endif
+#ifndef PRISM_COL4_TC32
+#define PRISM_COL4_TC32 16   // columns per tile at n = 1024
+#endif
+constexpr int kCol4Iter = PRISM_COL4_ITER;
+
+template <int R, int TC>
+__global__ __launch_bounds__(TC * R) __attribute__((amdgpu_waves_per_eu(2))) void k_col_pass4(float2* __restrict__ state,
+                                                   const float2* __restrict__ prop,
+                                                   const float2* __restrict__ tw2, int iters) {
+  constexpr int N = R * R, H2 = N / 2, Q = R / 4, LS = R + 1;
+  constexpr int NT = TC * R;
+  constexpr int TILES = H2 / TC;         // tiles per wave
+  constexpr int CS = R * LS + 16 / TC;   // LDS column stride (float2): the TC
+                                         // columns of a 16-lane group hit
+                                         // distinct banks
+  __shared__ float2 twl[R * R];
+  __shared__ float2 pyl[H2];  // P_p(ky) for |ky| < n/4, compact order
+  __shared__ float2 lds[TC * CS];
+  const int tid = threadIdx.x, c = tid % TC, b = tid / TC;
+  for (int i = tid; i < R * R; i += NT) twl[i] = tw2[i];
+  for (int i = tid; i < H2; i += NT) pyl[i] = prop[i < H2 / 2 ? i : i + H2];
+  float2* L = lds + c * CS;
+  const float2* twb = twl + b;
+  const float inv_n = 1.0f / (float)N;
+
+  // Buffer accesses: one wave function per resource, lane (b, c) at a fixed
+  // vector byte offset, the row and tile offsets in scalar registers.
+  const unsigned lane_off = (unsigned)(b * H2 + c) * 8u;
+  float2 s[R];  // next tile's column elements y = R a + b
+  auto load_tile = [&](int tile) {
+    const int w = tile / TILES, c0 = (tile % TILES) * TC;
+    const __amdgpu_buffer_rsrc_t rs = wave_rsrc(state + (size_t)w * N * H2, N * H2);
+#pragma unroll
+    for (int a = 0; a < R; ++a) s[a] = buf_load(rs, lane_off, (c0 + R * a * H2) * 8);
+  };
+  // Iteration it handles tile it * gridDim.x + g, with g the XCD-grouped
+  // workgroup index: workgroups resident on one XCD at the same time take
+  // adjacent tiles, which share the 128-byte lines of every row.
+  const int g = xcd_tile(blockIdx.x, gridDim.x), nwg = gridDim.x;
+  load_tile(g);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): no load pending at the loop head
+  __syncthreads();
+#pragma unroll 1
+  for (int it = 0; it < iters; ++it) {
+    const int tile = it * nwg + g;
+    const int w = tile / TILES, c0 = (tile % TILES) * TC;
+    float2 v[R];
+#pragma unroll
+    for (int a = 0; a < R; ++a) v[a] = s[a];
+    // the next tile is in flight during this one (the last iteration
+    // re-reads its own tile to keep the load count uniform)
+    load_tile(min(it + 1, iters - 1) * nwg + g);
+    dft_reg<R, false>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) L[k1 * LS + b] = k1 ? cmul(v[k1], twb[k1 * R]) : v[k1];
+    __syncthreads();
+    const int jj = c0 + c;
+    const int kx = jj < H2 / 2 ? jj : jj - H2;
+    const float2 px = cscale(prop[kx & (N - 1)], inv_n);
+#pragma unroll
+    for (int bb = 0; bb < R; ++bb) v[bb] = L[b * LS + bb];
+    dft_reg<R, false>(v);  // lane (k1 = b, c): ky index b + R k2
+#pragma unroll
+    for (int k2 = 0; k2 < R; ++k2) {
+      if (k2 < Q || k2 >= R - Q) {
+        const int kyi = b + R * k2;
+        const int ky = kyi < H2 ? kyi : kyi - N;
+        const float2 p2 = pyl[k2 < Q ? kyi : kyi - H2];
+        v[k2] = 16 * (kx * kx + ky * ky) < N * N ? cmul(cmul(v[k2], px), p2)
+                                                  : make_float2(0.f, 0.f);
+      } else {
+        v[k2] = make_float2(0.f, 0.f);
+      }
+    }
+    dft_reg<R, true>(v);  // over k2 -> m1
+    __syncthreads();
+#pragma unroll
+    for (int m1 = 0; m1 < R; ++m1) L[m1 * LS + b] = m1 ? cmulc(v[m1], twb[m1 * R]) : v[m1];
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) v[k1] = L[b * LS + k1];
+    dft_reg<R, true>(v);  // lane (m1 = b, c): y = b + R m2
+    const __amdgpu_buffer_rsrc_t rd = wave_rsrc(state + (size_t)w * N * H2, N * H2);
+#pragma unroll
+    for (int m2 = 0; m2 < R; ++m2) buf_store(rd, lane_off, (c0 + R * m2 * H2) * 8, v[m2]);
+    __syncthreads();
   }
 }
 
@@ -435,8 +671,40 @@ hipError_t launch_beam_init(float2* state, const int32_t* beams_mn, int b0, int 
     default: return hipErrorInvalidValue; \
   }
 
+hipError_t launch_twiddles2(float2* tw2, int n, hipStream_t st) {
+  const int R = four_step_radix(n);
+  if (R == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_twiddles2, dim3(blocks_for((size_t)R * R, 256)), dim3(256), 0, st, tw2, R);
+  return hipGetLastError();
+}
+
+int four_step_radix(int n) { return n == 1024 ? 32 : (n == 256 ? 16 : 0); }
+
+// Largest power of two <= maxit dividing units with units / it >= min_wgs
+// (1 if none).
+static int pick_iters(int units, int maxit, int min_wgs) {
+  int it = maxit;
+  while (it > 1 && (units % it != 0 || units / it < min_wgs)) it /= 2;
+  return it;
+}
+
 hipError_t launch_row_pass(float2* state, int nwaves, int n, const float2* trans_p,
-                           const float2* twN, hipStream_t st) {
+                           const float2* twN, const float2* tw2, hipStream_t st) {
+  // row groups of 4 waves x 64/R rows; the iteration count is the largest
+  // power of two (up to kRow4Iter) that divides them and still leaves two
+  // workgroups per compute unit
+  if (n == 1024 || n == 256) {
+    const int R = n == 1024 ? 32 : 16;
+    const int groups = nwaves * n / (4 * 64 / R);
+    const int it = pick_iters(groups, kRow4Iter, 512);
+    if (R == 32)
+      hipLaunchKernelGGL(k_row_pass4<32>, dim3((unsigned)(groups / it)), dim3(256), 0, st, state,
+                         trans_p, tw2, it);
+    else
+      hipLaunchKernelGGL(k_row_pass4<16>, dim3((unsigned)(groups / it)), dim3(256), 0, st, state,
+                         trans_p, tw2, it);
+    return hipGetLastError();
+  }
 #define ROW(NN)                                                                                 \
   hipLaunchKernelGGL(k_row_pass<NN>, dim3((unsigned)((size_t)nwaves * NN / row_nseq(NN))),     \
                      dim3(kRowNT), 0, st, state, trans_p, twN)
@@ -448,7 +716,22 @@ hipError_t launch_row_pass(float2* state, int nwaves, int n, const float2* trans
 int col_tiles(int n) { return (n / 2) / col_tc(n); }
 
 hipError_t launch_col_pass(float2* state, int nwaves, int n, const float2* prop_p,
-                           const float2* twN, hipStream_t st) {
+                           const float2* twN, const float2* tw2, hipStream_t st) {
+  // tiles per launch: nwaves x (n/2) / (256/R), walked kCol4Iter at a time
+  if (n == 1024) {
+    constexpr int TC = PRISM_COL4_TC32, TPW = 512 / TC;
+    const int tiles = nwaves * TPW;
+    const int it = pick_iters(tiles, kCol4Iter, TC == 16 ? 256 : 512);
+    hipLaunchKernelGGL((k_col_pass4<32, TC>), dim3((unsigned)(tiles / it)), dim3(TC * 32), 0, st,
+                       state, prop_p, tw2, it);
+    return hipGetLastError();
+  }
+  if (n == 256) {
+    const int tiles = nwaves * 8, it = pick_iters(tiles, kCol4Iter, 512);
+    hipLaunchKernelGGL((k_col_pass4<16, 16>), dim3((unsigned)(tiles / it)), dim3(256), 0, st,
+                       state, prop_p, tw2, it);
+    return hipGetLastError();
+  }
   DetBins none{};
 #define COL(NN)                                                                                  \
   hipLaunchKernelGGL((k_col_pass<NN, false>), dim3((unsigned)(nwaves * col_tiles(NN))),          \
