@@ -253,14 +253,19 @@ __global__ __launch_bounds__(256) void k_row_pass4(float2* __restrict__ state,
   const size_t row_base = (size_t)blockIdx.x * (GROUP * iters) + wv * RPW + rw;
 
   float2 s[2 * Q];  // compact inputs of the next row: a < Q, then a >= R - Q
-  auto load_src = [&](size_t row) {
-    const float2* src = state + row * H2 + j;
+  // Buffer loads from the workgroup's first row; live == false gives a
+  // zero-length resource (zeros, no memory traffic).
+  const float2* wg_rows = state + (size_t)blockIdx.x * (GROUP * iters) * H2;
+  const unsigned lane_off = (unsigned)(((wv * RPW + rw) * H2 + j) * 8);
+  auto load_src = [&](int it, bool live) {
+    const __amdgpu_buffer_rsrc_t rs = wave_rsrc(wg_rows, live ? GROUP * iters * H2 : 0);
+    const int soff = it * GROUP * H2 * 8;
 #pragma unroll
-    for (int a = 0; a < Q; ++a) s[a] = src[R * a];
+    for (int a = 0; a < Q; ++a) s[a] = buf_load(rs, lane_off, soff + R * a * 8);
 #pragma unroll
-    for (int a = 0; a < Q; ++a) s[Q + a] = src[R * (R - Q + a) - H2];
+    for (int a = 0; a < Q; ++a) s[Q + a] = buf_load(rs, lane_off, soff + (R * (R - Q + a) - H2) * 8);
   };
-  load_src(row_base);
+  load_src(0, true);
   // wait here for the first row (s_waitcnt vmcnt(0)) so that the loop head
   // carries no pending load and never waits for the previous row's stores
   __builtin_amdgcn_s_waitcnt(0x0F70);
@@ -274,9 +279,7 @@ __global__ __launch_bounds__(256) void k_row_pass4(float2* __restrict__ state,
     // Next row's inputs first, then this row's t_p: both are waited for
     // together at the t_p product, after the inverse transform, so no load
     // is still pending (and no store waited for) at the top of the loop.
-    // The last iteration re-reads its own row (L2-resident) to keep the
-    // load count uniform.
-    load_src(row_base + (size_t)min(it + 1, iters - 1) * GROUP);
+    load_src(min(it + 1, iters - 1), it + 1 < iters);
     float2 tt[R];
     {
       const float2* t = trans + (row & (size_t)(N - 1)) * N + j;
@@ -355,9 +358,12 @@ __global__ __launch_bounds__(TC * R) __attribute__((amdgpu_waves_per_eu(2))) voi
   // vector byte offset, the row and tile offsets in scalar registers.
   const unsigned lane_off = (unsigned)(b * H2 + c) * 8u;
   float2 s[R];  // next tile's column elements y = R a + b
-  auto load_tile = [&](int tile) {
+  // live == false: a zero-length resource, the loads return zeros and
+  // touch no memory (keeps the instruction stream of every iteration alike)
+  auto load_tile = [&](int tile, bool live) {
     const int w = tile / TILES, c0 = (tile % TILES) * TC;
-    const __amdgpu_buffer_rsrc_t rs = wave_rsrc(state + (size_t)w * N * H2, N * H2);
+    const __amdgpu_buffer_rsrc_t rs =
+        wave_rsrc(state + (size_t)w * N * H2, live ? N * H2 : 0);
 #pragma unroll
     for (int a = 0; a < R; ++a) s[a] = buf_load(rs, lane_off, (c0 + R * a * H2) * 8);
   };
@@ -365,7 +371,7 @@ __global__ __launch_bounds__(TC * R) __attribute__((amdgpu_waves_per_eu(2))) voi
   // workgroup index: workgroups resident on one XCD at the same time take
   // adjacent tiles, which share the 128-byte lines of every row.
   const int g = xcd_tile(blockIdx.x, gridDim.x), nwg = gridDim.x;
-  load_tile(g);
+  load_tile(g, true);
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): no load pending at the loop head
   __syncthreads();
 #pragma unroll 1
@@ -375,9 +381,8 @@ __global__ __launch_bounds__(TC * R) __attribute__((amdgpu_waves_per_eu(2))) voi
     float2 v[R];
 #pragma unroll
     for (int a = 0; a < R; ++a) v[a] = s[a];
-    // the next tile is in flight during this one (the last iteration
-    // re-reads its own tile to keep the load count uniform)
-    load_tile(min(it + 1, iters - 1) * nwg + g);
+    // the next tile is in flight during this one
+    load_tile(min(it + 1, iters - 1) * nwg + g, it + 1 < iters);
     dft_reg<R, false>(v);
 #pragma unroll
     for (int k1 = 0; k1 < R; ++k1) L[k1 * LS + b] = k1 ? cmul(v[k1], twb[k1 * R]) : v[k1];
