@@ -304,30 +304,36 @@ __global__ __launch_bounds__(kNT16) __attribute__((amdgpu_waves_per_eu(2))) void
   const int tile = blockIdx.x;
   const int nblk = n_actp / kC16KB;
   const uint32_t* a16g = a16 + (size_t)blockIdx.y * nblk * (2 * G) * kC16KB;
-  if (tid == 0) {
+  if (tid < 64) {
+    // group geometry in wave 0, one lane per probe (G <= 64): offsets of
+    // each window from the first, their extent, and the union origin
     const int2 o0 = origin[p_base];
-    int minx = 0, maxx = 0, miny = 0, maxy = 0;
-    for (int g = 0; g < gcount; ++g) {
-      const int2 o = origin[p_base + g];
-      const int rx = wrap_mod16((long long)o.x - o0.x + ns / 2, ns) - ns / 2;
-      const int ry = wrap_mod16((long long)o.y - o0.y + ns / 2, ns) - ns / 2;
-      offx[g] = rx;
-      offy[g] = ry;
-      minx = min(minx, rx);
-      maxx = max(maxx, rx);
-      miny = min(miny, ry);
-      maxy = max(maxy, ry);
+    int rx = 0, ry = 0;
+    if (tid < gcount) {
+      const int2 o = origin[p_base + tid];
+      rx = wrap_mod16((long long)o.x - o0.x + ns / 2, ns) - ns / 2;
+      ry = wrap_mod16((long long)o.y - o0.y + ns / 2, ns) - ns / 2;
     }
-    for (int g = 0; g < gcount; ++g) {
-      offx[g] -= minx;
-      offy[g] -= miny;
+    int minx = rx, maxx = rx, miny = ry, maxy = ry;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      minx = min(minx, __shfl_xor(minx, off, 64));
+      maxx = max(maxx, __shfl_xor(maxx, off, 64));
+      miny = min(miny, __shfl_xor(miny, off, 64));
+      maxy = max(maxy, __shfl_xor(maxy, off, 64));
     }
-    const int smax = w / 2;
-    ginfo[0] = (maxx - minx <= smax && maxy - miny <= smax) ? 0 : 1;
-    ginfo[1] = wrap_mod16((long long)o0.y + miny, ns);
-    ginfo[2] = wrap_mod16((long long)o0.x + minx, ns);
-    ginfo[3] = w + (maxy - miny);
-    ginfo[4] = w + (maxx - minx);
+    if (tid < G) {
+      offx[tid] = rx - minx;
+      offy[tid] = ry - miny;
+    }
+    if (tid == 0) {
+      const int smax = w / 2;
+      ginfo[0] = (maxx - minx <= smax && maxy - miny <= smax) ? 0 : 1;
+      ginfo[1] = wrap_mod16((long long)o0.y + miny, ns);
+      ginfo[2] = wrap_mod16((long long)o0.x + minx, ns);
+      ginfo[3] = w + (maxy - miny);
+      ginfo[4] = w + (maxx - minx);
+    }
   }
   for (int g = tid; g < G; g += kNT16) zero[g] = 0;
   __syncthreads();
