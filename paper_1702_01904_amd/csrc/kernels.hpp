@@ -82,6 +82,8 @@ hipError_t launch_contract(const float2* smatrix, const ActiveBeam* act, int n_a
                            const float2* alpha, const int2* origin, int np, int ns, int w,
                            int group, float2* window, hipStream_t st);
 int contract_group(int w);
+// Workgroups per probe group along the union tiles (each loops over tiles).
+int contract_tile_slots(int w);
 
 // Low-precision probe step (BF16 or FP16 operands, FP32 accumulation).
 enum class Prec { kBF16 = 1, kFP16 = 2 };

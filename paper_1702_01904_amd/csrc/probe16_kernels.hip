@@ -301,7 +301,6 @@ __global__ __launch_bounds__(kNT16) __attribute__((amdgpu_waves_per_eu(2))) void
   const int tid = threadIdx.x;
   const int p_base = blockIdx.y * G;
   const int gcount = min(G, np - p_base);
-  const int tile = blockIdx.x;
   const int nblk = n_actp / kC16KB;
   const uint32_t* a16g = a16 + (size_t)blockIdx.y * nblk * (2 * G) * kC16KB;
   if (tid < 64) {
@@ -337,18 +336,20 @@ __global__ __launch_bounds__(kNT16) __attribute__((amdgpu_waves_per_eu(2))) void
   }
   for (int g = tid; g < G; g += kNT16) zero[g] = 0;
   __syncthreads();
+  // the workgroups of a group share its tiles round-robin
   if (ginfo[0] == 0) {
     const UnionGeom16 U{ginfo[1], ginfo[2], ginfo[3], ginfo[4]};
-    if (tile * kTile16 >= U.uy * U.ux) return;
-    contract16_tile<G, P>(s16, n_actp, a16g, np, p_base, gcount, ns, w, U, tile, offx, offy, -1,
-                          out_scale, smem, window);
+    for (int tile = blockIdx.x; tile * kTile16 < U.uy * U.ux; tile += gridDim.x)
+      contract16_tile<G, P>(s16, n_actp, a16g, np, p_base, gcount, ns, w, U, tile, offx, offy,
+                            -1, out_scale, smem, window);
   } else {
-    if (tile * kTile16 >= w * w) return;
-    for (int g = 0; g < gcount; ++g) {
-      const int2 o = origin[p_base + g];
-      const UnionGeom16 U{o.y, o.x, w, w};
-      contract16_tile<G, P>(s16, n_actp, a16g, np, p_base, gcount, ns, w, U, tile, zero, zero, g,
-                            out_scale, smem, window);
+    for (int tile = blockIdx.x; tile * kTile16 < w * w; tile += gridDim.x) {
+      for (int g = 0; g < gcount; ++g) {
+        const int2 o = origin[p_base + g];
+        const UnionGeom16 U{o.y, o.x, w, w};
+        contract16_tile<G, P>(s16, n_actp, a16g, np, p_base, gcount, ns, w, U, tile, zero, zero,
+                              g, out_scale, smem, window);
+      }
     }
   }
 }
@@ -396,9 +397,7 @@ hipError_t launch_alpha16(const double* probe_xy, int p0, int np, const ActiveBe
 hipError_t launch_contract16(const void* s16, int n_actp, const void* a16, const int2* origin,
                              int np, int ns, int w, int group, float out_scale, float2* window,
                              Prec prec, hipStream_t st) {
-  const int ext = w + w / 2;
-  const dim3 grid((unsigned)((ext * ext + kTile16 - 1) / kTile16),
-                  (unsigned)((np + group - 1) / group));
+  const dim3 grid((unsigned)contract_tile_slots(w), (unsigned)((np + group - 1) / group));
   const uint32_t* s = static_cast<const uint32_t*>(s16);
   const uint32_t* a = static_cast<const uint32_t*>(a16);
 #define C16(GG, PP)                                                                          \

@@ -13,6 +13,8 @@
 //   B'[2b][x] = Re S_b(x),   B'[2b+1][x]   = Im S_b(x),
 // run on v_mfma_f32_16x16x4f32 with FP32 accumulation. Each output pixel
 // of the union is kept for the probes whose own window contains it.
+#include <algorithm>
+
 #include "fft_lds.hpp"
 #include "kernels.hpp"
 
@@ -63,6 +65,9 @@ __global__ void k_alpha(const double* __restrict__ probe_xy, int p0, int np,
 #endif
 #ifndef PRISM_CG128
 #define PRISM_CG128 64 // probes per group for W >= 128
+#endif
+#ifndef PRISM_CTILES_PER_WG
+#define PRISM_CTILES_PER_WG 4  // union tiles per workgroup for a single window
 #endif
 constexpr int kCNT = 256;                 // threads per contraction workgroup (4 waves)
 constexpr int kCCT = PRISM_CCT;
@@ -249,7 +254,6 @@ __global__ __launch_bounds__(kCNT) __attribute__((amdgpu_waves_per_eu(2))) void 
   const int tid = threadIdx.x;
   const int p_base = blockIdx.y * G;
   const int gcount = min(G, np - p_base);
-  const int tile = blockIdx.x;
   if (tid < 64) {
     // group geometry in wave 0, one lane per probe (G <= 64): offsets of
     // each window from the first, their extent, and the union origin
@@ -282,22 +286,24 @@ __global__ __launch_bounds__(kCNT) __attribute__((amdgpu_waves_per_eu(2))) void 
     }
   }
   __syncthreads();
+  // the workgroups of a group share its tiles round-robin
   if (ginfo[0] == 0) {
     UnionGeom U{ginfo[1], ginfo[2], ginfo[3], ginfo[4]};
-    if (tile * kCTile >= U.uy * U.ux) return;
-    contract_tile<G>(S, act, n_act, alpha, np, p_base, gcount, ns, w, U, tile, offx, offy, -1,
-                     smem, window);
+    for (int tile = blockIdx.x; tile * kCTile < U.uy * U.ux; tile += gridDim.x)
+      contract_tile<G>(S, act, n_act, alpha, np, p_base, gcount, ns, w, U, tile, offx, offy, -1,
+                       smem, window);
   } else {
     // windows too far apart to share: one probe at a time, its window alone
-    if (tile * kCTile >= w * w) return;
     __shared__ int zero[G];
     for (int g = tid; g < G; g += kCNT) zero[g] = 0;
     __syncthreads();
-    for (int g = 0; g < gcount; ++g) {
-      const int2 o = origin[p_base + g];
-      UnionGeom U{o.y, o.x, w, w};
-      contract_tile<G>(S, act, n_act, alpha, np, p_base, gcount, ns, w, U, tile, zero, zero, g,
-                       smem, window);
+    for (int tile = blockIdx.x; tile * kCTile < w * w; tile += gridDim.x) {
+      for (int g = 0; g < gcount; ++g) {
+        const int2 o = origin[p_base + g];
+        UnionGeom U{o.y, o.x, w, w};
+        contract_tile<G>(S, act, n_act, alpha, np, p_base, gcount, ns, w, U, tile, zero, zero, g,
+                         smem, window);
+      }
     }
   }
 }
@@ -387,14 +393,16 @@ hipError_t launch_alpha(const double* probe_xy, int p0, int np, const ActiveBeam
   return hipGetLastError();
 }
 
+int contract_tile_slots(int w) {
+  const int own = (w * w + kCTile - 1) / kCTile;  // tiles of one window
+  return std::max(1, own / PRISM_CTILES_PER_WG);
+}
+
 hipError_t launch_contract(const float2* smatrix, const ActiveBeam* act, int n_act,
                            const float2* alpha, const int2* origin, int np, int ns, int w,
                            int group, float2* window, hipStream_t st) {
-  const int smax = w / 2;
-  const int ext = w + smax;
-  const unsigned tiles = (unsigned)((ext * ext + kCTile - 1) / kCTile);
   const unsigned groups = (unsigned)((np + group - 1) / group);
-  const dim3 grid(tiles, groups);
+  const dim3 grid((unsigned)contract_tile_slots(w), groups);
   switch (group) {
     case 16:
       hipLaunchKernelGGL(k_contract<16>, grid, dim3(kCNT), 0, st, smatrix, act, n_act, alpha,

@@ -322,6 +322,42 @@ def test_fcc1024_prism_full_scan_sampled_16bit(fcc, f, prec):
         assert e <= TOL16
 
 
+# ------------------------------------------------------------------ 2048^2 nanoparticle (16-bit case)
+
+@pytest.fixture(scope="module")
+def np2048():
+    d = build_inputs("np2048", 0)
+    plan = G.make_plan(d)
+    return d, plan
+
+
+def test_np2048_prism_f8_all_precisions(np2048):
+    # 1024 sub-pixel probes over the particle; FP32 against one-probe oracle
+    # runs, BF16 / FP16 against the same probes and against the (pinned)
+    # FP32 path over the whole scan
+    d, plan = np2048
+    f = 8
+    amax = _amax(d, f)
+    S = G.build_smatrix(plan, f, amax)
+    D32 = G.probe_outputs(plan, f, amax, S, d["probes"], d["optics"], d["edges"])
+    D = {p: _outputs_at(plan, p, f, amax, S, d["probes"], d["optics"], d["edges"])
+         for p in ("bf16", "fp16")}
+    for p in D:
+        e = eps(D[p], D32)
+        print(f"np2048 f={f} {p} vs fp32 over {len(D32)} probes eps_rel={e:.3e}")
+        assert e <= TOL16
+    for i in (0, 517):
+        x0, y0 = d["probes"][i]
+        ref = O.prism_probe_direct(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax,
+                                   d["optics"], x0, y0, d["edges"])
+        e32 = eps(D32[i], ref)
+        print(f"np2048 prism f={f} probe {i} fp32 eps_rel={e32:.3e} "
+              + " ".join(f"{p}={eps(D[p][i], ref):.3e}" for p in D))
+        assert e32 <= TOL
+        for p in D:
+            assert eps(D[p][i], ref) <= TOL16
+
+
 def test_fcc1024_empty_cell_prism_closed_form():
     d = build_inputs("fcc1024", 0, n_slices=3)
     d["phase"] = np.zeros_like(d["phase"])
