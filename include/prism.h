@@ -21,7 +21,7 @@
  *   - Complex values are interleaved float pairs (re, im) ("c64").
  *
  * Limits of this implementation: n is a power of two in [128, 2048]; the
- * PRISM window side W = n / (2 f) is a power of two in [8, 128]; at most
+ * PRISM window side W = n / (2 f) is a power of two in [8, 256]; at most
  * PRISM_MAX_DET detector bins.
  */
 #ifndef PRISM_H

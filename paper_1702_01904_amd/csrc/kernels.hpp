@@ -112,6 +112,12 @@ struct BinLists {
   int n;
   int off[kMaxDet + 1];
 };
+// W = 256: window FFT in two passes (rows in place, then columns fused with
+// |Psi|^2 / W^2 and bin sums) into partial[probe][tile][n_det], tiles =
+// window256_tiles(); reduce with launch_reduce_partials.
+int window256_tiles();
+hipError_t launch_window256(float2* window, int np, const float2* twW, int f,
+                            const DetBins& bins, double* partial, hipStream_t st);
 hipError_t launch_window_detect(const float2* window, int np, int w, const float2* twW,
                                 const uint16_t* pix, const BinLists& lists, double* out,
                                 hipStream_t st);

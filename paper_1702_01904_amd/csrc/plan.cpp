@@ -313,6 +313,7 @@ struct ProbeWs {
   uint32_t* a16;    // 16-bit: [chunk / G][n_actp / 32][2G][32] (pairs)
   int2* origin;
   float2* window;
+  double* partial;  // W = 256: [chunk][tiles][PRISM_MAX_DET] detector partials
 };
 
 // Active beams padded to whole pairs of 16-bit K blocks.
@@ -323,7 +324,8 @@ int padded_beams(int n_act) {
 size_t probe_layout(int w, int ns, int n_act, int chunk, int prec, ProbeWs* pw, void* base) {
   Carve c(base);
   pw->twW = c.take<float2>(w);
-  pw->pix = c.take<uint16_t>((size_t)PRISM_MAX_DET * w * w);  // worst case: overlapping bins
+  // per-bin pixel lists (W <= 128), worst case: overlapping bins
+  pw->pix = c.take<uint16_t>(w == 256 ? 0 : (size_t)PRISM_MAX_DET * w * w);
   pw->act = c.take<prism::ActiveBeam>(n_act);
   if (prec == PRISM_PREC_FP32) {
     pw->alpha = c.take<float2>((size_t)chunk * n_act);
@@ -338,6 +340,8 @@ size_t probe_layout(int w, int ns, int n_act, int chunk, int prec, ProbeWs* pw, 
   }
   pw->origin = c.take<int2>(chunk);
   pw->window = c.take<float2>((size_t)chunk * w * w);
+  pw->partial = w == 256 ? c.take<double>((size_t)chunk * prism::window256_tiles() * PRISM_MAX_DET)
+                         : nullptr;
   return c.used + 256;
 }
 
@@ -496,7 +500,7 @@ int prism_probe_workspace_bytes(const prism_plan* cp, int f, double amax_mrad,
   if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
   if (int r = check_optics(p, o)) return r;
   const int w = p->n / (2 * f);
-  if (!is_pow2(w) || w < 8 || w > 128) return fail(PRISM_EINVAL, "window side n/(2f) must be 8..128");
+  if (!is_pow2(w) || w < 8 || w > 256) return fail(PRISM_EINVAL, "window side n/(2f) must be 8..256");
   const auto* act = get_active(p, f, amax_mrad, *mn, o->alpha_mrad);
   const int G = prism::contract_group(w);
   ProbeWs pw;
@@ -640,7 +644,7 @@ int prism_probe_outputs(prism_plan* p, int f, double amax_mrad, const void* S, c
   prism::DetBins bins;
   if (int r = make_bins(p, d, &bins)) return r;
   const int n = p->n, ns = n / 2, w = n / (2 * f);
-  if (!is_pow2(w) || w < 8 || w > 128) return fail(PRISM_EINVAL, "window side n/(2f) must be 8..128");
+  if (!is_pow2(w) || w < 8 || w > 256) return fail(PRISM_EINVAL, "window side n/(2f) must be 8..256");
   const auto* act = get_active(p, f, amax_mrad, *mn, o->alpha_mrad);
   const int n_act = (int)act->size();
   if (n_act < 1) return fail(PRISM_EINVAL, "no beam of the set lies inside the probe aperture");
@@ -658,8 +662,9 @@ int prism_probe_outputs(prism_plan* p, int f, double amax_mrad, const void* S, c
   probe_layout(w, ns, n_act, chunk, prec, &pw, base);
   hipStream_t st = static_cast<hipStream_t>(stream);
   LAUNCH(p, st, "twiddles", prism::launch_twiddles(pw.twW, w, st));
-  const auto* pl = get_pixlists(p, w, f, bins);
-  if (!pl->pix.empty())
+  // per-bin pixel lists drive the W <= 128 detector; W = 256 bins per element
+  const prism_plan::PixLists* pl = w == 256 ? nullptr : get_pixlists(p, w, f, bins);
+  if (pl && !pl->pix.empty())
     HIP_TRY(hipMemcpyAsync(pw.pix, pl->pix.data(), pl->pix.size() * sizeof(uint16_t),
                            hipMemcpyHostToDevice, st),
             "copy detector pixel lists");
@@ -669,6 +674,21 @@ int prism_probe_outputs(prism_plan* p, int f, double amax_mrad, const void* S, c
   prism::ProbeOptics po = probe_optics(p, o);
   po.norm = 1.0 / ((double)w * std::sqrt((double)n_act));
   const float2* Sd = static_cast<const float2*>(S);
+  // window FFT, |Psi|^2 and detector sums of one chunk of probes
+  auto window_stage = [&](int np, int p0) -> int {
+    double* dst = out + (size_t)p0 * bins.n;
+    if (w == 256) {
+      LAUNCH(p, st, "window256",
+             prism::launch_window256(pw.window, np, pw.twW, f, bins, pw.partial, st));
+      LAUNCH(p, st, "reduce_partials",
+             prism::launch_reduce_partials(pw.partial, np, prism::window256_tiles(), bins.n, dst,
+                                           st));
+    } else {
+      LAUNCH(p, st, "window_detect",
+             prism::launch_window_detect(pw.window, np, w, pw.twW, pw.pix, pl->lists, dst, st));
+    }
+    return PRISM_OK;
+  };
   if (prec != PRISM_PREC_FP32) {
     const prism::Prec pr = prec == PRISM_PREC_BF16 ? prism::Prec::kBF16 : prism::Prec::kFP16;
     const int n_actp = padded_beams(n_act);
@@ -684,9 +704,7 @@ int prism_probe_outputs(prism_plan* p, int f, double amax_mrad, const void* S, c
       LAUNCH(p, st, "contract16",
              prism::launch_contract16(pw.s16, n_actp, pw.a16, pw.origin, np, ns, w, G, out_scale,
                                       pw.window, pr, st));
-      LAUNCH(p, st, "window_detect",
-             prism::launch_window_detect(pw.window, np, w, pw.twW, pw.pix, pl->lists,
-                                         out + (size_t)p0 * bins.n, st));
+      if (int r = window_stage(np, p0)) return r;
     }
     return PRISM_OK;
   }
@@ -695,9 +713,7 @@ int prism_probe_outputs(prism_plan* p, int f, double amax_mrad, const void* S, c
     LAUNCH(p, st, "alpha", prism::launch_alpha(xy, p0, np, pw.act, n_act, f, ns, w, po, pw.alpha, pw.origin, st));
     LAUNCH(p, st, "contract", prism::launch_contract(Sd, pw.act, n_act, pw.alpha, pw.origin, np, ns, w, G, pw.window,
                                    st));
-    LAUNCH(p, st, "window_detect",
-           prism::launch_window_detect(pw.window, np, w, pw.twW, pw.pix, pl->lists,
-                                       out + (size_t)p0 * bins.n, st));
+    if (int r = window_stage(np, p0)) return r;
   }
   return PRISM_OK;
 }

@@ -16,6 +16,7 @@
 #include <algorithm>
 
 #include "fft_lds.hpp"
+#include "fft_reg.hpp"
 #include "kernels.hpp"
 
 namespace prism {
@@ -309,6 +310,100 @@ __global__ __launch_bounds__(kCNT) __attribute__((amdgpu_waves_per_eu(2))) void 
 }
 
 // ---------------------------------------------------------------------------
+// W = 256 windows (too large for one workgroup's LDS): the 2D FFT runs as
+// two four-step passes over the window buffer, 256 = 16 x 16.
+//   rows : 16 lanes per row, lane j holds x = 16 a + j; DFT over a, twiddle
+//          w_256^{jc}, LDS transpose, DFT over b -> row[c + 16 d], in place;
+//   cols : tiles of 16 columns, lane (b, c) holds y = 16 a + b of column c;
+//          the same steps along y, then I = |Psi|^2 / W^2 at full-grid
+//          frequency f k_w is summed per detector bin (FP64) into one partial
+//          per (probe, tile).
+constexpr int kW4 = 256, kR4 = 16;
+
+__device__ __forceinline__ void load_tw16(float2* twl, const float2* __restrict__ twW, int tid) {
+  // twl[m][j] = w_256^{j m}
+  twl[tid] = twW[((tid & 15) * (tid >> 4)) & (kW4 - 1)];
+}
+
+__global__ __launch_bounds__(256) void k_window_rows256(float2* __restrict__ window,
+                                                        const float2* __restrict__ twW) {
+  constexpr int R = kR4, LS = R + 1;
+  __shared__ float2 twl[R * R];
+  __shared__ float2 lds[R * R * LS];
+  const int tid = threadIdx.x, j = tid % R, rr = tid / R;
+  load_tw16(twl, twW, tid);
+  __syncthreads();
+  float2* row = window + ((size_t)blockIdx.x * R + rr) * kW4;
+  float2* L = lds + rr * R * LS;
+  float2 v[R];
+#pragma unroll
+  for (int a = 0; a < R; ++a) v[a] = row[R * a + j];
+  dft_reg<R, false>(v);
+#pragma unroll
+  for (int c = 0; c < R; ++c) L[c * LS + j] = c ? cmul(v[c], twl[c * R + j]) : v[c];
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < R; ++b) v[b] = L[j * LS + b];
+  dft_reg<R, false>(v);
+#pragma unroll
+  for (int d = 0; d < R; ++d) row[j + R * d] = v[d];
+}
+
+__global__ __launch_bounds__(256) void k_window_cols256_detect(const float2* __restrict__ window,
+                                                               const float2* __restrict__ twW,
+                                                               int f, DetBins bins,
+                                                               double* __restrict__ partial) {
+  constexpr int R = kR4, LS = R + 1, TC = 16, TILES = kW4 / TC;
+  constexpr int CS = R * LS + 1;  // column stride: 16 columns on distinct banks
+  __shared__ float2 twl[R * R];
+  __shared__ float2 lds[TC * CS];
+  __shared__ double red[kMaxDet][4];
+  const int tid = threadIdx.x, c = tid % TC, b = tid / TC;
+  load_tw16(twl, twW, tid);
+  __syncthreads();
+  const size_t p = blockIdx.x / TILES;
+  const int tile = blockIdx.x % TILES, col = tile * TC + c;
+  const float2* src = window + p * kW4 * kW4 + col;
+  float2* L = lds + c * CS;
+  float2 v[R];
+#pragma unroll
+  for (int a = 0; a < R; ++a) v[a] = src[(size_t)(R * a + b) * kW4];
+  dft_reg<R, false>(v);
+#pragma unroll
+  for (int k1 = 0; k1 < R; ++k1) L[k1 * LS + b] = k1 ? cmul(v[k1], twl[k1 * R + b]) : v[k1];
+  __syncthreads();
+#pragma unroll
+  for (int bb = 0; bb < R; ++bb) v[bb] = L[b * LS + bb];
+  dft_reg<R, false>(v);  // lane (k1 = b, c): ky index b + R k2
+  const long long kx = col < kW4 / 2 ? col : col - kW4;
+  const double inv_w2 = 1.0 / ((double)kW4 * (double)kW4);
+  double acc[kMaxDet];
+#pragma unroll
+  for (int q = 0; q < kMaxDet; ++q) acc[q] = 0.0;
+#pragma unroll
+  for (int k2 = 0; k2 < R; ++k2) {
+    const int kyi = b + R * k2;
+    const long long ky = kyi < kW4 / 2 ? kyi : kyi - kW4;
+    const long long kk = (long long)f * f * (kx * kx + ky * ky);
+    const double I = ((double)v[k2].x * v[k2].x + (double)v[k2].y * v[k2].y) * inv_w2;
+#pragma unroll
+    for (int q = 0; q < kMaxDet; ++q)
+      if (q < bins.n && kk >= bins.lo[q] && kk < bins.hi[q]) acc[q] += I;
+  }
+#pragma unroll
+  for (int q = 0; q < kMaxDet; ++q) {
+    if (q < bins.n) {  // uniform
+      const double sum = wave_sum(acc[q]);
+      if ((tid & 63) == 0) red[q][tid >> 6] = sum;
+    }
+  }
+  __syncthreads();
+  if (tid < bins.n)
+    partial[((size_t)p * TILES + tile) * bins.n + tid] =
+        red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
+}
+
+// ---------------------------------------------------------------------------
 __host__ __device__ constexpr int wd_nt(int w) { return (w * w / 16) < 64 ? 64 : w * w / 16; }
 
 // One probe per workgroup: 2D FFT of the W x W window in LDS, then
@@ -419,6 +514,19 @@ hipError_t launch_contract(const float2* smatrix, const ActiveBeam* act, int n_a
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+int window256_tiles() { return kW4 / 16; }
+
+hipError_t launch_window256(float2* window, int np, const float2* twW, int f,
+                            const DetBins& bins, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_window_rows256, dim3((unsigned)((size_t)np * kW4 / kR4)), dim3(256), 0, st,
+                     window, twW);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_window_cols256_detect, dim3((unsigned)((size_t)np * window256_tiles())),
+                     dim3(256), 0, st, window, twW, f, bins, partial);
   return hipGetLastError();
 }
 

@@ -188,8 +188,8 @@ def test_errors_before_any_launch():
     # zero probes is a no-op that needs no buffers
     assert L.prism_multislice_outputs(h, None, 0, ctypes.byref(optics), ctypes.byref(det), None,
                                       None, 0, None) == _native.PRISM_OK
-    # probe step: window too large (f = 1 at n = 128 gives W = 64: fine; n=512 f=1 W=256: not)
-    big = Plan(512, 51.2, 80.0, [2.0])
+    # probe step: window too large (f = 1 at n = 128 gives W = 64: fine; n=1024 f=1 W=512: not)
+    big = Plan(1024, 102.4, 80.0, [2.0])
     Lb, hb = _raw(big)
     amax1 = big.alpha_max_default(20.0, 1)
     r = Lb.prism_probe_outputs(hb, 1, amax1, dummy, dummy, 4, ctypes.byref(optics),

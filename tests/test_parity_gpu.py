@@ -331,12 +331,12 @@ def np2048():
     return d, plan
 
 
-def test_np2048_prism_f8_all_precisions(np2048):
-    # 1024 sub-pixel probes over the particle; FP32 against one-probe oracle
-    # runs, BF16 / FP16 against the same probes and against the (pinned)
-    # FP32 path over the whole scan
+@pytest.mark.parametrize("f", [8, 4])
+def test_np2048_prism_all_precisions(np2048, f):
+    # 1024 sub-pixel probes over the particle (f = 4: W = 256, the two-pass
+    # window FFT); FP32 against one-probe oracle runs, BF16 / FP16 against the
+    # same probes and against the (pinned) FP32 path over the whole scan
     d, plan = np2048
-    f = 8
     amax = _amax(d, f)
     S = G.build_smatrix(plan, f, amax)
     D32 = G.probe_outputs(plan, f, amax, S, d["probes"], d["optics"], d["edges"])
