@@ -144,11 +144,23 @@ int prism_build_smatrix(prism_plan* plan, int f, double alpha_max_mrad, void* sm
  * W x W window of Eq. RegionBounds (centre pixel floor(x0/dx_S + 1/2),
  * periodic wrap), Fourier transform, and integrate |Psi|^2 / W^2 over each
  * detector bin: out_dev float64 [P][n_det]. The S-matrix must come from
- * prism_build_smatrix with the same f and alpha_max_mrad. */
+ * prism_build_smatrix with the same f and alpha_max_mrad, and the probe
+ * semi-angle may not exceed alpha_max_mrad (PRISM_EINVAL): every beam inside
+ * the aperture must be in the set. Several optics (defocus, C3, semi-angle)
+ * can be evaluated on one resident S-matrix. */
 int prism_probe_outputs(prism_plan* plan, int f, double alpha_max_mrad, const void* smatrix_dev,
                         const double* probe_xy_dev, int n_probes, const prism_optics* optics,
                         const prism_detector* detector, double* out_dev, void* ws,
                         size_t ws_bytes, void* stream);
+
+/* The same probe step with the full diffraction pattern as output (Fig. 1f:
+ * the CBED alternative to virtual detectors): cbed_dev float32 [P][W][W],
+ * I(kw) = |FFT_W psi|^2 / W^2 with both axes in W-point fftfreq order (window
+ * frequency kw sits at full-grid frequency f kw). Workspace, precision and
+ * errors as prism_probe_outputs; PRISM_EINVAL for a null cbed_dev. */
+int prism_probe_cbed(prism_plan* plan, int f, double alpha_max_mrad, const void* smatrix_dev,
+                     const double* probe_xy_dev, int n_probes, const prism_optics* optics,
+                     float* cbed_dev, void* ws, size_t ws_bytes, void* stream);
 
 /* Conventional multislice STEM (Eq. 5 run once per probe): incident probe
  * iFFT[A e^{-i chi} e^{-2 pi i q.r0}] n / sqrt(N_A), H slice steps,

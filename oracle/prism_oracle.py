@@ -362,7 +362,7 @@ def prism_outputs(S, beams, f, cell, energy_keV, optics, probes, edges_mrad, fft
 
 
 def prism_probe_direct(phase, thickness, cell, energy_keV, f, alpha_max_mrad, optics, x0, y0,
-                       edges_mrad, fft=None):
+                       edges_mrad, fft=None, return_cbed=False):
     """PRISM output of one probe without forming the S-matrix.
 
     By linearity of Eq. 5, the window sum of Eq. PRISMfinal equals the window
@@ -370,7 +370,8 @@ def prism_probe_direct(phase, thickness, cell, energy_keV, f, alpha_max_mrad, op
     psi0 = sum_b alpha_b exp(2 pi i q_b . r). One multislice run per probe
     therefore gives PRISM's output exactly (identity checked against
     ``prism_outputs``); this is how single probes of large grids are sampled.
-    Returns float64 [n_det].
+    Returns float64 [n_det] (and the window intensity [W][W] when
+    ``return_cbed``).
     """
     F = _fft(fft)
     phase = np.asarray(phase, dtype=np.float64)
@@ -393,7 +394,8 @@ def prism_probe_direct(phase, thickness, cell, energy_keV, f, alpha_max_mrad, op
     win = exit_[np.ix_(rows, cols)]
     I = np.abs(F.fft2(win)) ** 2 / float(w * w)
     theta = theta_of_k2(k2_grid(w, scale=f), lam, dq)
-    return detector_sums(I, theta, edges_mrad)
+    D = detector_sums(I, theta, edges_mrad)
+    return (D, I) if return_cbed else D
 
 
 # --------------------------------------------------------------------------

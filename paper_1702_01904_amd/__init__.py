@@ -195,6 +195,20 @@ class Plan:
             ctypes.byref(o), ctypes.byref(det.struct), _ptr(out), _ptr(workspace),
             workspace.numel(), _stream_ptr(stream)))
 
+    def probe_cbed(self, f, alpha_max_mrad, smatrix, probe_xy, optics, out, workspace, stream=None):
+        """Full diffraction patterns: out float32 device [P][W][W] (W = n / 2f, fftfreq order)."""
+        import torch
+        P = probe_xy.shape[0]
+        w = self.n // (2 * int(f))
+        _check_dev(probe_xy, torch.float64, 2 * P, "probe_xy")
+        _check_dev(out, torch.float32, P * w * w, "out")
+        _check_dev(smatrix, torch.complex64, None, "smatrix")
+        _check_dev(workspace, torch.uint8, None, "workspace")
+        o = _optics(optics)
+        _native.check(self._L.prism_probe_cbed(
+            self._h, int(f), float(alpha_max_mrad), _ptr(smatrix), _ptr(probe_xy), int(P),
+            ctypes.byref(o), _ptr(out), _ptr(workspace), workspace.numel(), _stream_ptr(stream)))
+
     def multislice_outputs(self, probe_xy, optics, edges_mrad, out, workspace, stream=None):
         import torch
         det = _Det(edges_mrad)

@@ -23,8 +23,9 @@ EXPORTS = (
     "prism_plan_create", "prism_plan_destroy", "prism_wavelength", "prism_beam_count",
     "prism_beams", "prism_smatrix_bytes", "prism_build_workspace_bytes",
     "prism_multislice_workspace_bytes", "prism_probe_workspace_bytes", "prism_probe_group",
-    "prism_set_probe_precision", "prism_set_potential_slices", "prism_build_smatrix", "prism_probe_outputs",
-    "prism_multislice_outputs", "prism_profile_enable", "prism_profile_report",
+    "prism_set_probe_precision", "prism_set_potential_slices", "prism_build_smatrix",
+    "prism_probe_outputs", "prism_probe_cbed", "prism_multislice_outputs",
+    "prism_profile_enable", "prism_profile_report",
     "prism_last_error",
 )
 
@@ -85,6 +86,8 @@ def lib():
         "prism_build_smatrix": (I, [P, I, D, P, P, ctypes.c_size_t, P]),
         "prism_probe_outputs": (I, [P, I, D, P, P, I, ctypes.POINTER(PrismOptics),
                                     ctypes.POINTER(PrismDetector), P, P, ctypes.c_size_t, P]),
+        "prism_probe_cbed": (I, [P, I, D, P, P, I, ctypes.POINTER(PrismOptics), P, P,
+                                 ctypes.c_size_t, P]),
         "prism_multislice_outputs": (I, [P, P, I, ctypes.POINTER(PrismOptics),
                                          ctypes.POINTER(PrismDetector), P, P, ctypes.c_size_t, P]),
         "prism_profile_enable": (I, [P, I]),

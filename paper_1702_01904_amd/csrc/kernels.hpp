@@ -118,6 +118,13 @@ struct BinLists {
 int window256_tiles();
 hipError_t launch_window256(float2* window, int np, const float2* twW, int f,
                             const DetBins& bins, double* partial, hipStream_t st);
+// W = 256 CBED: cbed[p][ky][kx] = |Psi|^2 / W^2 (float32, fftfreq order).
+hipError_t launch_window256_cbed(float2* window, int np, const float2* twW, float* cbed,
+                                 hipStream_t st);
+// Full CBED output: cbed[p][ky][kx] = |FFT_W window_p|^2 / W^2 (float32,
+// window fftfreq order), W <= 128.
+hipError_t launch_window_cbed(const float2* window, int np, int w, const float2* twW,
+                              float* cbed, hipStream_t st);
 hipError_t launch_window_detect(const float2* window, int np, int w, const float2* twW,
                                 const uint16_t* pix, const BinLists& lists, double* out,
                                 hipStream_t st);

@@ -394,6 +394,111 @@ int prepare_slices(prism_plan* p, const SliceWs& w, hipStream_t st) {
 
 }  // namespace
 
+namespace {
+
+// PRISM probe step (Fig. 1d-f). d != nullptr: detector sums into out;
+// d == nullptr: full CBED intensities into cbed.
+int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, const double* xy, int P,
+               const prism_optics* o, const prism_detector* d, double* out, float* cbed,
+               void* ws, size_t ws_bytes, void* stream) {
+  const std::vector<int32_t>* mn;
+  if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
+  if (P < 0) return fail(PRISM_EINVAL, "negative probe count");
+  if (int r = check_optics(p, o)) return r;
+  if (o->alpha_mrad > amax_mrad)
+    return fail(PRISM_EINVAL, "probe semi-angle exceeds the beam set's alpha_max");
+  const bool want_cbed = d == nullptr;
+  prism::DetBins bins{};
+  if (!want_cbed)
+    if (int r = make_bins(p, d, &bins)) return r;
+  const int n = p->n, ns = n / 2, w = n / (2 * f);
+  if (!is_pow2(w) || w < 8 || w > 256) return fail(PRISM_EINVAL, "window side n/(2f) must be 8..256");
+  const auto* act = get_active(p, f, amax_mrad, *mn, o->alpha_mrad);
+  const int n_act = (int)act->size();
+  if (n_act < 1) return fail(PRISM_EINVAL, "no beam of the set lies inside the probe aperture");
+  if (P == 0) return PRISM_OK;
+  if (!S || !xy || !ws || (want_cbed ? !cbed : !out)) return fail(PRISM_EINVAL, "null device buffer");
+  const int G = prism::contract_group(w);
+  void* base = aligned_base(ws);
+  const size_t avail = ws_bytes;  // layouts include 256 B of alignment slack
+  ProbeWs pw;
+  int chunk = std::min(pref_probe_chunk(w, G), (P + G - 1) / G * G);
+  const int prec = p->prec;
+  while (chunk >= G && probe_layout(w, ns, n_act, chunk, prec, &pw, nullptr) > avail)
+    chunk = chunk > 8 * G ? (chunk * 3 / 4) / G * G : chunk - G;
+  if (chunk < G) return fail(PRISM_ENOSPACE, "workspace smaller than the probe-step minimum");
+  probe_layout(w, ns, n_act, chunk, prec, &pw, base);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  LAUNCH(p, st, "twiddles", prism::launch_twiddles(pw.twW, w, st));
+  // per-bin pixel lists drive the W <= 128 detector; W = 256 bins per element
+  const prism_plan::PixLists* pl =
+      (w == 256 || want_cbed) ? nullptr : get_pixlists(p, w, f, bins);
+  if (pl && !pl->pix.empty())
+    HIP_TRY(hipMemcpyAsync(pw.pix, pl->pix.data(), pl->pix.size() * sizeof(uint16_t),
+                           hipMemcpyHostToDevice, st),
+            "copy detector pixel lists");
+  HIP_TRY(hipMemcpyAsync(pw.act, act->data(), act->size() * sizeof(prism::ActiveBeam),
+                         hipMemcpyHostToDevice, st),
+          "copy active beams");
+  prism::ProbeOptics po = probe_optics(p, o);
+  po.norm = 1.0 / ((double)w * std::sqrt((double)n_act));
+  const float2* Sd = static_cast<const float2*>(S);
+  // window FFT, |Psi|^2 and detector sums of one chunk of probes
+  auto window_stage = [&](int np, int p0) -> int {
+    if (want_cbed) {
+      float* dst = cbed + (size_t)p0 * w * w;
+      if (w == 256) {
+        LAUNCH(p, st, "window256_cbed", prism::launch_window256_cbed(pw.window, np, pw.twW, dst, st));
+      } else {
+        LAUNCH(p, st, "window_cbed", prism::launch_window_cbed(pw.window, np, w, pw.twW, dst, st));
+      }
+      return PRISM_OK;
+    }
+    double* dst = out + (size_t)p0 * bins.n;
+    if (w == 256) {
+      LAUNCH(p, st, "window256",
+             prism::launch_window256(pw.window, np, pw.twW, f, bins, pw.partial, st));
+      LAUNCH(p, st, "reduce_partials",
+             prism::launch_reduce_partials(pw.partial, np, prism::window256_tiles(), bins.n, dst,
+                                           st));
+    } else {
+      LAUNCH(p, st, "window_detect",
+             prism::launch_window_detect(pw.window, np, w, pw.twW, pw.pix, pl->lists, dst, st));
+    }
+    return PRISM_OK;
+  };
+  if (prec != PRISM_PREC_FP32) {
+    const prism::Prec pr = prec == PRISM_PREC_BF16 ? prism::Prec::kBF16 : prism::Prec::kFP16;
+    const int n_actp = padded_beams(n_act);
+    const float out_scale = (float)po.norm;
+    po.norm = 1.0;
+    LAUNCH(p, st, "s16_scale", prism::launch_s16_scale(Sd, pw.act, n_act, ns, pw.scale, st));
+    LAUNCH(p, st, "s16_pack", prism::launch_s16_pack(Sd, pw.act, n_act, n_actp, ns, pw.scale, pw.s16, pr, st));
+    for (int p0 = 0; p0 < P; p0 += chunk) {
+      const int np = std::min(chunk, P - p0);
+      LAUNCH(p, st, "alpha16",
+             prism::launch_alpha16(xy, p0, np, pw.act, n_act, n_actp, f, ns, w, po, pw.scale, G,
+                                   pw.a16, pw.origin, pr, st));
+      LAUNCH(p, st, "contract16",
+             prism::launch_contract16(pw.s16, n_actp, pw.a16, pw.origin, np, ns, w, G, out_scale,
+                                      pw.window, pr, st));
+      if (int r = window_stage(np, p0)) return r;
+    }
+    return PRISM_OK;
+  }
+  for (int p0 = 0; p0 < P; p0 += chunk) {
+    const int np = std::min(chunk, P - p0);
+    LAUNCH(p, st, "alpha", prism::launch_alpha(xy, p0, np, pw.act, n_act, f, ns, w, po, pw.alpha, pw.origin, st));
+    LAUNCH(p, st, "contract", prism::launch_contract(Sd, pw.act, n_act, pw.alpha, pw.origin, np, ns, w, G, pw.window,
+                                   st));
+    if (int r = window_stage(np, p0)) return r;
+  }
+  return PRISM_OK;
+}
+
+
+}  // namespace
+
 // =========================================================================
 // C ABI
 // =========================================================================
@@ -637,85 +742,14 @@ int prism_multislice_outputs(prism_plan* p, const double* xy, int P, const prism
 int prism_probe_outputs(prism_plan* p, int f, double amax_mrad, const void* S, const double* xy,
                         int P, const prism_optics* o, const prism_detector* d, double* out,
                         void* ws, size_t ws_bytes, void* stream) {
-  const std::vector<int32_t>* mn;
-  if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
-  if (P < 0) return fail(PRISM_EINVAL, "negative probe count");
-  if (int r = check_optics(p, o)) return r;
-  prism::DetBins bins;
-  if (int r = make_bins(p, d, &bins)) return r;
-  const int n = p->n, ns = n / 2, w = n / (2 * f);
-  if (!is_pow2(w) || w < 8 || w > 256) return fail(PRISM_EINVAL, "window side n/(2f) must be 8..256");
-  const auto* act = get_active(p, f, amax_mrad, *mn, o->alpha_mrad);
-  const int n_act = (int)act->size();
-  if (n_act < 1) return fail(PRISM_EINVAL, "no beam of the set lies inside the probe aperture");
-  if (P == 0) return PRISM_OK;
-  if (!S || !xy || !out || !ws) return fail(PRISM_EINVAL, "null device buffer");
-  const int G = prism::contract_group(w);
-  void* base = aligned_base(ws);
-  const size_t avail = ws_bytes;  // layouts include 256 B of alignment slack
-  ProbeWs pw;
-  int chunk = std::min(pref_probe_chunk(w, G), (P + G - 1) / G * G);
-  const int prec = p->prec;
-  while (chunk >= G && probe_layout(w, ns, n_act, chunk, prec, &pw, nullptr) > avail)
-    chunk = chunk > 8 * G ? (chunk * 3 / 4) / G * G : chunk - G;
-  if (chunk < G) return fail(PRISM_ENOSPACE, "workspace smaller than the probe-step minimum");
-  probe_layout(w, ns, n_act, chunk, prec, &pw, base);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  LAUNCH(p, st, "twiddles", prism::launch_twiddles(pw.twW, w, st));
-  // per-bin pixel lists drive the W <= 128 detector; W = 256 bins per element
-  const prism_plan::PixLists* pl = w == 256 ? nullptr : get_pixlists(p, w, f, bins);
-  if (pl && !pl->pix.empty())
-    HIP_TRY(hipMemcpyAsync(pw.pix, pl->pix.data(), pl->pix.size() * sizeof(uint16_t),
-                           hipMemcpyHostToDevice, st),
-            "copy detector pixel lists");
-  HIP_TRY(hipMemcpyAsync(pw.act, act->data(), act->size() * sizeof(prism::ActiveBeam),
-                         hipMemcpyHostToDevice, st),
-          "copy active beams");
-  prism::ProbeOptics po = probe_optics(p, o);
-  po.norm = 1.0 / ((double)w * std::sqrt((double)n_act));
-  const float2* Sd = static_cast<const float2*>(S);
-  // window FFT, |Psi|^2 and detector sums of one chunk of probes
-  auto window_stage = [&](int np, int p0) -> int {
-    double* dst = out + (size_t)p0 * bins.n;
-    if (w == 256) {
-      LAUNCH(p, st, "window256",
-             prism::launch_window256(pw.window, np, pw.twW, f, bins, pw.partial, st));
-      LAUNCH(p, st, "reduce_partials",
-             prism::launch_reduce_partials(pw.partial, np, prism::window256_tiles(), bins.n, dst,
-                                           st));
-    } else {
-      LAUNCH(p, st, "window_detect",
-             prism::launch_window_detect(pw.window, np, w, pw.twW, pw.pix, pl->lists, dst, st));
-    }
-    return PRISM_OK;
-  };
-  if (prec != PRISM_PREC_FP32) {
-    const prism::Prec pr = prec == PRISM_PREC_BF16 ? prism::Prec::kBF16 : prism::Prec::kFP16;
-    const int n_actp = padded_beams(n_act);
-    const float out_scale = (float)po.norm;
-    po.norm = 1.0;
-    LAUNCH(p, st, "s16_scale", prism::launch_s16_scale(Sd, pw.act, n_act, ns, pw.scale, st));
-    LAUNCH(p, st, "s16_pack", prism::launch_s16_pack(Sd, pw.act, n_act, n_actp, ns, pw.scale, pw.s16, pr, st));
-    for (int p0 = 0; p0 < P; p0 += chunk) {
-      const int np = std::min(chunk, P - p0);
-      LAUNCH(p, st, "alpha16",
-             prism::launch_alpha16(xy, p0, np, pw.act, n_act, n_actp, f, ns, w, po, pw.scale, G,
-                                   pw.a16, pw.origin, pr, st));
-      LAUNCH(p, st, "contract16",
-             prism::launch_contract16(pw.s16, n_actp, pw.a16, pw.origin, np, ns, w, G, out_scale,
-                                      pw.window, pr, st));
-      if (int r = window_stage(np, p0)) return r;
-    }
-    return PRISM_OK;
-  }
-  for (int p0 = 0; p0 < P; p0 += chunk) {
-    const int np = std::min(chunk, P - p0);
-    LAUNCH(p, st, "alpha", prism::launch_alpha(xy, p0, np, pw.act, n_act, f, ns, w, po, pw.alpha, pw.origin, st));
-    LAUNCH(p, st, "contract", prism::launch_contract(Sd, pw.act, n_act, pw.alpha, pw.origin, np, ns, w, G, pw.window,
-                                   st));
-    if (int r = window_stage(np, p0)) return r;
-  }
-  return PRISM_OK;
+  if (!d) return fail(PRISM_EINVAL, "null detector");
+  return probe_step(p, f, amax_mrad, S, xy, P, o, d, out, nullptr, ws, ws_bytes, stream);
+}
+
+int prism_probe_cbed(prism_plan* p, int f, double amax_mrad, const void* S, const double* xy,
+                     int P, const prism_optics* o, float* cbed, void* ws, size_t ws_bytes,
+                     void* stream) {
+  return probe_step(p, f, amax_mrad, S, xy, P, o, nullptr, nullptr, cbed, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -349,10 +349,12 @@ __global__ __launch_bounds__(256) void k_window_rows256(float2* __restrict__ win
   for (int d = 0; d < R; ++d) row[j + R * d] = v[d];
 }
 
+template <bool CBED>
 __global__ __launch_bounds__(256) void k_window_cols256_detect(const float2* __restrict__ window,
                                                                const float2* __restrict__ twW,
                                                                int f, DetBins bins,
-                                                               double* __restrict__ partial) {
+                                                               double* __restrict__ partial,
+                                                               float* __restrict__ cbed) {
   constexpr int R = kR4, LS = R + 1, TC = 16, TILES = kW4 / TC;
   constexpr int CS = R * LS + 1;  // column stride: 16 columns on distinct banks
   __shared__ float2 twl[R * R];
@@ -375,8 +377,16 @@ __global__ __launch_bounds__(256) void k_window_cols256_detect(const float2* __r
 #pragma unroll
   for (int bb = 0; bb < R; ++bb) v[bb] = L[b * LS + bb];
   dft_reg<R, false>(v);  // lane (k1 = b, c): ky index b + R k2
-  const long long kx = col < kW4 / 2 ? col : col - kW4;
   const double inv_w2 = 1.0 / ((double)kW4 * (double)kW4);
+  if constexpr (CBED) {
+    float* dst = cbed + p * kW4 * kW4 + col;
+#pragma unroll
+    for (int k2 = 0; k2 < R; ++k2)
+      dst[(size_t)(b + R * k2) * kW4] =
+          (float)(((double)v[k2].x * v[k2].x + (double)v[k2].y * v[k2].y) * inv_w2);
+    return;
+  }
+  const long long kx = col < kW4 / 2 ? col : col - kW4;
   double acc[kMaxDet];
 #pragma unroll
   for (int q = 0; q < kMaxDet; ++q) acc[q] = 0.0;
@@ -404,18 +414,34 @@ __global__ __launch_bounds__(256) void k_window_cols256_detect(const float2* __r
 }
 
 // ---------------------------------------------------------------------------
-__host__ __device__ constexpr int wd_nt(int w) { return (w * w / 16) < 64 ? 64 : w * w / 16; }
+#ifndef PRISM_WD_PREFETCH
+#define PRISM_WD_PREFETCH 0  // window kernel: load the next probe during the current one
+#endif
+#ifndef PRISM_WD_GRID
+#define PRISM_WD_GRID 1048576  // window kernel: most workgroups (each then walks probes)
+#endif
+#ifndef PRISM_WD128_NT
+#define PRISM_WD128_NT 1024  // threads per W = 128 window workgroup
+#endif
+__host__ __device__ constexpr int wd_nt(int w) {
+  return w == 128 ? PRISM_WD128_NT : ((w * w / 16) < 64 ? 64 : w * w / 16);
+}
 
-// One probe per workgroup: 2D FFT of the W x W window in LDS, then
-// I(kw) = |Psi(kw)|^2 / W^2 summed over each bin's pixel list in FP64
-// (the lists encode the angle test at full-grid frequency f kw). The first
-// row stage reads the window straight from HBM.
-template <int W>
+// 2D FFT of each W x W window in LDS, then either I(kw) = |Psi(kw)|^2 / W^2
+// summed over each bin's pixel list in FP64 (the lists encode the angle test
+// at full-grid frequency f kw), or (CBED) I written out in full. Workgroups
+// walk probes p = blockIdx.x, + gridDim.x, ...: the first row stage of the
+// next probe is loaded into registers while the current one is transformed
+// (one window fills most of a compute unit's LDS, so this overlap is the
+// only one there is).
+template <int W, bool CBED>
 __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __restrict__ window,
+                                                            int np,
                                                             const float2* __restrict__ twW,
                                                             const uint16_t* __restrict__ pix,
                                                             BinLists lists,
-                                                            double* __restrict__ out) {
+                                                            double* __restrict__ out,
+                                                            float* __restrict__ cbed) {
   constexpr int NT = wd_nt(W);
   constexpr int NW = NT / 64;
   using Rows = RowBatch<W, W>;
@@ -425,11 +451,10 @@ __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __rest
   __shared__ float2 tw[W];
   __shared__ double red[8][NW];
   const int tid = threadIdx.x;
-  const size_t p = blockIdx.x;
-  const float2* src = window + p * W * W;
   load_twiddles<W, NT>(tw, twW, tid);
-  {
-    float2 v[S8::PER][8];
+  float2 nxt[S8::PER][8];
+  auto load = [&](int p) {  // first row stage of window p
+    const float2* src = window + (size_t)p * W * W;
 #pragma unroll
     for (int q = 0; q < S8::PER; ++q) {
       const int b = tid + q * NT;
@@ -437,40 +462,61 @@ __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __rest
         int row, j;
         stage_coords<Rows, S8::NB>(b, row, j);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[q][r] = src[row * W + j + r * (W / 8)];
+        for (int r = 0; r < 8; ++r) nxt[q][r] = src[row * W + j + r * (W / 8)];
       }
     }
-    stage_out<Rows, 8, 1, NT, false>(lds, tid, v);
-  }
-  __syncthreads();
-  fft_from<Rows, NT, false, 8>(lds, tw, tid);
-  fft_lds<Cols, NT, false>(lds, tw, tid);
+  };
+  if (PRISM_WD_PREFETCH) load(blockIdx.x);
   const double inv_w2 = 1.0 / ((double)W * (double)W);
-  for (int j0 = 0; j0 < lists.n; j0 += 8) {
-    double acc[8];
+#pragma unroll 1
+  for (int p = blockIdx.x; p < np; p += gridDim.x) {
+    float2 v[S8::PER][8];
+    if (!PRISM_WD_PREFETCH) load(p);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      acc[q] = 0.0;
-      const int j = j0 + q;
-      if (j < lists.n) {
-        for (int i = lists.off[j] + tid; i < lists.off[j + 1]; i += NT) {
-          const float2 z = lds[lpad(pix[i])];
-          acc[q] += (double)z.x * z.x + (double)z.y * z.y;
+    for (int q = 0; q < S8::PER; ++q)
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[q][r] = nxt[q][r];
+    if (PRISM_WD_PREFETCH)
+      load(min(p + (int)gridDim.x, np - 1));  // the last round re-reads its own window
+    stage_out<Rows, 8, 1, NT, false>(lds, tid, v);
+    __syncthreads();
+    fft_from<Rows, NT, false, 8>(lds, tw, tid);
+    fft_lds<Cols, NT, false>(lds, tw, tid);
+    if constexpr (CBED) {
+      float* dst = cbed + (size_t)p * W * W;
+      for (int e = tid; e < W * W; e += NT) {
+        const float2 z = lds[lpad(e)];
+        dst[e] = (float)(((double)z.x * z.x + (double)z.y * z.y) * inv_w2);
+      }
+    } else {
+      for (int j0 = 0; j0 < lists.n; j0 += 8) {
+        double acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          acc[q] = 0.0;
+          const int j = j0 + q;
+          if (j < lists.n) {
+            for (int i = lists.off[j] + tid; i < lists.off[j + 1]; i += NT) {
+              const float2 z = lds[lpad(pix[i])];
+              acc[q] += (double)z.x * z.x + (double)z.y * z.y;
+            }
+          }
         }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const double sm = wave_sum(acc[q]);
+          if ((tid & 63) == 0) red[q][tid >> 6] = sm;
+        }
+        __syncthreads();
+        if (tid < 8 && j0 + tid < lists.n) {
+          double sm = 0.0;
+          for (int wv = 0; wv < NW; ++wv) sm += red[tid][wv];
+          out[(size_t)p * lists.n + j0 + tid] = sm * inv_w2;
+        }
+        __syncthreads();
       }
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const double s = wave_sum(acc[q]);
-      if ((tid & 63) == 0) red[q][tid >> 6] = s;
-    }
-    __syncthreads();
-    if (tid < 8 && j0 + tid < lists.n) {
-      double s = 0.0;
-      for (int wv = 0; wv < NW; ++wv) s += red[tid][wv];
-      out[p * lists.n + j0 + tid] = s * inv_w2;
-    }
-    __syncthreads();
+    __syncthreads();  // LDS free for the next probe
   }
 }
 
@@ -525,18 +571,35 @@ hipError_t launch_window256(float2* window, int np, const float2* twW, int f,
                      window, twW);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_window_cols256_detect, dim3((unsigned)((size_t)np * window256_tiles())),
-                     dim3(256), 0, st, window, twW, f, bins, partial);
+  hipLaunchKernelGGL(k_window_cols256_detect<false>, dim3((unsigned)((size_t)np * window256_tiles())),
+                     dim3(256), 0, st, window, twW, f, bins, partial, (float*)nullptr);
   return hipGetLastError();
 }
+
+hipError_t launch_window256_cbed(float2* window, int np, const float2* twW, float* cbed,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_window_rows256, dim3((unsigned)((size_t)np * kW4 / kR4)), dim3(256), 0, st,
+                     window, twW);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  DetBins none{};
+  hipLaunchKernelGGL(k_window_cols256_detect<true>, dim3((unsigned)((size_t)np * window256_tiles())),
+                     dim3(256), 0, st, window, twW, 1, none, (double*)nullptr, cbed);
+  return hipGetLastError();
+}
+
+// Workgroups for the window kernels: one per probe up to PRISM_WD_GRID, then
+// each walks several probes.
+static unsigned window_grid(int np) { return (unsigned)std::min(np, PRISM_WD_GRID); }
 
 hipError_t launch_window_detect(const float2* window, int np, int w, const float2* twW,
                                 const uint16_t* pix, const BinLists& lists, double* out,
                                 hipStream_t st) {
-#define WD(WW)                                                                                   \
-  case WW:                                                                                       \
-    hipLaunchKernelGGL(k_window_detect<WW>, dim3((unsigned)np), dim3(wd_nt(WW)), 0, st, window,   \
-                       twW, pix, lists, out);                                                    \
+  if (np <= 0) return hipSuccess;
+#define WD(WW)                                                                                  \
+  case WW:                                                                                      \
+    hipLaunchKernelGGL((k_window_detect<WW, false>), dim3(window_grid(np)), dim3(wd_nt(WW)), 0, \
+                       st, window, np, twW, pix, lists, out, (float*)nullptr);                  \
     break;
   switch (w) {
     WD(8)
@@ -548,6 +611,29 @@ hipError_t launch_window_detect(const float2* window, int np, int w, const float
       return hipErrorInvalidValue;
   }
 #undef WD
+  return hipGetLastError();
+}
+
+hipError_t launch_window_cbed(const float2* window, int np, int w, const float2* twW,
+                              float* cbed, hipStream_t st) {
+  if (np <= 0) return hipSuccess;
+  BinLists none{};
+#define WC(WW)                                                                                 \
+  case WW:                                                                                     \
+    hipLaunchKernelGGL((k_window_detect<WW, true>), dim3(window_grid(np)), dim3(wd_nt(WW)), 0, \
+                       st, window, np, twW, (const uint16_t*)nullptr, none, (double*)nullptr,  \
+                       cbed);                                                                  \
+    break;
+  switch (w) {
+    WC(8)
+    WC(16)
+    WC(32)
+    WC(64)
+    WC(128)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef WC
   return hipGetLastError();
 }
 

@@ -60,6 +60,19 @@ def probe_outputs(plan, f, amax, S, probes, optics, edges, ws_bytes=None):
     return out.cpu().numpy()
 
 
+def probe_cbed(plan, f, amax, S, probes, optics):
+    import torch
+    xy = torch.from_numpy(np.ascontiguousarray(probes, dtype=np.float64)).to(device())
+    w = plan.n // (2 * f)
+    out = torch.full((len(probes), w, w), float("nan"), dtype=torch.float32, device=device())
+    pref, _ = plan.probe_workspace_bytes(f, amax, optics)
+    ws = workspace(pref)
+    say(f"probe_cbed n={plan.n} f={f} P={len(probes)} W={w} ws={ws.numel()}")
+    plan.probe_cbed(f, amax, S, xy, optics, out, ws)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
 def multislice_outputs(plan, probes, optics, edges, ws_bytes=None):
     import torch
     xy = torch.from_numpy(np.ascontiguousarray(probes, dtype=np.float64)).to(device())

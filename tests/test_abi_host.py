@@ -195,6 +195,20 @@ def test_errors_before_any_launch():
     r = Lb.prism_probe_outputs(hb, 1, amax1, dummy, dummy, 4, ctypes.byref(optics),
                                ctypes.byref(det), dummy, dummy, 1 << 30, None)
     assert r == _native.PRISM_EINVAL and b"window" in Lb.prism_last_error()
+    # probe step: semi-angle beyond the beam set's alpha_max
+    wider = _native.PrismOptics(amax + 1.0, 0.0, 0.0)
+    r = L.prism_probe_outputs(h, 2, amax, dummy, dummy, 4, ctypes.byref(wider), ctypes.byref(det),
+                              dummy, dummy, 1 << 30, None)
+    assert r == _native.PRISM_EINVAL and b"alpha_max" in L.prism_last_error()
+    # CBED output: null output buffer, and the same checks as the detector path
+    r = L.prism_probe_cbed(h, 2, amax, dummy, dummy, 4, ctypes.byref(optics), None, dummy,
+                           1 << 30, None)
+    assert r == _native.PRISM_EINVAL
+    r = L.prism_probe_cbed(h, 2, amax, dummy, dummy, 4, ctypes.byref(wider), dummy, dummy,
+                           1 << 30, None)
+    assert r == _native.PRISM_EINVAL
+    assert L.prism_probe_cbed(h, 2, amax, None, None, 0, ctypes.byref(optics), None, None, 0,
+                              None) == _native.PRISM_OK
     # probe step: too small workspace
     r = L.prism_probe_outputs(h, 2, amax, dummy, dummy, 4, ctypes.byref(optics), ctypes.byref(det),
                               dummy, dummy, 128, None)

@@ -125,6 +125,49 @@ def test_prism_tiny_16bit(tiny, f, prec):
     assert eps(D32, ref) <= TOL
 
 
+@pytest.mark.parametrize("f", [1, 2])
+def test_prism_cbed_tiny(tiny, f):
+    # full diffraction patterns (float32) against the oracle's window
+    # intensities, and their detector sums against the detector path
+    d, plan = tiny
+    amax = _amax(d, f)
+    S = G.build_smatrix(plan, f, amax)
+    pr = d["probes"][::7]
+    C = G.probe_cbed(plan, f, amax, S, pr, d["optics"])
+    beams, Sref = O.smatrix(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax)
+    _, Cref = O.prism_outputs(Sref, beams, f, d["cell"], d["energy_keV"], d["optics"], pr,
+                              d["edges"], return_cbed=True)
+    e = eps(C, Cref)
+    print(f"cbed tiny f={f} P={len(pr)} eps_rel={e:.3e}")
+    assert e <= TOL
+    D = G.probe_outputs(plan, f, amax, S, pr, d["optics"], d["edges"])
+    lam = O.wavelength(d["energy_keV"])
+    w = plan.n // (2 * f)
+    theta = O.theta_of_k2(O.k2_grid(w, scale=f), lam, 1.0 / d["cell"])
+    Dc = np.stack([O.detector_sums(c.astype(np.float64), theta, d["edges"]) for c in C])
+    assert eps(Dc, D) <= TOL
+
+
+def test_optics_sweep_on_resident_smatrix(tiny):
+    # one S-matrix, several probes' optics (defocus, C3, semi-angle): only the
+    # coefficients change (the paper's re-use of the S-matrix)
+    d, plan = tiny
+    f = 2
+    amax = _amax(d, f, alpha_mrad=25.0)
+    S = G.build_smatrix(plan, f, amax)
+    beams, Sref = O.smatrix(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax)
+    sweep = [dict(alpha_mrad=25.0, C1_A=0.0, C3_A=0.0),
+             dict(alpha_mrad=20.0, C1_A=60.0, C3_A=0.0),
+             dict(alpha_mrad=15.0, C1_A=-40.0, C3_A=2.0e5)]
+    for optics in sweep:
+        D = G.probe_outputs(plan, f, amax, S, d["probes"], optics, d["edges"])
+        ref = O.prism_outputs(Sref, beams, f, d["cell"], d["energy_keV"], optics, d["probes"],
+                              d["edges"])
+        e = eps(D, ref)
+        print(f"sweep {optics} eps_rel={e:.3e}")
+        assert e <= TOL
+
+
 def test_prism_f1_equals_gpu_multislice(tiny):
     # P6 re-run on GPU outputs only
     d, plan = tiny
@@ -356,6 +399,21 @@ def test_np2048_prism_all_precisions(np2048, f):
         assert e32 <= TOL
         for p in D:
             assert eps(D[p][i], ref) <= TOL16
+
+
+def test_np2048_cbed_w256(np2048):
+    # W = 256 diffraction patterns: one probe against the oracle's direct route
+    d, plan = np2048
+    f = 4
+    amax = _amax(d, f)
+    S = G.build_smatrix(plan, f, amax)
+    pr = d["probes"][[3]]
+    C = G.probe_cbed(plan, f, amax, S, pr, d["optics"])
+    _, Cref = O.prism_probe_direct(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax,
+                                   d["optics"], pr[0, 0], pr[0, 1], d["edges"], return_cbed=True)
+    e = eps(C[0], Cref)
+    print(f"np2048 cbed W=256 eps_rel={e:.3e}")
+    assert e <= TOL
 
 
 def test_fcc1024_empty_cell_prism_closed_form():
