@@ -38,9 +38,9 @@ CONFIG = "fcc1024"
 # workload (f = 4), calibrated with a 256 MiB device copy (fetch x2.0,
 # write x1.0); see profiles/fcc1024_prism_f4_hbm_traffic.md. Valid only for
 # the kernel sources with this hash; reported as null otherwise.
-TRAFFIC_SRC_SHA = "3828e37b5fedfc69"
-TRAFFIC_BYTES = {"row_pass": 530019928, "col_pass": 525991183, "contract": 1754190034,
-                 "window_detect": 270041376}
+TRAFFIC_SRC_SHA = "e604edb4038df7de"
+TRAFFIC_BYTES = {"row_pass": 531742286, "col_pass": 522063867, "contract": 1063450576,
+                 "window_detect": 270103063, "contract16": 815224643}
 
 
 def kernel_source_sha():
@@ -57,7 +57,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--f", type=int, default=4, help="interpolation factor of the headline run")
     ap.add_argument("--other-f", default="8,16", help="extra f values timed (comma list, '' none)")
-    ap.add_argument("--ms-probes", type=int, default=128, help="multislice probes timed")
+    ap.add_argument("--ms-probes", type=int, default=128,
+                    help="multislice probes timed (0: skip the multislice baseline)")
     ap.add_argument("--precisions", default="bf16,fp16",
                     help="16-bit window-sum variants timed at the headline f ('' none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -266,21 +267,24 @@ def main():
         del c
 
     # multislice baseline on the same GPU, seeded probe subset
-    rng = np.random.default_rng(args.seed + 7)
-    sub = d["probes"][rng.choice(P, args.ms_probes, replace=False)]
-    xy_ms = torch.from_numpy(sub).to(dev)
-    out_ms = torch.empty((len(sub), n_det), dtype=torch.float64, device=dev)
-    ws_ms = torch.empty(plan.multislice_workspace_bytes(n_det)[0], dtype=torch.uint8, device=dev)
-    plan.multislice_outputs(xy_ms[:8], optics, edges, out_ms, ws_ms)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    plan.multislice_outputs(xy_ms, optics, edges, out_ms, ws_ms)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_multi = e0.elapsed_time(e1)
-    multi_rate = len(sub) / (ms_multi * 1e-3)
-    log(f"multislice: {len(sub)} probes in {ms_multi:.1f} ms -> {multi_rate:.1f} probes/s")
+    multi_rate = None
+    if args.ms_probes > 0:
+        rng = np.random.default_rng(args.seed + 7)
+        sub = d["probes"][rng.choice(P, args.ms_probes, replace=False)]
+        xy_ms = torch.from_numpy(sub).to(dev)
+        out_ms = torch.empty((len(sub), n_det), dtype=torch.float64, device=dev)
+        ws_ms = torch.empty(plan.multislice_workspace_bytes(n_det)[0], dtype=torch.uint8,
+                            device=dev)
+        plan.multislice_outputs(xy_ms[:8], optics, edges, out_ms, ws_ms)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.multislice_outputs(xy_ms, optics, edges, out_ms, ws_ms)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_multi = e0.elapsed_time(e1)
+        multi_rate = len(sub) / (ms_multi * 1e-3)
+        log(f"multislice: {len(sub)} probes in {ms_multi:.1f} ms -> {multi_rate:.1f} probes/s")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -307,8 +311,8 @@ def main():
                    "f": args.f, "grid": N, "slices": H, "probes": P,
                    "beams": geo["B"], "active_beams": geo["BA"], "window": geo["W"],
                    "tolerance": "eps_rel <= 1e-4 vs FP64 oracle (tests/test_parity_gpu.py)"},
-        "multislice_probes_per_s": round(multi_rate, 2),
-        "speedup_vs_gpu_multislice": round(value / multi_rate, 2),
+        "multislice_probes_per_s": round(multi_rate, 2) if multi_rate else None,
+        "speedup_vs_gpu_multislice": round(value / multi_rate, 2) if multi_rate else None,
         "per_f": per_f,
         "precision_variants": variants,
         "kernel_ms_per_step": kernels,
