@@ -27,6 +27,7 @@ import scipy.fft as sfft
 
 __all__ = [
     "HC_KEV_A", "ME_C2_KEV", "wavelength", "kfreq", "k2_grid", "theta_of_k2",
+    "tilt_k", "tilted_k2", "tilt_shift",
     "band_mask", "propagator", "transmission", "aperture_of_k2", "chi_of_k2",
     "detector_sums", "ScipyFFT", "DftMatrix", "slice_step", "multislice",
     "entrance_probe", "multislice_stem", "default_alpha_max", "beam_set",
@@ -96,6 +97,31 @@ def chi_of_k2(k2, lam, dq, C1, C3):
     """Aberration phase chi(q) = pi lambda q^2 C1 + (pi/2) lambda^3 q^4 C3."""
     q2 = np.asarray(k2, dtype=np.float64) * (dq * dq)
     return np.pi * lam * q2 * C1 + 0.5 * np.pi * lam ** 3 * q2 * q2 * C3
+
+
+def tilt_k(optics, lam, dq):
+    """Probe tilt as a full-grid frequency offset (kx_t, ky_t) = theta_t / (lambda dq).
+
+    The tilted probe's aperture and aberrations are centred on q_t = theta_t /
+    lambda (the paper's closing discussion: the probe centre moves away from
+    q = 0). ``optics`` keys ``tilt_x_mrad``, ``tilt_y_mrad`` (default 0).
+    """
+    lq = lam * dq
+    return (optics.get("tilt_x_mrad", 0.0) * 1e-3 / lq, optics.get("tilt_y_mrad", 0.0) * 1e-3 / lq)
+
+
+def tilted_k2(kx, ky, optics, lam, dq):
+    """|k - k_t|^2 (float64) for integer full-grid frequencies kx, ky."""
+    ktx, kty = tilt_k(optics, lam, dq)
+    dx = np.asarray(kx, dtype=np.float64) - ktx
+    dy = np.asarray(ky, dtype=np.float64) - kty
+    return dx * dx + dy * dy
+
+
+def tilt_shift(optics, height):
+    """Entrance-position offset h tan(theta_t) of the coefficient equation (Angstrom)."""
+    return (height * math.tan(optics.get("tilt_x_mrad", 0.0) * 1e-3),
+            height * math.tan(optics.get("tilt_y_mrad", 0.0) * 1e-3))
 
 
 def detector_sums(intensity, theta, edges_mrad):
@@ -179,18 +205,22 @@ def multislice(psi, phase, thickness, lam, dq, band_limit=True, fft=None):
     return psi
 
 
-def entrance_probe(n, cell, lam, optics, x0, y0, fft=None):
+def entrance_probe(n, cell, lam, optics, x0, y0, fft=None, height=0.0):
     """Incident STEM probe on the full grid, normalised to unit total intensity.
 
-    Psi_0(q) = A(q) exp(-i chi(q)) exp(-2 pi i q . r0); psi_0 = iFFT(Psi_0) n / sqrt(N_A).
+    Psi_0(q) = A(q - q_t) exp(-i chi(q - q_t)) exp(-2 pi i q . (r0 - h tan theta_t));
+    psi_0 = iFFT(Psi_0) n / sqrt(N_A). Without tilt this is the untilted probe
+    centred on r0; ``height`` h is the specimen thickness (coefficient equation).
     """
     F = _fft(fft)
     dq = 1.0 / cell
     k = kfreq(n)
-    k2 = k2_grid(n)
-    A = aperture_of_k2(k2, lam, dq, optics["alpha_mrad"] * 1e-3)
+    dk2 = tilted_k2(k[None, :], k[:, None], optics, lam, dq)
+    A = aperture_of_k2(dk2, lam, dq, optics["alpha_mrad"] * 1e-3)
     NA = int(A.sum())
-    chi = chi_of_k2(k2, lam, dq, optics.get("C1_A", 0.0), optics.get("C3_A", 0.0))
+    chi = chi_of_k2(dk2, lam, dq, optics.get("C1_A", 0.0), optics.get("C3_A", 0.0))
+    sx, sy = tilt_shift(optics, height)
+    x0, y0 = x0 - sx, y0 - sy
     shift = np.exp(-2j * np.pi * (k[None, :] * x0 + k[:, None] * y0) * dq)
     Psi0 = A * np.exp(-1j * chi) * shift
     return F.ifft2(Psi0) * (n / math.sqrt(NA))
@@ -215,7 +245,8 @@ def multislice_stem(phase, thickness, cell, energy_keV, optics, probes, edges_mr
     cbed = np.zeros((P, n, n)) if return_cbed else None
     for s in range(0, P, batch):
         pr = probes[s:s + batch]
-        psi = np.stack([entrance_probe(n, cell, lam, optics, x0, y0, F) for x0, y0 in pr])
+        psi = np.stack([entrance_probe(n, cell, lam, optics, x0, y0, F, height=float(np.sum(thickness)))
+                        for x0, y0 in pr])
         psi = multislice(psi, phase, thickness, lam, dq, band_limit, F)
         I = np.abs(F.fft2(psi)) ** 2 / float(n * n)
         out[s:s + len(pr)] = detector_sums(I, theta, edges_mrad)
@@ -302,30 +333,31 @@ def window_indices(x0, ns, w, dxs):
     return (window_origin(x0, ns, w, dxs) + np.arange(w)) % ns
 
 
-def prism_coefficients(beams, f, cell, lam, optics, x0, y0):
-    """Probe coefficients alpha_{m,n}(r0) (coefficient equation, no tilt).
+def prism_coefficients(beams, f, cell, lam, optics, x0, y0, height=0.0):
+    """Probe coefficients alpha_{m,n}(r0) (coefficient equation).
 
-    alpha = A(q) exp(-i chi(q)) exp(-2 pi i q . r0) at q = (m f dq, n f dq),
-    divided by W sqrt(B_A) so that the window probe carries unit intensity.
-    Returns (alpha complex128 [B], active bool [B]); ``W`` is applied by the
-    caller through ``prism_probe_wave``.
+    alpha = A(q - q_t) exp(-i chi(q - q_t)) exp(-2 pi i q . (r0 - h tan theta_t))
+    at q = (m f dq, n f dq) (q_t = 0 without tilt; ``height`` h is the
+    specimen thickness). Returns (alpha complex128 [B], active bool [B]); the
+    normalisation 1 / (W sqrt(B_A)) is applied through ``prism_probe_wave``.
     """
     dq = 1.0 / cell
     m = beams[:, 0].astype(np.float64)
     nn = beams[:, 1].astype(np.float64)
-    k2 = (beams[:, 0] * f) ** 2 + (beams[:, 1] * f) ** 2
-    A = aperture_of_k2(k2, lam, dq, optics["alpha_mrad"] * 1e-3)
-    chi = chi_of_k2(k2, lam, dq, optics.get("C1_A", 0.0), optics.get("C3_A", 0.0))
-    shift = np.exp(-2j * np.pi * (m * f * x0 + nn * f * y0) * dq)
+    dk2 = tilted_k2(beams[:, 0] * f, beams[:, 1] * f, optics, lam, dq)
+    A = aperture_of_k2(dk2, lam, dq, optics["alpha_mrad"] * 1e-3)
+    chi = chi_of_k2(dk2, lam, dq, optics.get("C1_A", 0.0), optics.get("C3_A", 0.0))
+    sx, sy = tilt_shift(optics, height)
+    shift = np.exp(-2j * np.pi * (m * f * (x0 - sx) + nn * f * (y0 - sy)) * dq)
     return A * np.exp(-1j * chi) * shift, A
 
 
-def prism_probe_wave(S, beams, f, cell, lam, optics, x0, y0):
+def prism_probe_wave(S, beams, f, cell, lam, optics, x0, y0, height=0.0):
     """Eq. PRISMfinal inside the Eq. RegionBounds window; returns psi [W][W] (indexed [v][u])."""
     ns = S.shape[-1]
     w = ns // f
     dxs = cell / ns
-    alpha, A = prism_coefficients(beams, f, cell, lam, optics, x0, y0)
+    alpha, A = prism_coefficients(beams, f, cell, lam, optics, x0, y0, height)
     BA = int(A.sum())
     act = np.nonzero(A)[0]                       # beams with alpha = 0 are skipped
     rows = window_indices(y0, ns, w, dxs)
@@ -336,7 +368,7 @@ def prism_probe_wave(S, beams, f, cell, lam, optics, x0, y0):
 
 
 def prism_outputs(S, beams, f, cell, energy_keV, optics, probes, edges_mrad, fft=None,
-                  return_cbed=False):
+                  return_cbed=False, height=0.0):
     """PRISM probe step: window sum, FFT, |Psi|^2 / W^2 and detector sums (Fig. 1d-f).
 
     The window's Fourier pixel is f dq, so window frequency kw maps to the
@@ -353,7 +385,7 @@ def prism_outputs(S, beams, f, cell, energy_keV, optics, probes, edges_mrad, fft
     out = np.zeros((probes.shape[0], n_det))
     cbed = np.zeros((probes.shape[0], w, w)) if return_cbed else None
     for p, (x0, y0) in enumerate(probes):
-        psi = prism_probe_wave(S, beams, f, cell, lam, optics, x0, y0)
+        psi = prism_probe_wave(S, beams, f, cell, lam, optics, x0, y0, height)
         I = np.abs(F.fft2(psi)) ** 2 / float(w * w)
         out[p] = detector_sums(I, theta, edges_mrad)
         if return_cbed:
@@ -381,7 +413,8 @@ def prism_probe_direct(phase, thickness, cell, energy_keV, f, alpha_max_mrad, op
     beams = beam_set(n, cell, lam, f, alpha_max_mrad * 1e-3)
     ns = n // 2
     w = ns // f
-    alpha, A = prism_coefficients(beams, f, cell, lam, optics, x0, y0)
+    alpha, A = prism_coefficients(beams, f, cell, lam, optics, x0, y0,
+                                  float(np.sum(thickness)))
     coef = alpha / (w * math.sqrt(int(A.sum())))
     psi0 = np.zeros((n, n), dtype=np.complex128)
     for c, (m, nn) in zip(coef, beams):

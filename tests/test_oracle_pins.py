@@ -225,6 +225,93 @@ def test_p6_prism_f1_equals_multislice():
     assert O.rel_l2(Dp, Dm) < 1e-12
 
 
+# ---------------------------------------------------------------- probe tilt
+
+def _tilted(optics, tx, ty):
+    return dict(optics, tilt_x_mrad=tx, tilt_y_mrad=ty)
+
+
+def test_tilt_empty_cell_detectors_are_shifted_aperture_fractions():
+    n, cell, E, H = 128, 12.8, 80.0, 3
+    phase, th = _empty(n, H)
+    lam = O.wavelength(E)
+    tx, ty = 7.3, -4.1
+    optics = _tilted(dict(alpha_mrad=20.0, C1_A=40.0, C3_A=1e4), tx, ty)
+    edges = [(0.0, 10.0), (10.0, 20.0), (20.0, 40.0)]
+    D = O.multislice_stem(phase, th, cell, E, optics, np.array([[3.0, 5.5]]), edges)
+    # brute force: aperture centred on the tilt, pixels binned by their own angle
+    cnt = np.zeros(3)
+    na = 0
+    for ky in range(-n // 2, n // 2):
+        for kx in range(-n // 2, n // 2):
+            if math.hypot(lam * kx / cell - tx * 1e-3, lam * ky / cell - ty * 1e-3) <= 0.020:
+                na += 1
+                a = lam * math.hypot(kx, ky) / cell * 1e3
+                cnt += [lo <= a < hi for lo, hi in edges]
+    assert np.allclose(D[0], cnt / na, atol=1e-12)
+    assert cnt[2] > 0  # the tilt pushes part of the disc beyond 20 mrad
+
+
+def test_tilt_by_whole_pixels_rolls_the_diffraction_pattern():
+    # a tilt of exactly (3, -2) Fourier pixels shifts |Psi(k)|^2 by (3, -2)
+    n, cell, E, H = 64, 12.8, 80.0, 2
+    phase, th = _empty(n, H)
+    lam = O.wavelength(E)
+    lq = lam / cell
+    o0 = dict(alpha_mrad=15.5, C1_A=25.0, C3_A=3e4)
+    ot = _tilted(o0, 3 * lq * 1e3, -2 * lq * 1e3)
+    _, c0 = O.multislice_stem(phase, th, cell, E, o0, np.array([[6.0, 6.0]]), [(0, 1)],
+                              return_cbed=True)
+    _, ct = O.multislice_stem(phase, th, cell, E, ot, np.array([[6.0, 6.0]]), [(0, 1)],
+                              return_cbed=True)
+    assert np.abs(np.roll(np.roll(c0[0], -2, axis=0), 3, axis=1) - ct[0]).max() < 1e-13
+
+
+def test_tilt_height_term_returns_exit_probe_to_r0():
+    # a tilted probe drifts by about h theta through the specimen; the
+    # coefficient equation's -h tan(theta) entrance offset brings the exit
+    # probe back to r0 (a sign error would leave it 2 h theta away)
+    n, cell, E, H = 256, 25.6, 80.0, 10
+    phase = np.zeros((H, n, n))
+    th = np.full(H, 20.0)                    # h = 200 A
+    lam = O.wavelength(E)
+    optics = _tilted(dict(alpha_mrad=20.0), 8.0, -5.0)
+    x0, y0 = 12.8, 12.8
+    psi0 = O.entrance_probe(n, cell, lam, optics, x0, y0, height=float(th.sum()))
+    ex = O.multislice(psi0, phase, th, lam, 1.0 / cell)
+    I = np.abs(ex) ** 2
+    x = np.arange(n) * cell / n
+    m = (np.abs(x - x0) < 6.0)
+    sub = I[np.ix_(m, m)]
+    cx = (sub.sum(axis=0) * x[m]).sum() / sub.sum()
+    cy = (sub.sum(axis=1) * x[m]).sum() / sub.sum()
+    assert math.hypot(cx - x0, cy - y0) < 0.1
+    # without the height term the exit probe sits about h theta away
+    psi_no = O.entrance_probe(n, cell, lam, optics, x0, y0, height=0.0)
+    I2 = np.abs(O.multislice(psi_no, phase, th, lam, 1.0 / cell)) ** 2
+    sub2 = I2[np.ix_(m, m)]
+    cx2 = (sub2.sum(axis=0) * x[m]).sum() / sub2.sum()
+    assert abs(cx2 - x0 - 200.0 * 8e-3) < 0.2
+
+
+def test_tilt_prism_f1_equals_multislice():
+    d = build_inputs("tiny", 1)
+    lam = O.wavelength(d["energy_keV"])
+    optics = _tilted(dict(alpha_mrad=18.0, C1_A=-25.0, C3_A=0.0), 4.0, 2.5)
+    probes = d["probes"][::23]
+    Dm = O.multislice_stem(d["phase"], d["thickness"], d["cell"], d["energy_keV"],
+                           optics, probes, d["edges"])
+    amax = O.default_alpha_max(0.018 + math.hypot(4.0, 2.5) * 1e-3, 1, lam, 1 / d["cell"]) * 1e3
+    beams, S = O.smatrix(d["phase"], d["thickness"], d["cell"], d["energy_keV"], 1, amax)
+    Dp = O.prism_outputs(S, beams, 1, d["cell"], d["energy_keV"], optics, probes, d["edges"],
+                         height=float(np.sum(d["thickness"])))
+    assert O.rel_l2(Dp, Dm) < 1e-12
+    # the tilt matters: the untilted result differs
+    Du = O.multislice_stem(d["phase"], d["thickness"], d["cell"], d["energy_keV"],
+                           dict(optics, tilt_x_mrad=0.0, tilt_y_mrad=0.0), probes, d["edges"])
+    assert O.rel_l2(Du, Dm) > 1e-3
+
+
 # ---------------------------------------------------------------- P7 periodised-probe identity
 
 @pytest.mark.parametrize("f", [2, 4])
