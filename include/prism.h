@@ -61,11 +61,17 @@ typedef struct {
 
 /* Probe-forming optics: hard aperture of semi-angle alpha (aperture
  * equation) and aberration phase chi = pi lambda q^2 C1 +
- * (pi/2) lambda^3 q^4 C3 (chi equation). */
+ * (pi/2) lambda^3 q^4 C3 (chi equation). Probe tilt (theta_x, theta_y):
+ * aperture and chi are centred on q_t = theta / lambda, and the position
+ * term of the coefficient equation uses r0 - h tan(theta) with h the total
+ * slice thickness, so that the exit probe is centred on r0. Zero tilt is the
+ * untilted probe. */
 typedef struct {
   double alpha_mrad;
   double C1_A;
   double C3_A;
+  double tilt_x_mrad;
+  double tilt_y_mrad;
 } prism_optics;
 
 /* Virtual detectors (Fig. 1f): bin j collects the intensity at angles
@@ -145,8 +151,8 @@ int prism_build_smatrix(prism_plan* plan, int f, double alpha_max_mrad, void* sm
  * periodic wrap), Fourier transform, and integrate |Psi|^2 / W^2 over each
  * detector bin: out_dev float64 [P][n_det]. The S-matrix must come from
  * prism_build_smatrix with the same f and alpha_max_mrad, and the probe
- * semi-angle may not exceed alpha_max_mrad (PRISM_EINVAL): every beam inside
- * the aperture must be in the set. Several optics (defocus, C3, semi-angle)
+ * semi-angle plus the tilt magnitude may not exceed alpha_max_mrad
+ * (PRISM_EINVAL): every beam inside the aperture must be in the set. Several optics (defocus, C3, semi-angle)
  * can be evaluated on one resident S-matrix. */
 int prism_probe_outputs(prism_plan* plan, int f, double alpha_max_mrad, const void* smatrix_dev,
                         const double* probe_xy_dev, int n_probes, const prism_optics* optics,
@@ -163,7 +169,8 @@ int prism_probe_cbed(prism_plan* plan, int f, double alpha_max_mrad, const void*
                      float* cbed_dev, void* ws, size_t ws_bytes, void* stream);
 
 /* Conventional multislice STEM (Eq. 5 run once per probe): incident probe
- * iFFT[A e^{-i chi} e^{-2 pi i q.r0}] n / sqrt(N_A), H slice steps,
+ * iFFT[A e^{-i chi} e^{-2 pi i q.r0}] n / sqrt(N_A) (tilt as in prism_optics),
+ * H slice steps,
  * I = |FFT psi_H|^2 / n^2 integrated per detector bin: out_dev float64
  * [P][n_det]. */
 int prism_multislice_outputs(prism_plan* plan, const double* probe_xy_dev, int n_probes,

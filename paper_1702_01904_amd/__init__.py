@@ -27,8 +27,10 @@ def _stream_ptr(stream):
 
 
 def _optics(optics):
+    """dict(alpha_mrad, C1_A=0, C3_A=0, tilt_x_mrad=0, tilt_y_mrad=0) -> prism_optics."""
     return PrismOptics(float(optics["alpha_mrad"]), float(optics.get("C1_A", 0.0)),
-                       float(optics.get("C3_A", 0.0)))
+                       float(optics.get("C3_A", 0.0)), float(optics.get("tilt_x_mrad", 0.0)),
+                       float(optics.get("tilt_y_mrad", 0.0)))
 
 
 class _Det:

@@ -37,7 +37,8 @@ class PrismGeometry(ctypes.Structure):
 
 class PrismOptics(ctypes.Structure):
     _fields_ = [("alpha_mrad", ctypes.c_double), ("C1_A", ctypes.c_double),
-                ("C3_A", ctypes.c_double)]
+                ("C3_A", ctypes.c_double), ("tilt_x_mrad", ctypes.c_double),
+                ("tilt_y_mrad", ctypes.c_double)]
 
 
 class PrismDetector(ctypes.Structure):

@@ -33,7 +33,8 @@ struct ProbeOptics {
   double dq;       // 1 / cell (1/A)
   double C1, C3;   // aberrations (A)
   double cell;     // cell side (A)
-  int k2_aperture; // largest full-grid |k|^2 inside the aperture
+  double ktx, kty; // tilt as a full-grid frequency offset: chi is taken at k - k_t
+  double sx, sy;   // entrance offset h tan(theta_t) (A): positions enter as r0 - s
   double norm;     // incident-wave normalisation factor
 };
 
@@ -46,8 +47,11 @@ hipError_t launch_prop_lut(float2* lut, int n, int H, const double* thick_dev, d
 
 hipError_t launch_beam_init(float2* state, const int32_t* beams_mn, int b0, int nb, int n, int f,
                             const float2* twN, hipStream_t st);
+// aper[ky + n/2] = (kx_lo, kx_hi): the aperture's full-grid pixels of row ky
+// (empty when kx_lo > kx_hi), decided on the host.
 hipError_t launch_probe_init(float2* state, const double* probe_xy, int p0, int np, int n,
-                             const ProbeOptics& po, const float2* twN, hipStream_t st);
+                             const ProbeOptics& po, const int2* aper, const float2* twN,
+                             hipStream_t st);
 // Four-step slice passes (n = R^2): R, or 0 where the Stockham kernels run.
 int four_step_radix(int n);
 // tw2[m][j] = exp(-2 pi i j m / n), j, m < R (n entries; nothing for R = 0).

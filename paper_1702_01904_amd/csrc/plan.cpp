@@ -92,19 +92,32 @@ struct prism_plan {
   int n = 0;
   int prec = PRISM_PREC_FP32;  // operand precision of the probe-step window sum
   double cell = 0, energy = 0, lam = 0, dq = 0;
+  double height = 0;           // total slice thickness (A)
   int H = 0;
   std::vector<double> thick;
   const float* phase = nullptr;
   std::map<std::pair<int, uint64_t>, std::vector<int32_t>> beams;  // (f, alpha_max) -> [B][2]
-  std::map<std::tuple<int, uint64_t, uint64_t>, std::vector<prism::ActiveBeam>> active;
+  std::map<std::tuple<int, uint64_t, uint64_t, uint64_t, uint64_t>, std::vector<prism::ActiveBeam>>
+      active;
   struct PixLists {
     std::vector<uint16_t> pix;
     prism::BinLists lists;
   };
   std::map<std::string, PixLists> pixlists;  // window detector bin lists
+  // multislice aperture rows per (alpha, tilt): kept here because the
+  // asynchronous copy to the device reads them after the call returns
+  std::map<std::tuple<uint64_t, uint64_t, uint64_t>, std::vector<int32_t>> aper_rows;
 
   // scattering angle (rad) of integer full-grid |k|^2
   double theta(long long k2) const { return (lam * dq) * std::sqrt((double)k2); }
+  // tilt as a full-grid frequency offset (theta_t / (lambda dq))
+  double tilt_k(double tilt_mrad) const { return tilt_mrad * 1e-3 / (lam * dq); }
+  // probe aperture test of full-grid frequency (kx, ky) for a tilted probe:
+  // (lambda dq) |k - k_t| <= alpha, the same FP64 expression as the oracle's
+  bool in_aperture(long long kx, long long ky, const prism_optics* o) const {
+    const double dx = (double)kx - tilt_k(o->tilt_x_mrad), dy = (double)ky - tilt_k(o->tilt_y_mrad);
+    return (lam * dq) * std::sqrt(dx * dx + dy * dy) <= o->alpha_mrad * 1e-3;
+  }
 
   // smallest k2 >= 0 with theta(k2) >= ang
   long long first_ge(double ang) const {
@@ -166,14 +179,51 @@ int beams_checked(const prism_plan* cp, int f, double amax_mrad, const std::vect
   return PRISM_OK;
 }
 
+// Per-row kx interval of the (tilted) aperture over full-grid rows
+// ky = -n/2 .. n/2-1, and its pixel count. A row of a disc is one interval.
+long long aperture_rows(const prism_plan* p, const prism_optics* o, std::vector<int32_t>* rows) {
+  const int n = p->n;
+  if (rows) rows->assign(2 * (size_t)n, 0);
+  const double ktx = p->tilt_k(o->tilt_x_mrad), kty = p->tilt_k(o->tilt_y_mrad);
+  const double ka = o->alpha_mrad * 1e-3 / (p->lam * p->dq);
+  long long cnt = 0;
+  for (int ky = -n / 2; ky < n / 2; ++ky) {
+    int lo = 1, hi = 0;  // empty
+    if (std::fabs(ky - kty) <= ka + 1.0) {
+      const long long x0 = (long long)std::floor(ktx - ka) - 1, x1 = (long long)std::ceil(ktx + ka) + 1;
+      for (long long kx = std::max<long long>(x0, -n / 2); kx <= std::min<long long>(x1, n / 2 - 1); ++kx)
+        if (p->in_aperture(kx, ky, o)) {
+          if (lo > hi) lo = hi = (int)kx;
+          else hi = (int)kx;
+          ++cnt;
+        }
+    }
+    if (rows) {
+      (*rows)[2 * (size_t)(ky + n / 2)] = lo;
+      (*rows)[2 * (size_t)(ky + n / 2) + 1] = hi;
+    }
+  }
+  return cnt;
+}
+
 int check_optics(const prism_plan* p, const prism_optics* o) {
   if (!o) return fail(PRISM_EINVAL, "null optics");
   if (!(o->alpha_mrad > 0.0) || !std::isfinite(o->alpha_mrad) || !std::isfinite(o->C1_A) ||
-      !std::isfinite(o->C3_A))
-    return fail(PRISM_EINVAL, "optics: alpha must be positive, C1/C3 finite");
-  const long long k2ap = p->last_le(o->alpha_mrad * 1e-3);
-  if (16 * k2ap >= (long long)p->n * p->n)
+      !std::isfinite(o->C3_A) || !std::isfinite(o->tilt_x_mrad) || !std::isfinite(o->tilt_y_mrad))
+    return fail(PRISM_EINVAL, "optics: alpha must be positive; C1, C3 and tilt finite");
+  // every aperture pixel strictly inside the half-band limit |k| < n/4 (the
+  // compact wave state stores nothing beyond it)
+  const double ktx = p->tilt_k(o->tilt_x_mrad), kty = p->tilt_k(o->tilt_y_mrad);
+  const double ka = o->alpha_mrad * 1e-3 / (p->lam * p->dq);
+  if (std::hypot(ktx, kty) + ka >= p->n / 4.0 + 2.0)
     return fail(PRISM_EINVAL, "probe aperture must lie inside the half-band anti-aliasing limit");
+  const long long n2 = (long long)p->n * p->n;
+  const long long y0 = (long long)std::floor(kty - ka) - 1, y1 = (long long)std::ceil(kty + ka) + 1;
+  const long long x0 = (long long)std::floor(ktx - ka) - 1, x1 = (long long)std::ceil(ktx + ka) + 1;
+  for (long long ky = y0; ky <= y1; ++ky)
+    for (long long kx = x0; kx <= x1; ++kx)
+      if (p->in_aperture(kx, ky, o) && 16 * (kx * kx + ky * ky) >= n2)
+        return fail(PRISM_EINVAL, "probe aperture must lie inside the half-band anti-aliasing limit");
   return PRISM_OK;
 }
 
@@ -200,32 +250,26 @@ prism::ProbeOptics probe_optics(const prism_plan* p, const prism_optics* o) {
   po.C1 = o->C1_A;
   po.C3 = o->C3_A;
   po.cell = p->cell;
-  po.k2_aperture = (int)p->last_le(o->alpha_mrad * 1e-3);
+  po.ktx = p->tilt_k(o->tilt_x_mrad);
+  po.kty = p->tilt_k(o->tilt_y_mrad);
+  po.sx = p->height * std::tan(o->tilt_x_mrad * 1e-3);
+  po.sy = p->height * std::tan(o->tilt_y_mrad * 1e-3);
   po.norm = 1.0;
   return po;
 }
 
-long long aperture_pixels(const prism_plan* p, long long k2ap) {
-  const int n = p->n;
-  long long cnt = 0;
-  for (int ky = -n / 2; ky < n / 2; ++ky)
-    for (int kx = -n / 2; kx < n / 2; ++kx)
-      if ((long long)kx * kx + (long long)ky * ky <= k2ap) ++cnt;
-  return cnt;
-}
-
+// Beams of the set inside the (tilted) probe aperture.
 const std::vector<prism::ActiveBeam>* get_active(prism_plan* p, int f, double amax_mrad,
-                                                 const std::vector<int32_t>& mn, double alpha_mrad) {
-  const auto key = std::make_tuple(f, dbits(amax_mrad), dbits(alpha_mrad));
+                                                 const std::vector<int32_t>& mn,
+                                                 const prism_optics* o) {
+  const auto key = std::make_tuple(f, dbits(amax_mrad), dbits(o->alpha_mrad),
+                                   dbits(o->tilt_x_mrad), dbits(o->tilt_y_mrad));
   auto it = p->active.find(key);
   if (it != p->active.end()) return &it->second;
   std::vector<prism::ActiveBeam> act;
-  const double a = alpha_mrad * 1e-3;
-  for (size_t b = 0; b < mn.size() / 2; ++b) {
-    const long long k2 = (long long)(mn[2 * b] * f) * (mn[2 * b] * f) +
-                         (long long)(mn[2 * b + 1] * f) * (mn[2 * b + 1] * f);
-    if (p->theta(k2) <= a) act.push_back(prism::ActiveBeam{(int)b, mn[2 * b], mn[2 * b + 1]});
-  }
+  for (size_t b = 0; b < mn.size() / 2; ++b)
+    if (p->in_aperture((long long)mn[2 * b] * f, (long long)mn[2 * b + 1] * f, o))
+      act.push_back(prism::ActiveBeam{(int)b, mn[2 * b], mn[2 * b + 1]});
   return &(p->active[key] = std::move(act));
 }
 
@@ -277,6 +321,7 @@ struct SliceWs {
   float2* prop;
   float2* trans;
   int32_t* mn;
+  int2* aper;      // multislice: aperture kx interval per full-grid row
   float2* state;
   double* partial;
 };
@@ -291,6 +336,7 @@ size_t slice_layout(const prism_plan* p, int chunk, int n_beams, int n_det, Slic
   w->prop = c.take<float2>((size_t)p->H * n);
   w->trans = c.take<float2>((size_t)p->H * n * n);
   w->mn = c.take<int32_t>(2 * (size_t)std::max(n_beams, 0));
+  w->aper = c.take<int2>(n_det > 0 ? (size_t)n : 0);
   w->state = c.take<float2>((size_t)chunk * n * (n / 2));
   w->partial = c.take<double>((size_t)chunk * prism::col_tiles(n) * std::max(n_det, 0));
   return c.used + 256;
@@ -405,15 +451,15 @@ int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, const doub
   if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
   if (P < 0) return fail(PRISM_EINVAL, "negative probe count");
   if (int r = check_optics(p, o)) return r;
-  if (o->alpha_mrad > amax_mrad)
-    return fail(PRISM_EINVAL, "probe semi-angle exceeds the beam set's alpha_max");
+  if (o->alpha_mrad + std::hypot(o->tilt_x_mrad, o->tilt_y_mrad) > amax_mrad)
+    return fail(PRISM_EINVAL, "probe semi-angle plus tilt exceeds the beam set's alpha_max");
   const bool want_cbed = d == nullptr;
   prism::DetBins bins{};
   if (!want_cbed)
     if (int r = make_bins(p, d, &bins)) return r;
   const int n = p->n, ns = n / 2, w = n / (2 * f);
   if (!is_pow2(w) || w < 8 || w > 256) return fail(PRISM_EINVAL, "window side n/(2f) must be 8..256");
-  const auto* act = get_active(p, f, amax_mrad, *mn, o->alpha_mrad);
+  const auto* act = get_active(p, f, amax_mrad, *mn, o);
   const int n_act = (int)act->size();
   if (n_act < 1) return fail(PRISM_EINVAL, "no beam of the set lies inside the probe aperture");
   if (P == 0) return PRISM_OK;
@@ -527,6 +573,7 @@ int prism_plan_create(prism_plan** out, const prism_geometry* g) {
   p->dq = 1.0 / g->cell_A;
   p->H = g->n_slices;
   p->thick.assign(g->slice_thickness_A, g->slice_thickness_A + g->n_slices);
+  for (double t : p->thick) p->height += t;
   *out = p;
   return PRISM_OK;
 }
@@ -606,7 +653,7 @@ int prism_probe_workspace_bytes(const prism_plan* cp, int f, double amax_mrad,
   if (int r = check_optics(p, o)) return r;
   const int w = p->n / (2 * f);
   if (!is_pow2(w) || w < 8 || w > 256) return fail(PRISM_EINVAL, "window side n/(2f) must be 8..256");
-  const auto* act = get_active(p, f, amax_mrad, *mn, o->alpha_mrad);
+  const auto* act = get_active(p, f, amax_mrad, *mn, o);
   const int G = prism::contract_group(w);
   ProbeWs pw;
   const int ns = p->n / 2;
@@ -717,13 +764,20 @@ int prism_multislice_outputs(prism_plan* p, const double* xy, int P, const prism
   SliceWs w;
   slice_layout(p, chunk, 0, bins.n, &w, base);
   prism::ProbeOptics po = probe_optics(p, o);
-  po.norm = 1.0 / std::sqrt((double)aperture_pixels(p, po.k2_aperture));
+  std::vector<int32_t>& rows = p->aper_rows[std::make_tuple(
+      dbits(o->alpha_mrad), dbits(o->tilt_x_mrad), dbits(o->tilt_y_mrad))];
+  const long long n_ap = aperture_rows(p, o, &rows);
+  if (n_ap < 1) return fail(PRISM_EINVAL, "the probe aperture holds no grid frequency");
+  po.norm = 1.0 / std::sqrt((double)n_ap);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (int r = prepare_slices(p, w, st)) return r;
+  HIP_TRY(hipMemcpyAsync(w.aper, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                         st),
+          "copy aperture rows");
   const int tiles = prism::col_tiles(n);
   for (int p0 = 0; p0 < P; p0 += chunk) {
     const int np = std::min(chunk, P - p0);
-    LAUNCH(p, st, "probe_init", prism::launch_probe_init(w.state, xy, p0, np, n, po, w.twN, st));
+    LAUNCH(p, st, "probe_init", prism::launch_probe_init(w.state, xy, p0, np, n, po, w.aper, w.twN, st));
     for (int s = 0; s < p->H; ++s) {
       LAUNCH(p, st, "row_pass", prism::launch_row_pass(w.state, np, n, w.trans + (size_t)s * n * n, w.twN, w.tw2, st));
       if (s + 1 < p->H) {

@@ -143,9 +143,10 @@ __global__ void k_alpha16(const double* __restrict__ probe_xy, int p0, int np,
                             wrap_mod16((long long)cy - w / 2, ns));
     }
     const double kx = (double)act[a].m * f, ky = (double)act[a].n * f;
-    const double q2 = (kx * kx + ky * ky) * (po.dq * po.dq);
+    const double dx = kx - po.ktx, dy = ky - po.kty;
+    const double q2 = (dx * dx + dy * dy) * (po.dq * po.dq);
     double t = -(0.5 * po.lam * q2 * po.C1 + 0.25 * po.lam * po.lam * po.lam * q2 * q2 * po.C3) -
-               (kx * x0 + ky * y0) * po.dq;
+               (kx * (x0 - po.sx) + ky * (y0 - po.sy)) * po.dq;
     t -= floor(t);
     double s, c;
     sincospi(2.0 * t, &s, &c);

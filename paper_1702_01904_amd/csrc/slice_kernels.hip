@@ -543,12 +543,15 @@ void k_col_pass(float2* __restrict__ state, const float2* __restrict__ prop,
 // ---------------------------------------------------------------------------
 // Incident multislice probe, built per compact column in Fourier space and
 // brought to X(y, kx) by an inverse FFT along y:
-//   X0(y, kx) = norm * sum_ky A e^{-i chi} e^{-2 pi i q.r0} e^{2 pi i ky y / n}
-// with norm = 1 / sqrt(N_A). Phases are evaluated in FP64.
+//   X0(y, kx) = norm * sum_ky A e^{-i chi} e^{-2 pi i q.(r0 - s)} e^{2 pi i ky y / n}
+// with norm = 1 / sqrt(N_A), chi at k - k_t and s the tilt's entrance offset.
+// The aperture comes as one kx interval per row (decided on the host).
+// Phases are evaluated in FP64.
 template <int N>
 __global__ __launch_bounds__(col_nt(N)) void k_probe_init(float2* __restrict__ state,
                                                           const double* __restrict__ probe_xy,
                                                           int p0, ProbeOptics po,
+                                                          const int2* __restrict__ aper,
                                                           const float2* __restrict__ twN) {
   constexpr int TC = col_tc(N), NT = col_nt(N);
   constexpr int H2 = N / 2, Q = N / 4;
@@ -559,7 +562,8 @@ __global__ __launch_bounds__(col_nt(N)) void k_probe_init(float2* __restrict__ s
   const int tid = threadIdx.x;
   const int tile = blockIdx.x;
   const int w = tile / TILES, c0 = (tile % TILES) * TC;
-  const double x0 = probe_xy[2 * (size_t)(p0 + w)], y0 = probe_xy[2 * (size_t)(p0 + w) + 1];
+  const double x0 = probe_xy[2 * (size_t)(p0 + w)] - po.sx;
+  const double y0 = probe_xy[2 * (size_t)(p0 + w) + 1] - po.sy;
   load_twiddles<N, NT>(tw, twN, tid);
   const double dq2 = po.dq * po.dq;
   for (int e = tid; e < TC * N; e += NT) {
@@ -567,10 +571,11 @@ __global__ __launch_bounds__(col_nt(N)) void k_probe_init(float2* __restrict__ s
     const int jj = c0 + c;
     const int kx = jj < Q ? jj : jj - H2;
     const int ky = signed_k(y, N);
-    const int k2 = kx * kx + ky * ky;
+    const int2 row = aper[ky + N / 2];
     float2 v = make_float2(0.f, 0.f);
-    if (k2 <= po.k2_aperture) {
-      const double q2 = (double)k2 * dq2;
+    if (kx >= row.x && kx <= row.y) {
+      const double dx = (double)kx - po.ktx, dy = (double)ky - po.kty;
+      const double q2 = (dx * dx + dy * dy) * dq2;
       double t = -(0.5 * po.lam * q2 * po.C1 + 0.25 * po.lam * po.lam * po.lam * q2 * q2 * po.C3) -
                  ((double)kx * x0 + (double)ky * y0) * po.dq;
       t -= floor(t);
@@ -759,10 +764,11 @@ hipError_t launch_col_detect(const float2* state, int nwaves, int n, const float
 }
 
 hipError_t launch_probe_init(float2* state, const double* probe_xy, int p0, int np, int n,
-                             const ProbeOptics& po, const float2* twN, hipStream_t st) {
+                             const ProbeOptics& po, const int2* aper, const float2* twN,
+                             hipStream_t st) {
 #define PINIT(NN)                                                                                \
   hipLaunchKernelGGL(k_probe_init<NN>, dim3((unsigned)(np * col_tiles(NN))), dim3(col_nt(NN)), 0, \
-                     st, state, probe_xy, p0, po, twN)
+                     st, state, probe_xy, p0, po, aper, twN)
   PRISM_DISPATCH_N(n, PINIT)
 #undef PINIT
   return hipGetLastError();

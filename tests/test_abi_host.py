@@ -195,6 +195,19 @@ def test_errors_before_any_launch():
     r = Lb.prism_probe_outputs(hb, 1, amax1, dummy, dummy, 4, ctypes.byref(optics),
                                ctypes.byref(det), dummy, dummy, 1 << 30, None)
     assert r == _native.PRISM_EINVAL and b"window" in Lb.prism_last_error()
+    # tilt: aperture pushed across the half-band limit (104 mrad at 80 keV)
+    tilted = _native.PrismOptics(20.0, 0.0, 0.0, 90.0, 0.0)
+    assert L.prism_multislice_outputs(h, dummy, 4, ctypes.byref(tilted), ctypes.byref(det), dummy,
+                                      dummy, 1 << 30, None) == _native.PRISM_EINVAL
+    assert b"half-band" in L.prism_last_error()
+    # tilt: semi-angle + tilt beyond the beam set's alpha_max
+    t5 = _native.PrismOptics(20.0, 0.0, 0.0, 3.0, 4.0)
+    r = L.prism_probe_outputs(h, 2, 24.0, dummy, dummy, 4, ctypes.byref(t5), ctypes.byref(det),
+                              dummy, dummy, 1 << 30, None)
+    assert r == _native.PRISM_EINVAL and b"tilt" in L.prism_last_error()
+    nan_tilt = _native.PrismOptics(20.0, 0.0, 0.0, float("nan"), 0.0)
+    assert L.prism_multislice_outputs(h, dummy, 4, ctypes.byref(nan_tilt), ctypes.byref(det),
+                                      dummy, dummy, 1 << 30, None) == _native.PRISM_EINVAL
     # probe step: semi-angle beyond the beam set's alpha_max
     wider = _native.PrismOptics(amax + 1.0, 0.0, 0.0)
     r = L.prism_probe_outputs(h, 2, amax, dummy, dummy, 4, ctypes.byref(wider), ctypes.byref(det),

@@ -168,6 +168,34 @@ def test_optics_sweep_on_resident_smatrix(tiny):
         assert e <= TOL
 
 
+def test_tilted_probe_multislice_and_prism_tiny(tiny):
+    # probe tilt (aperture and chi centred on the tilt, entrance offset
+    # h tan(theta)): multislice and PRISM f = 1, 2 against the oracle, and
+    # PRISM f = 1 against the GPU multislice
+    d, plan = tiny
+    optics = dict(alpha_mrad=18.0, C1_A=-25.0, C3_A=1e4, tilt_x_mrad=4.0, tilt_y_mrad=2.5)
+    h = float(np.sum(d["thickness"]))
+    pr = d["probes"][::9]
+    Dm = G.multislice_outputs(plan, pr, optics, d["edges"])
+    ref_m = O.multislice_stem(d["phase"], d["thickness"], d["cell"], d["energy_keV"], optics, pr,
+                              d["edges"])
+    e = eps(Dm, ref_m)
+    print(f"tilt multislice tiny eps_rel={e:.3e}")
+    assert e <= TOL
+    for f in (1, 2):
+        amax = _amax(d, f, alpha_mrad=18.0 + np.hypot(4.0, 2.5))
+        S = G.build_smatrix(plan, f, amax)
+        D = G.probe_outputs(plan, f, amax, S, pr, optics, d["edges"])
+        beams, Sref = O.smatrix(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax)
+        ref = O.prism_outputs(Sref, beams, f, d["cell"], d["energy_keV"], optics, pr, d["edges"],
+                              height=h)
+        e = eps(D, ref)
+        print(f"tilt prism tiny f={f} eps_rel={e:.3e}")
+        assert e <= TOL
+        if f == 1:
+            assert eps(D, Dm) <= TOL
+
+
 def test_prism_f1_equals_gpu_multislice(tiny):
     # P6 re-run on GPU outputs only
     d, plan = tiny
