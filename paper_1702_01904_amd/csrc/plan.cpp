@@ -81,7 +81,14 @@ struct prism_plan {
     }
     return e;
   }
+  // second stream of the S-matrix build (created on first use, default
+  // priority) and the events that fork it from and join it to the caller's
+  hipStream_t aux = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   ~prism_plan() {
+    if (aux) (void)hipStreamDestroy(aux);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (join_ev) (void)hipEventDestroy(join_ev);
     for (auto& r : prof) {
       if (r.start) (void)hipEventDestroy(r.start);
       if (r.stop) (void)hipEventDestroy(r.stop);
@@ -716,6 +723,10 @@ int prism_set_potential_slices(prism_plan* p, const float* phase_dev) {
   return PRISM_OK;
 }
 
+#ifndef PRISM_BUILD_STREAMS
+#define PRISM_BUILD_STREAMS 2
+#endif
+
 int prism_build_smatrix(prism_plan* p, int f, double amax_mrad, void* S, void* ws, size_t ws_bytes,
                         void* stream) {
   const std::vector<int32_t>* mn;
@@ -734,14 +745,39 @@ int prism_build_smatrix(prism_plan* p, int f, double amax_mrad, void* S, void* w
           "copy beam list");
   float2* Sout = static_cast<float2*>(S);
   const size_t splane = (size_t)(n / 2) * (n / 2);
-  for (int b0 = 0; b0 < B; b0 += chunk) {
-    const int nb = std::min(chunk, B - b0);
-    LAUNCH(p, st, "beam_init", prism::launch_beam_init(w.state, w.mn, b0, nb, n, f, w.twN, st));
+  // Small builds (at most two chunks of beams, so single launches leave the
+  // GPU partly idle) run in two lanes: the state buffer is split in two and
+  // alternate beam groups run on the caller's stream and on the plan's
+  // second stream, so that one group's VALU-heavy row pass overlaps the
+  // other's memory-bound column pass. Larger builds keep one lane, where
+  // every launch fills the GPU and kernel timings stay exclusive.
+  const int lanes =
+      (PRISM_BUILD_STREAMS > 1 && chunk >= 2 && B > chunk / 2 && B <= 2 * chunk) ? 2 : 1;
+  const int sub = chunk / lanes;
+  hipStream_t ls[2] = {st, st};
+  if (lanes == 2) {
+    if (!p->aux) HIP_TRY(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking), "create build stream");
+    if (!p->fork_ev) HIP_TRY(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming), "create event");
+    if (!p->join_ev) HIP_TRY(hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming), "create event");
+    ls[1] = p->aux;
+    HIP_TRY(hipEventRecord(p->fork_ev, st), "fork build stream");
+    HIP_TRY(hipStreamWaitEvent(p->aux, p->fork_ev, 0), "fork build stream");
+  }
+  int g = 0;
+  for (int b0 = 0; b0 < B; b0 += sub, ++g) {
+    const int nb = std::min(sub, B - b0);
+    hipStream_t sg = ls[g % lanes];
+    float2* state = w.state + (size_t)(g % lanes) * sub * n * (n / 2);
+    LAUNCH(p, sg, "beam_init", prism::launch_beam_init(state, w.mn, b0, nb, n, f, w.twN, sg));
     for (int s = 0; s < p->H; ++s) {
-      LAUNCH(p, st, "row_pass", prism::launch_row_pass(w.state, nb, n, w.trans + (size_t)s * n * n, w.twN, w.tw2, st));
-      LAUNCH(p, st, "col_pass", prism::launch_col_pass(w.state, nb, n, w.prop + (size_t)s * n, w.twN, w.tw2, st));
+      LAUNCH(p, sg, "row_pass", prism::launch_row_pass(state, nb, n, w.trans + (size_t)s * n * n, w.twN, w.tw2, sg));
+      LAUNCH(p, sg, "col_pass", prism::launch_col_pass(state, nb, n, w.prop + (size_t)s * n, w.twN, w.tw2, sg));
     }
-    LAUNCH(p, st, "extract", prism::launch_extract(w.state, nb, n, Sout + (size_t)b0 * splane, w.twH, st));
+    LAUNCH(p, sg, "extract", prism::launch_extract(state, nb, n, Sout + (size_t)b0 * splane, w.twH, sg));
+  }
+  if (lanes == 2) {
+    HIP_TRY(hipEventRecord(p->join_ev, p->aux), "join build stream");
+    HIP_TRY(hipStreamWaitEvent(st, p->join_ev, 0), "join build stream");
   }
   return PRISM_OK;
 }

@@ -243,6 +243,19 @@ def test_small_workspaces_give_same_results(tiny):
     assert eps(M_min, M_pref) <= 1e-6
 
 
+def test_two_lane_build_equals_one_lane(tiny):
+    # a workspace of ~40 waves for the 49 beams at f = 2 gives two lanes (two
+    # streams, alternate beam groups); every beam's arithmetic is the same as
+    # in the one-lane build, so S agrees bit for bit
+    d, plan = tiny
+    f = 2
+    amax = _amax(d, f)
+    S_one = G.build_smatrix(plan, f, amax)
+    _, mn = plan.build_workspace_bytes(f, amax)
+    S_two = G.build_smatrix(plan, f, amax, ws_bytes=mn + 39 * 128 * 64 * 8)
+    assert np.array_equal(S_two.cpu().numpy(), S_one.cpu().numpy())
+
+
 def test_empty_cell_closed_forms_tiny():
     d = build_inputs("tiny", 0)
     d["phase"] = np.zeros_like(d["phase"])
