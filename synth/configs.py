@@ -44,6 +44,18 @@ CONFIGS = {
         detectors=[(0.0, 20.0), (20.0, 40.0), (40.0, 80.0), (80.0, 150.0)],
         f_values=(1, 2, 4),
     ),
+    # 512^2 case (the radix-8/2 Stockham slice kernels, windows of 128 and
+    # 64 at f = 2 and 4); sampled against one-probe oracle runs.
+    "s512": dict(
+        specimen=dict(kind="random", cell=(51.2, 51.2, 12.0), n_atoms=400,
+                      z_choices=(6, 14, 29, 79)),
+        n=512, n_slices=6, slice_A=2.0,
+        energy_keV=80.0,
+        optics=dict(alpha_mrad=20.0, C1_A=10.0, C3_A=0.0),
+        scan=dict(nx=24, ny=24, step_A=0.2, origin_A=(20.0, 20.0)),
+        detectors=[(0.0, 20.0), (20.0, 50.0), (50.0, 100.0)],
+        f_values=(2, 4),
+    ),
     # Precision case (nanoparticle on an amorphous carbon slab, 2048^2).
     "np2048": dict(
         specimen=dict(kind="np_on_carbon", cell=(80.0, 80.0, 70.0),

@@ -331,6 +331,62 @@ def test_prism_mid_ragged_16bit(mid, f, prec):
     assert e <= TOL16
 
 
+@pytest.mark.parametrize("f", [8, 16])
+def test_prism_mid_small_windows(mid, f):
+    # W = 16 and 8: the smallest windows (G = 16 probes per group)
+    d, plan = mid
+    amax = _amax(d, f)
+    S = G.build_smatrix(plan, f, amax)
+    beams, Sref = O.smatrix(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax)
+    ref = O.prism_outputs(Sref, beams, f, d["cell"], d["energy_keV"], d["optics"], d["probes"],
+                          d["edges"])
+    D = G.probe_outputs(plan, f, amax, S, d["probes"], d["optics"], d["edges"])
+    e = eps(D, ref)
+    print(f"prism mid f={f} W={plan.n // (2 * f)} eps_rel={e:.3e}")
+    assert e <= TOL
+    D16 = _outputs_at(plan, "bf16", f, amax, S, d["probes"], d["optics"], d["edges"])
+    assert eps(D16, ref) <= TOL16
+
+
+# ------------------------------------------------------------------ 512^2 (Stockham slice kernels)
+
+@pytest.fixture(scope="module")
+def s512():
+    d = build_inputs("s512", 0)
+    plan = G.make_plan(d)
+    return d, plan
+
+
+def test_s512_multislice_sampled(s512):
+    d, plan = s512
+    pr = d["probes"][[0, 301]]
+    D = G.multislice_outputs(plan, pr, d["optics"], d["edges"])
+    ref = O.multislice_stem(d["phase"], d["thickness"], d["cell"], d["energy_keV"], d["optics"],
+                            pr, d["edges"])
+    e = eps(D, ref)
+    print(f"s512 multislice eps_rel={e:.3e}")
+    assert e <= TOL
+
+
+@pytest.mark.parametrize("f", [2, 4])
+def test_s512_prism_scan_sampled(s512, f):
+    # W = 128 (G = 64) and W = 64 (G = 32) on the whole 24 x 24 scan in tile
+    # order, three probes against one-probe oracle runs
+    d, plan = s512
+    amax = _amax(d, f)
+    S = G.build_smatrix(plan, f, amax)
+    _, tx, ty = plan.probe_group(f)
+    perm = tile_order(24, 24, tx, ty)
+    D = untile(G.probe_outputs(plan, f, amax, S, d["probes"][perm], d["optics"], d["edges"]), perm)
+    for p in (0, 300, 575):
+        x0, y0 = d["probes"][p]
+        ref = O.prism_probe_direct(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax,
+                                   d["optics"], x0, y0, d["edges"])
+        e = eps(D[p], ref)
+        print(f"s512 prism f={f} probe {p} eps_rel={e:.3e}")
+        assert e <= TOL
+
+
 # ------------------------------------------------------------------ full-size headline case
 
 @pytest.fixture(scope="module")
