@@ -90,10 +90,15 @@ int contract_group(int w);
 int contract_tile_slots(int w);
 
 // Low-precision probe step (BF16 or FP16 operands, FP32 accumulation).
-enum class Prec { kBF16 = 1, kFP16 = 2 };
-constexpr int kC16KB = 32;  // beams per K block of the 16-bit contraction
-// Beam rows of the packed 16-bit S-matrix are padded to a multiple of this.
-constexpr int kC16BeamPad = 2 * kC16KB;
+// Operand forms of the packed window sum: 16-bit (BF16, FP16; one 32-bit
+// word per complex value, 32 beams per K block) or FP32 (two words per
+// value, 16 beams per K block). A K block is 128 bytes of a pixel row.
+enum class Prec { kBF16 = 1, kFP16 = 2, kF32 = 3 };
+constexpr int kC16KB = 32;  // 32-bit words per K block row
+__host__ __device__ constexpr int prec_block_beams(Prec p) { return p == Prec::kF32 ? 16 : 32; }
+__host__ __device__ constexpr int prec_words(Prec p) { return p == Prec::kF32 ? 2 : 1; }
+// Beam rows of the packed S-matrix are padded to a whole pair of K blocks.
+__host__ __device__ constexpr int prec_beam_pad(Prec p) { return 2 * prec_block_beams(p); }
 // scale[a] = 2^-e with e the smallest integer such that every |Re|, |Im| of
 // active beam a's plane is < 2^e (1 for an all-zero plane).
 hipError_t launch_s16_scale(const float2* smatrix, const ActiveBeam* act, int n_act, int ns,

@@ -362,16 +362,29 @@ struct ProbeWs {
   prism::ActiveBeam* act;
   float2* alpha;    // FP32: [n_act][chunk]
   float* scale;     // 16-bit: [n_act] power-of-two beam scales
-  uint32_t* s16;    // 16-bit: [ns^2][n_actp] (re, im) pairs
-  uint32_t* a16;    // 16-bit: [chunk / G][n_actp / 32][2G][32] (pairs)
+  uint32_t* s16;    // packed S: [ns^2][n_actp] (re, im), one word (16-bit) or two (FP32)
+  uint32_t* a16;    // packed alpha: [chunk / G][K blocks][2G][32 words]
   int2* origin;
   float2* window;
   double* partial;  // W = 256: [chunk][tiles][PRISM_MAX_DET] detector partials
 };
 
-// Active beams padded to whole pairs of 16-bit K blocks.
-int padded_beams(int n_act) {
-  return (n_act + prism::kC16BeamPad - 1) / prism::kC16BeamPad * prism::kC16BeamPad;
+#ifndef PRISM_F32_PACKED
+#define PRISM_F32_PACKED 1  // FP32 window sum on the packed layout (else beam-major k_contract)
+#endif
+
+// Operand form of the packed window sum for a plan precision (FP32 packed
+// unless the beam-major kernel is selected at build time).
+bool packed_path(int prec) { return prec != PRISM_PREC_FP32 || PRISM_F32_PACKED; }
+prism::Prec packed_prec(int prec) {
+  return prec == PRISM_PREC_BF16 ? prism::Prec::kBF16
+                                 : (prec == PRISM_PREC_FP16 ? prism::Prec::kFP16 : prism::Prec::kF32);
+}
+
+// Active beams padded to a whole pair of K blocks.
+int padded_beams(int n_act, prism::Prec pk) {
+  const int pad = prism::prec_beam_pad(pk);
+  return (n_act + pad - 1) / pad * pad;
 }
 
 size_t probe_layout(int w, int ns, int n_act, int chunk, int prec, ProbeWs* pw, void* base) {
@@ -380,16 +393,18 @@ size_t probe_layout(int w, int ns, int n_act, int chunk, int prec, ProbeWs* pw, 
   // per-bin pixel lists (W <= 128), worst case: overlapping bins
   pw->pix = c.take<uint16_t>(w == 256 ? 0 : (size_t)PRISM_MAX_DET * w * w);
   pw->act = c.take<prism::ActiveBeam>(n_act);
-  if (prec == PRISM_PREC_FP32) {
+  if (!packed_path(prec)) {
     pw->alpha = c.take<float2>((size_t)chunk * n_act);
     pw->scale = nullptr;
     pw->s16 = pw->a16 = nullptr;
   } else {
-    const int n_actp = padded_beams(n_act);
+    const prism::Prec pk = packed_prec(prec);
+    const int n_actp = padded_beams(n_act, pk);
     pw->alpha = nullptr;
-    pw->scale = c.take<float>(n_act);
-    pw->s16 = c.take<uint32_t>((size_t)ns * ns * n_actp);
-    pw->a16 = c.take<uint32_t>((size_t)chunk * n_actp * 2);
+    pw->scale = pk == prism::Prec::kF32 ? nullptr : c.take<float>(n_act);
+    pw->s16 = c.take<uint32_t>((size_t)ns * ns * n_actp * prism::prec_words(pk));
+    // per probe: n_actp / KB blocks x 2 rows x 32 words
+    pw->a16 = c.take<uint32_t>((size_t)chunk * (n_actp / prism::prec_block_beams(pk)) * 64);
   }
   pw->origin = c.take<int2>(chunk);
   pw->window = c.take<float2>((size_t)chunk * w * w);
@@ -520,19 +535,21 @@ int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, const doub
     }
     return PRISM_OK;
   };
-  if (prec != PRISM_PREC_FP32) {
-    const prism::Prec pr = prec == PRISM_PREC_BF16 ? prism::Prec::kBF16 : prism::Prec::kFP16;
-    const int n_actp = padded_beams(n_act);
+  if (packed_path(prec)) {
+    const prism::Prec pr = packed_prec(prec);
+    const int n_actp = padded_beams(n_act, pr);
     const float out_scale = (float)po.norm;
     po.norm = 1.0;
-    LAUNCH(p, st, "s16_scale", prism::launch_s16_scale(Sd, pw.act, n_act, ns, pw.scale, st));
-    LAUNCH(p, st, "s16_pack", prism::launch_s16_pack(Sd, pw.act, n_act, n_actp, ns, pw.scale, pw.s16, pr, st));
+    if (pr != prism::Prec::kF32)
+      LAUNCH(p, st, "s16_scale", prism::launch_s16_scale(Sd, pw.act, n_act, ns, pw.scale, st));
+    LAUNCH(p, st, pr == prism::Prec::kF32 ? "s32_pack" : "s16_pack",
+           prism::launch_s16_pack(Sd, pw.act, n_act, n_actp, ns, pw.scale, pw.s16, pr, st));
     for (int p0 = 0; p0 < P; p0 += chunk) {
       const int np = std::min(chunk, P - p0);
-      LAUNCH(p, st, "alpha16",
+      LAUNCH(p, st, pr == prism::Prec::kF32 ? "alpha" : "alpha16",
              prism::launch_alpha16(xy, p0, np, pw.act, n_act, n_actp, f, ns, w, po, pw.scale, G,
                                    pw.a16, pw.origin, pr, st));
-      LAUNCH(p, st, "contract16",
+      LAUNCH(p, st, pr == prism::Prec::kF32 ? "contract" : "contract16",
              prism::launch_contract16(pw.s16, n_actp, pw.a16, pw.origin, np, ns, w, G, out_scale,
                                       pw.window, pr, st));
       if (int r = window_stage(np, p0)) return r;

@@ -1,7 +1,7 @@
-// PRISM probe step with 16-bit (BF16 or FP16) MFMA operands and FP32
-// accumulation: the same window sum as probe_kernels.hip (Eq. PRISMfinal
-// over the window of Eq. RegionBounds), for callers that accept the
-// rounding of the operands to 16 bits.
+// PRISM window sum (Eq. PRISMfinal over the window of Eq. RegionBounds) on
+// a packed, pixel-major copy of the active beams of S: with 16-bit (BF16 or
+// FP16) operands for callers that accept their rounding, or with FP32
+// operands. Accumulation is FP32 in both.
 //
 //  * Every active beam plane S_a is multiplied by an exact power of two
 //    scale[a] that brings its largest component below 1, and alpha_a is
@@ -14,6 +14,11 @@
 //    (rows 2g: (Re, -Im), rows 2g+1: (Im, Re)) per probe group and K block.
 //  * v_mfma_f32_16x16x32_{bf16,f16}: lane l holds A[l%16][8(l/16)+j],
 //    B[8(l/16)+j][l%16] (j < 8) and D[4(l/16)+i][l%16] (i < 4).
+//  * FP32: a K block is 16 beams (the same 128 bytes per row). Each lane
+//    reads 16 bytes = 4 K' values and feeds four v_mfma_f32_16x16x4f32
+//    steps; K' is visited as 4 (l/16) + 16 ks + s on both operands, a
+//    permutation of the block's 32 real K' indices, so the sum is the same.
+//    The scale is 1.
 //  * The 1 / (W sqrt(B_A)) normalisation is applied in FP32 at the end.
 #include "fft_lds.hpp"
 #include "kernels.hpp"
@@ -45,12 +50,22 @@ __device__ __forceinline__ uint32_t pack16(float lo, float hi) {
   return (uint32_t)a | ((uint32_t)b << 16);
 }
 
+// One 16-byte operand pair: one 16x16x32 MFMA (16-bit) or four 16x16x4
+// steps (FP32).
 template <Prec P>
 __device__ __forceinline__ floatx4 mfma16(u32x4 a, u32x4 b, floatx4 c) {
+  if constexpr (P == Prec::kF32) {
+    const floatx4 af = __builtin_bit_cast(floatx4, a), bf = __builtin_bit_cast(floatx4, b);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(af.x, bf.x, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(af.y, bf.y, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(af.z, bf.z, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(af.w, bf.w, c, 0, 0, 0);
+    return c;
+  }
   if constexpr (P == Prec::kBF16) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
-  } else {
+  } else if constexpr (P == Prec::kFP16) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(halfx8, a),
                                                   __builtin_bit_cast(halfx8, b), c, 0, 0, 0);
   }
@@ -81,6 +96,32 @@ __global__ __launch_bounds__(256) void k_s16_scale(const float2* __restrict__ S,
       sc = ldexpf(1.f, -e);
     }
     scale[a] = sc;
+  }
+}
+
+// FP32: 16 beams x 64 pixels per workgroup, transposed through LDS; a pixel
+// row holds n_actp (re, im) float pairs, zero past the active beams.
+__global__ __launch_bounds__(256) void k_s32_pack(const float2* __restrict__ S,
+                                                  const ActiveBeam* __restrict__ act, int n_act,
+                                                  int n_actp, int ns, float2* __restrict__ s32) {
+  __shared__ float2 tile[64][17];
+  const int tid = threadIdx.x;
+  const size_t pix0 = (size_t)blockIdx.x * 64;
+  const int a0 = blockIdx.y * 16;
+  const size_t npix = (size_t)ns * ns;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int idx = tid + 256 * i;
+    const int j = idx / 64, px = idx % 64;
+    const int a = a0 + j;
+    tile[px][j] = a < n_act ? S[(size_t)act[a].plane * npix + pix0 + px] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int idx = tid + 256 * i;
+    const int px = idx / 16, j = idx % 16;
+    s32[(pix0 + px) * n_actp + a0 + j] = tile[px][j];
   }
 }
 
@@ -118,21 +159,23 @@ __global__ __launch_bounds__(256) void k_s16_pack(const float2* __restrict__ S,
 }
 
 // One thread per (probe group, K block, probe g, beam bl): the A' entries of
-// alpha'' = exp(i phase) / scale[a], zero outside the probe / beam range.
+// alpha'' = exp(i phase) / scale[a] (scale 1 for FP32), zero outside the
+// probe / beam range.
 template <Prec P>
 __global__ void k_alpha16(const double* __restrict__ probe_xy, int p0, int np,
                           const ActiveBeam* __restrict__ act, int n_act, int f, int ns, int w,
                           ProbeOptics po, const float* __restrict__ scale, int group, int nblk,
                           size_t total, uint32_t* __restrict__ a16, int2* __restrict__ origin) {
+  constexpr int KB = prec_block_beams(P);
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
-  const int bl = (int)(i % kC16KB);
-  const int g = (int)((i / kC16KB) % group);
-  const int blk = (int)((i / ((size_t)kC16KB * group)) % nblk);
-  const size_t grp = i / ((size_t)kC16KB * group * nblk);
+  const int bl = (int)(i % KB);
+  const int g = (int)((i / KB) % group);
+  const int blk = (int)((i / ((size_t)KB * group)) % nblk);
+  const size_t grp = i / ((size_t)KB * group * nblk);
   const size_t p = grp * group + g;
-  const int a = blk * kC16KB + bl;
-  uint32_t row_re = 0u, row_im = 0u;
+  const int a = blk * KB + bl;
+  float re = 0.f, im = 0.f;
   if (p < (size_t)np && a < n_act) {
     const double x0 = probe_xy[2 * (p0 + p)], y0 = probe_xy[2 * (p0 + p) + 1];
     if (a == 0) {
@@ -150,14 +193,23 @@ __global__ void k_alpha16(const double* __restrict__ probe_xy, int p0, int np,
     t -= floor(t);
     double s, c;
     sincospi(2.0 * t, &s, &c);
-    const double inv = 1.0 / (double)scale[a];
-    const float re = (float)(c * inv), im = (float)(s * inv);
-    row_re = pack16<P>(re, -im);
-    row_im = pack16<P>(im, re);
+    const double inv = P == Prec::kF32 ? 1.0 : 1.0 / (double)scale[a];
+    re = (float)(c * inv);
+    im = (float)(s * inv);
   }
   const size_t base = (grp * nblk + blk) * (size_t)(2 * group) * (kC16KB);
-  a16[base + (size_t)(2 * g) * kC16KB + bl] = row_re;
-  a16[base + (size_t)(2 * g + 1) * kC16KB + bl] = row_im;
+  uint32_t* r0 = a16 + base + (size_t)(2 * g) * kC16KB;
+  uint32_t* r1 = r0 + kC16KB;
+  if constexpr (P == Prec::kF32) {
+    // row 2g: (Re a, -Im a), row 2g+1: (Im a, Re a) as float pairs
+    r0[2 * bl] = __builtin_bit_cast(uint32_t, re);
+    r0[2 * bl + 1] = __builtin_bit_cast(uint32_t, -im);
+    r1[2 * bl] = __builtin_bit_cast(uint32_t, im);
+    r1[2 * bl + 1] = __builtin_bit_cast(uint32_t, re);
+  } else {
+    r0[bl] = pack16<P>(re, -im);
+    r1[bl] = pack16<P>(im, re);
+  }
 }
 
 constexpr int kNT16 = 256;
@@ -170,7 +222,7 @@ struct UnionGeom16 {
 };
 
 template <int G, Prec P>
-__device__ __forceinline__ void contract16_tile(const uint32_t* __restrict__ s16, int n_actp,
+__device__ __forceinline__ void contract16_tile(const uint32_t* __restrict__ s16, int rowlen,
                                                 const uint32_t* __restrict__ a16g, int np,
                                                 int p_base, int gcount, int ns, int w,
                                                 const UnionGeom16& U, int tile, const int* offx,
@@ -184,7 +236,7 @@ __device__ __forceinline__ void contract16_tile(const uint32_t* __restrict__ s16
   constexpr int NBQ = kTile16 * 8 / kNT16;   // u32x4 of the B block per thread
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int npix = U.uy * U.ux;
-  const int nblk = n_actp / kC16KB;
+  const int nblk = rowlen / kC16KB;
 
   // S pixels this thread stages: tile column (tid + 256 i) / 8. Columns
   // past the union read pixel 0 instead; their outputs are never stored,
@@ -210,7 +262,7 @@ __device__ __forceinline__ void contract16_tile(const uint32_t* __restrict__ s16
     for (int i = 0; i < NAQ; ++i) ga[set][i] = ab[tid + kNT16 * i];
 #pragma unroll
     for (int i = 0; i < NBQ; ++i)
-      gb[set][i] = *reinterpret_cast<const u32x4*>(s16q + (size_t)spix[i] * n_actp + blk * kC16KB);
+      gb[set][i] = *reinterpret_cast<const u32x4*>(s16q + (size_t)spix[i] * rowlen + blk * kC16KB);
   };
   auto stash = [&](int set) {
     uint32_t* A = smem + set * ABUF;
@@ -253,7 +305,7 @@ __device__ __forceinline__ void contract16_tile(const uint32_t* __restrict__ s16
     }
   };
 
-  // n_actp is a multiple of 2 K blocks, so blocks always come in pairs
+  // rows hold a whole number of K-block pairs
   fetch(0, 0);
   fetch(1, 1);
   for (int blk = 0; blk < nblk; blk += 2) {
@@ -291,7 +343,7 @@ __device__ __forceinline__ void contract16_tile(const uint32_t* __restrict__ s16
 
 template <int G, Prec P>
 __global__ __launch_bounds__(kNT16) __attribute__((amdgpu_waves_per_eu(2))) void k_contract16(
-    const uint32_t* __restrict__ s16, int n_actp, const uint32_t* __restrict__ a16,
+    const uint32_t* __restrict__ s16, int rowlen, const uint32_t* __restrict__ a16,
     const int2* __restrict__ origin, int np, int ns, int w, float out_scale,
     float2* __restrict__ window) {
   constexpr int LDS = 2 * (2 * G * kPitch16) + 2 * (kTile16 * kPitch16);
@@ -302,7 +354,7 @@ __global__ __launch_bounds__(kNT16) __attribute__((amdgpu_waves_per_eu(2))) void
   const int tid = threadIdx.x;
   const int p_base = blockIdx.y * G;
   const int gcount = min(G, np - p_base);
-  const int nblk = n_actp / kC16KB;
+  const int nblk = rowlen / kC16KB;
   const uint32_t* a16g = a16 + (size_t)blockIdx.y * nblk * (2 * G) * kC16KB;
   if (tid < 64) {
     // group geometry in wave 0, one lane per probe (G <= 64): offsets of
@@ -341,14 +393,14 @@ __global__ __launch_bounds__(kNT16) __attribute__((amdgpu_waves_per_eu(2))) void
   if (ginfo[0] == 0) {
     const UnionGeom16 U{ginfo[1], ginfo[2], ginfo[3], ginfo[4]};
     for (int tile = blockIdx.x; tile * kTile16 < U.uy * U.ux; tile += gridDim.x)
-      contract16_tile<G, P>(s16, n_actp, a16g, np, p_base, gcount, ns, w, U, tile, offx, offy,
+      contract16_tile<G, P>(s16, rowlen, a16g, np, p_base, gcount, ns, w, U, tile, offx, offy,
                             -1, out_scale, smem, window);
   } else {
     for (int tile = blockIdx.x; tile * kTile16 < w * w; tile += gridDim.x) {
       for (int g = 0; g < gcount; ++g) {
         const int2 o = origin[p_base + g];
         const UnionGeom16 U{o.y, o.x, w, w};
-        contract16_tile<G, P>(s16, n_actp, a16g, np, p_base, gcount, ns, w, U, tile, zero, zero,
+        contract16_tile<G, P>(s16, rowlen, a16g, np, p_base, gcount, ns, w, U, tile, zero, zero,
                               g, out_scale, smem, window);
       }
     }
@@ -367,13 +419,17 @@ hipError_t launch_s16_scale(const float2* smatrix, const ActiveBeam* act, int n_
 
 hipError_t launch_s16_pack(const float2* smatrix, const ActiveBeam* act, int n_act, int n_actp,
                            int ns, const float* scale, void* s16, Prec prec, hipStream_t st) {
-  const dim3 grid((unsigned)((size_t)ns * ns / 64), (unsigned)(n_actp / 32));
-  if (prec == Prec::kBF16)
-    hipLaunchKernelGGL(k_s16_pack<Prec::kBF16>, grid, dim3(256), 0, st, smatrix, act, n_act,
-                       n_actp, ns, scale, static_cast<uint32_t*>(s16));
-  else
-    hipLaunchKernelGGL(k_s16_pack<Prec::kFP16>, grid, dim3(256), 0, st, smatrix, act, n_act,
-                       n_actp, ns, scale, static_cast<uint32_t*>(s16));
+  const unsigned gx = (unsigned)((size_t)ns * ns / 64);
+  if (prec == Prec::kF32) {
+    hipLaunchKernelGGL(k_s32_pack, dim3(gx, (unsigned)(n_actp / 16)), dim3(256), 0, st, smatrix,
+                       act, n_act, n_actp, ns, static_cast<float2*>(s16));
+  } else if (prec == Prec::kBF16) {
+    hipLaunchKernelGGL(k_s16_pack<Prec::kBF16>, dim3(gx, (unsigned)(n_actp / 32)), dim3(256), 0,
+                       st, smatrix, act, n_act, n_actp, ns, scale, static_cast<uint32_t*>(s16));
+  } else {
+    hipLaunchKernelGGL(k_s16_pack<Prec::kFP16>, dim3(gx, (unsigned)(n_actp / 32)), dim3(256), 0,
+                       st, smatrix, act, n_act, n_actp, ns, scale, static_cast<uint32_t*>(s16));
+  }
   return hipGetLastError();
 }
 
@@ -382,16 +438,17 @@ hipError_t launch_alpha16(const double* probe_xy, int p0, int np, const ActiveBe
                           const float* scale, int group, void* a16, int2* origin, Prec prec,
                           hipStream_t st) {
   const int ngrp = (np + group - 1) / group;
-  const int nblk = n_actp / kC16KB;
-  const size_t total = (size_t)ngrp * nblk * group * kC16KB;
-  if (prec == Prec::kBF16)
-    hipLaunchKernelGGL(k_alpha16<Prec::kBF16>, dim3(blocks16(total, 256)), dim3(256), 0, st,
-                       probe_xy, p0, np, act, n_act, f, ns, w, po, scale, group, nblk, total,
-                       static_cast<uint32_t*>(a16), origin);
-  else
-    hipLaunchKernelGGL(k_alpha16<Prec::kFP16>, dim3(blocks16(total, 256)), dim3(256), 0, st,
-                       probe_xy, p0, np, act, n_act, f, ns, w, po, scale, group, nblk, total,
-                       static_cast<uint32_t*>(a16), origin);
+  const int kb = prec_block_beams(prec);
+  const int nblk = n_actp / kb;
+  const size_t total = (size_t)ngrp * nblk * group * kb;
+#define A16(PP)                                                                                \
+  hipLaunchKernelGGL(k_alpha16<PP>, dim3(blocks16(total, 256)), dim3(256), 0, st, probe_xy, p0, \
+                     np, act, n_act, f, ns, w, po, scale, group, nblk, total,                  \
+                     static_cast<uint32_t*>(a16), origin)
+  if (prec == Prec::kF32) A16(Prec::kF32);
+  else if (prec == Prec::kBF16) A16(Prec::kBF16);
+  else A16(Prec::kFP16);
+#undef A16
   return hipGetLastError();
 }
 
@@ -401,24 +458,25 @@ hipError_t launch_contract16(const void* s16, int n_actp, const void* a16, const
   const dim3 grid((unsigned)contract_tile_slots(w), (unsigned)((np + group - 1) / group));
   const uint32_t* s = static_cast<const uint32_t*>(s16);
   const uint32_t* a = static_cast<const uint32_t*>(a16);
-#define C16(GG, PP)                                                                          \
-  hipLaunchKernelGGL((k_contract16<GG, PP>), grid, dim3(kNT16), 0, st, s, n_actp, a, origin, np, \
+  const int rowlen = n_actp * prec_words(prec);  // 32-bit words per packed pixel row
+#define C16(GG, PP)                                                                           \
+  hipLaunchKernelGGL((k_contract16<GG, PP>), grid, dim3(kNT16), 0, st, s, rowlen, a, origin, np, \
                      ns, w, out_scale, window)
-  if (prec == Prec::kBF16) {
-    switch (group) {
-      case 16: C16(16, Prec::kBF16); break;
-      case 32: C16(32, Prec::kBF16); break;
-      case 64: C16(64, Prec::kBF16); break;
-      default: return hipErrorInvalidValue;
-    }
-  } else {
-    switch (group) {
-      case 16: C16(16, Prec::kFP16); break;
-      case 32: C16(32, Prec::kFP16); break;
-      case 64: C16(64, Prec::kFP16); break;
-      default: return hipErrorInvalidValue;
-    }
+#define C16G(PP)                          \
+  switch (group) {                        \
+    case 16: C16(16, PP); break;          \
+    case 32: C16(32, PP); break;          \
+    case 64: C16(64, PP); break;          \
+    default: return hipErrorInvalidValue; \
   }
+  if (prec == Prec::kF32) {
+    C16G(Prec::kF32)
+  } else if (prec == Prec::kBF16) {
+    C16G(Prec::kBF16)
+  } else {
+    C16G(Prec::kFP16)
+  }
+#undef C16G
 #undef C16
   return hipGetLastError();
 }
