@@ -33,6 +33,7 @@ __all__ = [
     "entrance_probe", "multislice_stem", "default_alpha_max", "beam_set",
     "plane_wave", "smatrix", "window_origin", "window_indices",
     "prism_coefficients", "prism_probe_wave", "prism_outputs", "prism_probe_direct",
+    "frozen_phonon_multislice", "frozen_phonon_prism",
     "t_multi", "t_prism", "time_ratio", "rel_l2", "one_minus_r2",
 ]
 
@@ -429,6 +430,45 @@ def prism_probe_direct(phase, thickness, cell, energy_keV, f, alpha_max_mrad, op
     theta = theta_of_k2(k2_grid(w, scale=f), lam, dq)
     D = detector_sums(I, theta, edges_mrad)
     return (D, I) if return_cbed else D
+
+
+# --------------------------------------------------------------------------
+# Frozen phonons ("Simulation and Analysis Implementation")
+# --------------------------------------------------------------------------
+# Thermal scattering: the whole simulation is repeated for K configurations
+# of randomly displaced atoms and the intensities are added incoherently;
+# the result reported here is their mean (sum / K).
+
+def frozen_phonon_multislice(phase_configs, thickness, cell, energy_keV, optics, probes,
+                             edges_mrad, fft=None, return_cbed=False):
+    """Mean over configurations of multislice STEM outputs (detector sums, CBED)."""
+    K = len(phase_configs)
+    D, C = 0.0, 0.0
+    for ph in phase_configs:
+        r = multislice_stem(ph, thickness, cell, energy_keV, optics, probes, edges_mrad,
+                            fft=fft, return_cbed=return_cbed)
+        if return_cbed:
+            D, C = D + r[0], C + r[1]
+        else:
+            D = D + r
+    return (D / K, C / K) if return_cbed else D / K
+
+
+def frozen_phonon_prism(phase_configs, thickness, cell, energy_keV, f, alpha_max_mrad, optics,
+                        probes, edges_mrad, fft=None, return_cbed=False):
+    """Mean over configurations of PRISM outputs, one S-matrix per configuration."""
+    K = len(phase_configs)
+    height = float(np.sum(thickness))
+    D, C = 0.0, 0.0
+    for ph in phase_configs:
+        beams, S = smatrix(ph, thickness, cell, energy_keV, f, alpha_max_mrad, fft=fft)
+        r = prism_outputs(S, beams, f, cell, energy_keV, optics, probes, edges_mrad, fft=fft,
+                          return_cbed=return_cbed, height=height)
+        if return_cbed:
+            D, C = D + r[0], C + r[1]
+        else:
+            D = D + r
+    return (D / K, C / K) if return_cbed else D / K
 
 
 # --------------------------------------------------------------------------

@@ -26,6 +26,7 @@ from .specimen import (
     raster_probes,
     annular_edges,
     build_inputs,
+    phonon_configurations,
 )
 
 __all__ = [
@@ -38,4 +39,5 @@ __all__ = [
     "raster_probes",
     "annular_edges",
     "build_inputs",
+    "phonon_configurations",
 ]

@@ -219,3 +219,44 @@ def build_inputs(name_or_cfg, seed=0, n_slices=None):
         edges=annular_edges(cfg["detectors"]),
         f_values=tuple(cfg["f_values"]),
     )
+
+
+DEFAULT_THERMAL_JITTER_A = 0.08   # rms displacement per Cartesian coordinate
+
+
+def phonon_configurations(name_or_cfg, seed, n_configs, jitter_A=None, n_slices=None):
+    """Frozen-phonon configurations of one specimen (random atomic displacements).
+
+    The undisplaced specimen is the workload's atom list for ``seed`` (an FCC
+    crystal on its exact lattice sites); configuration k adds independent
+    Gaussian displacements of standard deviation ``jitter_A`` (default: the
+    workload's own jitter, else 0.08 A) drawn from
+    ``default_rng([seed, k])`` in the order x, y, z. Returns the
+    ``build_inputs`` dict of the undisplaced specimen plus ``phase_configs``
+    (float32 [K][H][n][n]) and ``atom_configs`` (list of [n_atoms, 4]).
+    """
+    cfg = get_config(name_or_cfg) if isinstance(name_or_cfg, str) else name_or_cfg
+    spec = cfg["specimen"]
+    if jitter_A is None:
+        jitter_A = spec.get("jitter_A", DEFAULT_THERMAL_JITTER_A)
+    base_cfg = dict(cfg, specimen=dict(spec, jitter_A=0.0)) if spec["kind"] == "fcc" else cfg
+    d = build_inputs(base_cfg, seed, n_slices)
+    d["name"] = name_or_cfg if isinstance(name_or_cfg, str) else "custom"
+    cell = spec["cell"]
+    H = d["phase"].shape[0]
+    base = d["atoms"]
+    phases, atoms = [], []
+    for k in range(int(n_configs)):
+        rng = np.random.default_rng([int(seed), k])
+        n = base.shape[0]
+        disp = np.stack([rng.normal(0.0, jitter_A, n), rng.normal(0.0, jitter_A, n),
+                         rng.normal(0.0, jitter_A, n)], axis=1)
+        a = base.copy()
+        a[:, :3] += disp
+        atoms.append(a)
+        phases.append(phase_slices(a, cell[:2], cfg["n"], H, cfg["slice_A"]).astype(np.float32))
+    d["phase_configs"] = np.stack(phases)
+    d["atom_configs"] = atoms
+    d["jitter_A"] = float(jitter_A)
+    return d
+

@@ -14,7 +14,7 @@ import pytest
 from hypothesis import given, settings, strategies as st
 
 import oracle as O
-from synth import build_inputs
+from synth import build_inputs, phonon_configurations
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -382,6 +382,62 @@ def test_p8_prism_two_pixel_shift():
     D0 = O.prism_outputs(S0, b0, f, cell, E, d["optics"], pr, d["edges"])
     D1 = O.prism_outputs(S1, b1, f, cell, E, d["optics"], pr + [0.0, 2 * dx], d["edges"])
     assert np.abs(D1 - D0).max() <= 1e-10 * np.abs(D0).max()
+
+
+# ---------------------------------------------------------------- frozen phonons
+
+def test_frozen_phonon_prism_f1_equals_multislice_average():
+    # per configuration PRISM f = 1 is multislice (P6), so the averages agree
+    d = phonon_configurations("tiny", 2, 3)
+    cell, E = d["cell"], d["energy_keV"]
+    lam = O.wavelength(E)
+    amax = O.default_alpha_max(0.020, 1, lam, 1 / cell) * 1e3
+    pr = d["probes"][::37]
+    Dp = O.frozen_phonon_prism(d["phase_configs"], d["thickness"], cell, E, 1, amax, d["optics"],
+                               pr, d["edges"])
+    Dm = O.frozen_phonon_multislice(d["phase_configs"], d["thickness"], cell, E, d["optics"], pr,
+                                    d["edges"])
+    assert O.rel_l2(Dp, Dm) < 1e-12
+    # the configurations differ, so the average is not any single one
+    D0 = O.multislice_stem(d["phase_configs"][0], d["thickness"], cell, E, d["optics"], pr,
+                           d["edges"])
+    assert O.rel_l2(D0, Dm) > 1e-4
+
+
+def test_frozen_phonon_prism_mean_of_translated_configurations():
+    # configuration B is configuration A moved by one S-pixel (2 fine pixels),
+    # so its image at r equals A's at r - s (P8); the incoherent mean is then
+    # (D_A(r) + D_A(r - s)) / 2, computed from A's S-matrix alone
+    d = build_inputs("tiny", 8)
+    n, cell, E, f = d["n"], d["cell"], d["energy_keV"], 2
+    dx = cell / n
+    lam = O.wavelength(E)
+    amax = O.default_alpha_max(0.020, f, lam, 1 / cell) * 1e3
+    A = d["phase"].astype(np.float64)
+    B = np.roll(A, 2, axis=2)                       # +2 fine pixels in x
+    pr = np.array([[1.6, 2.4], [7.2, 0.0], [3.0, 11.8], [12.4, 6.6]])
+    D, C = O.frozen_phonon_prism([A, B], d["thickness"], cell, E, f, amax, d["optics"], pr,
+                                 d["edges"], return_cbed=True)
+    bA, SA = O.smatrix(A, d["thickness"], cell, E, f, amax)
+    D0, C0 = O.prism_outputs(SA, bA, f, cell, E, d["optics"], pr, d["edges"], return_cbed=True)
+    D1, C1 = O.prism_outputs(SA, bA, f, cell, E, d["optics"], pr - [2 * dx, 0.0], d["edges"],
+                             return_cbed=True)
+    assert np.abs(D - 0.5 * (D0 + D1)).max() <= 1e-10 * np.abs(D).max()
+    assert np.abs(C - 0.5 * (C0 + C1)).max() <= 1e-10 * np.abs(C).max()
+    assert np.abs(D1 - D0).max() > 1e-3 * np.abs(D0).max()   # the two terms differ
+
+
+def test_frozen_phonon_multislice_mean_of_translated_configurations():
+    d = build_inputs("tiny", 9)
+    n, cell, E = d["n"], d["cell"], d["energy_keV"]
+    dx = cell / n
+    A = d["phase"].astype(np.float64)
+    B = np.roll(A, 1, axis=1)                       # +1 fine pixel in y
+    pr = np.array([[1.6, 2.4], [7.2, 0.0], [3.0, 11.8]])
+    D = O.frozen_phonon_multislice([A, B], d["thickness"], cell, E, d["optics"], pr, d["edges"])
+    D0 = O.multislice_stem(A, d["thickness"], cell, E, d["optics"], pr, d["edges"])
+    D1 = O.multislice_stem(A, d["thickness"], cell, E, d["optics"], pr - [0.0, dx], d["edges"])
+    assert np.abs(D - 0.5 * (D0 + D1)).max() <= 1e-10 * np.abs(D).max()
 
 
 # ---------------------------------------------------------------- P9 tiny brute force
