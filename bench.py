@@ -61,6 +61,9 @@ def parse():
                     help="multislice probes timed (0: skip the multislice baseline)")
     ap.add_argument("--precisions", default="bf16,fp16",
                     help="16-bit window-sum variants timed at the headline f ('' none)")
+    ap.add_argument("--phonon-configs", type=int, default=2,
+                    help="frozen-phonon configurations timed at the headline f (0: skip the "
+                         "probe-side variants: resident-S step, CBED output, frozen phonons)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--calibration-copy", action="store_true",
@@ -90,6 +93,9 @@ def kernel_work(name, g):
         return "hbm", B * state
     if name in ("contract", "contract16"):
         return "mfma", 8.0 * BA * W * W * P
+    if name in ("s32_pack", "s16_pack"):
+        # read the active S planes, write the pixel-major copy (8 or 4 bytes per beam-pixel)
+        return "hbm", BA * g["NS"] ** 2 * (16.0 if name == "s32_pack" else 12.0)
     if name == "window_detect":
         return "hbm", 8.0 * W * W * P + 8.0 * P * g["n_det"]
     if name == "transmission":
@@ -236,11 +242,69 @@ def main():
     main_c = setup_f(args.f)
     ms, prof = timed(main_c, args.steps, args.warmup, True)
     value = P / (ms * 1e-3)
-    geo = dict(N=N, H=H, B=main_c["B"], BA=main_c["BA"], P=P, W=N // (2 * args.f), n_det=n_det)
+    geo = dict(N=N, NS=N // 2, H=H, B=main_c["B"], BA=main_c["BA"], P=P, W=N // (2 * args.f),
+               n_det=n_det)
     dom, roof = roofline(prof, geo, args.steps)
     kernels = {k: round(v["total_ms"] / args.steps, 3) for k, v in prof.items()}
     out_main = untile(main_c["out"].cpu().numpy(), main_c["perm"])
     finite = bool(np.all(np.isfinite(out_main)))
+
+    # probe-side variants at the headline f: probe step alone on a resident
+    # S-matrix, full CBED output, and frozen-phonon averaging (one S-matrix
+    # build per configuration, outputs accumulated with weight 1/K)
+    probe_side = None
+    if args.phonon_configs > 0:
+        from synth import phonon_configurations
+        c = main_c
+
+        def ev_time(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        ms_res = ev_time(lambda: plan.probe_outputs(c["f"], c["amax"], c["S"], c["xy"], optics,
+                                                    edges, c["out"], c["wsp"]), args.steps)
+        log(f"resident-S probe step: {ms_res:.2f} ms")
+        W = N // (2 * args.f)
+        cb = torch.empty((P, W, W), dtype=torch.float32, device=dev)
+        ms_cb = ev_time(lambda: plan.probe_cbed(c["f"], c["amax"], c["S"], c["xy"], optics, cb,
+                                                c["wsp"]), args.steps)
+        del cb
+        log(f"CBED probe step: {ms_cb:.2f} ms")
+        K = args.phonon_configs
+        ph = phonon_configurations(CONFIG, args.seed, K)
+        phases = [torch.from_numpy(x).to(dev) for x in ph["phase_configs"]]
+        jitter = ph["jitter_A"]
+        del ph
+        acc = torch.zeros((P, n_det), dtype=torch.float64, device=dev)
+
+        def phonon_run():
+            acc.zero_()
+            for x in phases:
+                plan.set_potential_slices(x)
+                plan.build_smatrix(c["f"], c["amax"], c["S"], c["wsb"])
+                plan.probe_outputs_accumulate(c["f"], c["amax"], c["S"], c["xy"], optics, edges,
+                                              1.0 / K, acc, c["wsp"])
+
+        ms_ph = ev_time(phonon_run, 1)
+        plan.set_potential_slices(phase)
+        torch.cuda.synchronize()
+        del phases, acc
+        log(f"frozen phonons, {K} configurations: {ms_ph:.2f} ms")
+        probe_side = {
+            "resident_smatrix": {"ms": round(ms_res, 3), "probes_per_s": round(P / (ms_res * 1e-3), 1)},
+            "cbed": {"ms": round(ms_cb, 3), "probes_per_s": round(P / (ms_cb * 1e-3), 1),
+                     "window": W, "bytes_out": P * W * W * 4},
+            "frozen_phonon": {"configs": K, "ms": round(ms_ph, 3),
+                              "probes_per_s": round(P / (ms_ph * 1e-3), 1),
+                              "jitter_A": jitter},
+        }
     del main_c
 
     # 16-bit window sums at the headline f (tolerance eps_rel <= 1e-2)
@@ -315,6 +379,7 @@ def main():
         "speedup_vs_gpu_multislice": round(value / multi_rate, 2) if multi_rate else None,
         "per_f": per_f,
         "precision_variants": variants,
+        "probe_side": probe_side,
         "kernel_ms_per_step": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -177,6 +177,36 @@ int prism_multislice_outputs(prism_plan* plan, const double* probe_xy_dev, int n
                              const prism_optics* optics, const prism_detector* detector,
                              double* out_dev, void* ws, size_t ws_bytes, void* stream);
 
+/* Frozen-phonon averaging ("Simulation and Analysis Implementation": the
+ * calculation is repeated for several configurations of randomly displaced
+ * atoms and the intensities are summed incoherently). The _accumulate forms
+ * run the same computation as the call they extend but store
+ *     out[i] = out[i] + weight * result[i]
+ * instead of overwriting: with one S-matrix (or one set of potential slices)
+ * per configuration and weight = 1/K, K calls into the same output leave the
+ * configuration average, with no extra buffer. The caller initialises the
+ * output (e.g. with zeros or with a first non-accumulating call). Each output
+ * element is read and written by one thread of one kernel, so the sum is
+ * formed in call order; FP64 for detector sums, the FP32 value of each term
+ * for CBED (the sum is formed in FP64 per term, then rounded to FP32).
+ * Errors: those of the extended call, and PRISM_EINVAL for a weight that is
+ * not finite. Calls that accumulate into the same output must be ordered
+ * (same stream or events). */
+int prism_probe_outputs_accumulate(prism_plan* plan, int f, double alpha_max_mrad,
+                                   const void* smatrix_dev, const double* probe_xy_dev,
+                                   int n_probes, const prism_optics* optics,
+                                   const prism_detector* detector, double weight,
+                                   double* out_dev, void* ws, size_t ws_bytes, void* stream);
+int prism_probe_cbed_accumulate(prism_plan* plan, int f, double alpha_max_mrad,
+                                const void* smatrix_dev, const double* probe_xy_dev,
+                                int n_probes, const prism_optics* optics, double weight,
+                                float* cbed_dev, void* ws, size_t ws_bytes, void* stream);
+int prism_multislice_outputs_accumulate(prism_plan* plan, const double* probe_xy_dev,
+                                        int n_probes, const prism_optics* optics,
+                                        const prism_detector* detector, double weight,
+                                        double* out_dev, void* ws, size_t ws_bytes,
+                                        void* stream);
+
 /* Per-kernel timing: while enabled, every kernel launch of this plan is
  * bracketed by HIP events recorded on its stream. prism_profile_report
  * waits for the recorded events, writes one line per kernel name

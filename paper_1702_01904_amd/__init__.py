@@ -184,6 +184,17 @@ class Plan:
     def probe_outputs(self, f, alpha_max_mrad, smatrix, probe_xy, optics, edges_mrad, out,
                       workspace, stream=None):
         """probe_xy: float64 device [P][2] (A); out: float64 device [P][n_det]."""
+        self._probe_outputs(None, f, alpha_max_mrad, smatrix, probe_xy, optics, edges_mrad, out,
+                            workspace, stream)
+
+    def probe_outputs_accumulate(self, f, alpha_max_mrad, smatrix, probe_xy, optics, edges_mrad,
+                                 weight, out, workspace, stream=None):
+        """As probe_outputs, but out += weight * result (frozen-phonon averaging)."""
+        self._probe_outputs(float(weight), f, alpha_max_mrad, smatrix, probe_xy, optics,
+                            edges_mrad, out, workspace, stream)
+
+    def _probe_outputs(self, weight, f, alpha_max_mrad, smatrix, probe_xy, optics, edges_mrad,
+                       out, workspace, stream):
         import torch
         det = _Det(edges_mrad)
         P = probe_xy.shape[0]
@@ -192,13 +203,26 @@ class Plan:
         _check_dev(smatrix, torch.complex64, None, "smatrix")
         _check_dev(workspace, torch.uint8, None, "workspace")
         o = _optics(optics)
-        _native.check(self._L.prism_probe_outputs(
-            self._h, int(f), float(alpha_max_mrad), _ptr(smatrix), _ptr(probe_xy), int(P),
-            ctypes.byref(o), ctypes.byref(det.struct), _ptr(out), _ptr(workspace),
-            workspace.numel(), _stream_ptr(stream)))
+        head = (self._h, int(f), float(alpha_max_mrad), _ptr(smatrix), _ptr(probe_xy), int(P),
+                ctypes.byref(o), ctypes.byref(det.struct))
+        tail = (_ptr(out), _ptr(workspace), workspace.numel(), _stream_ptr(stream))
+        if weight is None:
+            _native.check(self._L.prism_probe_outputs(*head, *tail))
+        else:
+            _native.check(self._L.prism_probe_outputs_accumulate(*head, weight, *tail))
 
     def probe_cbed(self, f, alpha_max_mrad, smatrix, probe_xy, optics, out, workspace, stream=None):
         """Full diffraction patterns: out float32 device [P][W][W] (W = n / 2f, fftfreq order)."""
+        self._probe_cbed(None, f, alpha_max_mrad, smatrix, probe_xy, optics, out, workspace, stream)
+
+    def probe_cbed_accumulate(self, f, alpha_max_mrad, smatrix, probe_xy, optics, weight, out,
+                              workspace, stream=None):
+        """As probe_cbed, but out += weight * pattern (frozen-phonon averaging)."""
+        self._probe_cbed(float(weight), f, alpha_max_mrad, smatrix, probe_xy, optics, out,
+                         workspace, stream)
+
+    def _probe_cbed(self, weight, f, alpha_max_mrad, smatrix, probe_xy, optics, out, workspace,
+                    stream):
         import torch
         P = probe_xy.shape[0]
         w = self.n // (2 * int(f))
@@ -207,11 +231,24 @@ class Plan:
         _check_dev(smatrix, torch.complex64, None, "smatrix")
         _check_dev(workspace, torch.uint8, None, "workspace")
         o = _optics(optics)
-        _native.check(self._L.prism_probe_cbed(
-            self._h, int(f), float(alpha_max_mrad), _ptr(smatrix), _ptr(probe_xy), int(P),
-            ctypes.byref(o), _ptr(out), _ptr(workspace), workspace.numel(), _stream_ptr(stream)))
+        head = (self._h, int(f), float(alpha_max_mrad), _ptr(smatrix), _ptr(probe_xy), int(P),
+                ctypes.byref(o))
+        tail = (_ptr(out), _ptr(workspace), workspace.numel(), _stream_ptr(stream))
+        if weight is None:
+            _native.check(self._L.prism_probe_cbed(*head, *tail))
+        else:
+            _native.check(self._L.prism_probe_cbed_accumulate(*head, weight, *tail))
 
     def multislice_outputs(self, probe_xy, optics, edges_mrad, out, workspace, stream=None):
+        self._multislice_outputs(None, probe_xy, optics, edges_mrad, out, workspace, stream)
+
+    def multislice_outputs_accumulate(self, probe_xy, optics, edges_mrad, weight, out, workspace,
+                                      stream=None):
+        """As multislice_outputs, but out += weight * result (frozen-phonon averaging)."""
+        self._multislice_outputs(float(weight), probe_xy, optics, edges_mrad, out, workspace,
+                                 stream)
+
+    def _multislice_outputs(self, weight, probe_xy, optics, edges_mrad, out, workspace, stream):
         import torch
         det = _Det(edges_mrad)
         P = probe_xy.shape[0]
@@ -219,9 +256,12 @@ class Plan:
         _check_dev(out, torch.float64, P * det.edges.shape[0], "out")
         _check_dev(workspace, torch.uint8, None, "workspace")
         o = _optics(optics)
-        _native.check(self._L.prism_multislice_outputs(
-            self._h, _ptr(probe_xy), int(P), ctypes.byref(o), ctypes.byref(det.struct), _ptr(out),
-            _ptr(workspace), workspace.numel(), _stream_ptr(stream)))
+        head = (self._h, _ptr(probe_xy), int(P), ctypes.byref(o), ctypes.byref(det.struct))
+        tail = (_ptr(out), _ptr(workspace), workspace.numel(), _stream_ptr(stream))
+        if weight is None:
+            _native.check(self._L.prism_multislice_outputs(*head, *tail))
+        else:
+            _native.check(self._L.prism_multislice_outputs_accumulate(*head, weight, *tail))
 
 
 def tile_order(nx, ny, tx, ty):

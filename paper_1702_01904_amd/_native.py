@@ -25,7 +25,8 @@ EXPORTS = (
     "prism_multislice_workspace_bytes", "prism_probe_workspace_bytes", "prism_probe_group",
     "prism_set_probe_precision", "prism_set_potential_slices", "prism_build_smatrix",
     "prism_probe_outputs", "prism_probe_cbed", "prism_multislice_outputs",
-    "prism_profile_enable", "prism_profile_report",
+    "prism_probe_outputs_accumulate", "prism_probe_cbed_accumulate",
+    "prism_multislice_outputs_accumulate", "prism_profile_enable", "prism_profile_report",
     "prism_last_error",
 )
 
@@ -91,6 +92,14 @@ def lib():
                                  ctypes.c_size_t, P]),
         "prism_multislice_outputs": (I, [P, P, I, ctypes.POINTER(PrismOptics),
                                          ctypes.POINTER(PrismDetector), P, P, ctypes.c_size_t, P]),
+        "prism_probe_outputs_accumulate": (I, [P, I, D, P, P, I, ctypes.POINTER(PrismOptics),
+                                               ctypes.POINTER(PrismDetector), D, P, P,
+                                               ctypes.c_size_t, P]),
+        "prism_probe_cbed_accumulate": (I, [P, I, D, P, P, I, ctypes.POINTER(PrismOptics), D, P,
+                                            P, ctypes.c_size_t, P]),
+        "prism_multislice_outputs_accumulate": (I, [P, P, I, ctypes.POINTER(PrismOptics),
+                                                    ctypes.POINTER(PrismDetector), D, P, P,
+                                                    ctypes.c_size_t, P]),
         "prism_profile_enable": (I, [P, I]),
         "prism_profile_report": (I, [P, ctypes.c_char_p, ctypes.c_size_t]),
         "prism_last_error": (ctypes.c_char_p, []),

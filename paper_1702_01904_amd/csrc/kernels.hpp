@@ -27,6 +27,20 @@ struct DetBins {
   int hi[kMaxDet];
 };
 
+// How a kernel stores a result v into an output element: overwrite (on = 0)
+// or add w * v to what is there (on = 1; the average over frozen-phonon
+// configurations is a sum of calls with w = 1/K).
+struct OutAcc {
+  int on;
+  double w;
+};
+__host__ __device__ inline void put_out(double* o, double v, OutAcc a) {
+  *o = a.on ? *o + a.w * v : v;
+}
+__host__ __device__ inline void put_out(float* o, double v, OutAcc a) {
+  *o = a.on ? (float)((double)*o + a.w * v) : (float)v;
+}
+
 // Per-probe optics for the GPU-side FP64 phase computations.
 struct ProbeOptics {
   double lam;      // wavelength (A)
@@ -67,7 +81,7 @@ hipError_t launch_col_detect(const float2* state, int nwaves, int n, const float
                              hipStream_t st);
 int col_tiles(int n);
 hipError_t launch_reduce_partials(const double* partial, int nwaves, int tiles, int n_det,
-                                  double* out, hipStream_t st);
+                                  double* out, OutAcc acc, hipStream_t st);
 hipError_t launch_extract(const float2* state, int nwaves, int n, float2* smatrix,
                           const float2* twH, hipStream_t st);
 
@@ -129,13 +143,13 @@ hipError_t launch_window256(float2* window, int np, const float2* twW, int f,
                             const DetBins& bins, double* partial, hipStream_t st);
 // W = 256 CBED: cbed[p][ky][kx] = |Psi|^2 / W^2 (float32, fftfreq order).
 hipError_t launch_window256_cbed(float2* window, int np, const float2* twW, float* cbed,
-                                 hipStream_t st);
+                                 OutAcc acc, hipStream_t st);
 // Full CBED output: cbed[p][ky][kx] = |FFT_W window_p|^2 / W^2 (float32,
 // window fftfreq order), W <= 128.
 hipError_t launch_window_cbed(const float2* window, int np, int w, const float2* twW,
-                              float* cbed, hipStream_t st);
+                              float* cbed, OutAcc acc, hipStream_t st);
 hipError_t launch_window_detect(const float2* window, int np, int w, const float2* twW,
                                 const uint16_t* pix, const BinLists& lists, double* out,
-                                hipStream_t st);
+                                OutAcc acc, hipStream_t st);
 
 }  // namespace prism

@@ -464,11 +464,19 @@ int prepare_slices(prism_plan* p, const SliceWs& w, hipStream_t st) {
 
 namespace {
 
+// Output store mode of the public calls: overwrite, or add weight * result.
+int out_mode(bool accumulate, double weight, prism::OutAcc* oa) {
+  if (accumulate && !std::isfinite(weight)) return fail(PRISM_EINVAL, "weight must be finite");
+  *oa = prism::OutAcc{accumulate ? 1 : 0, accumulate ? weight : 1.0};
+  return PRISM_OK;
+}
+
 // PRISM probe step (Fig. 1d-f). d != nullptr: detector sums into out;
-// d == nullptr: full CBED intensities into cbed.
+// d == nullptr: full CBED intensities into cbed. oa selects overwrite or
+// weighted accumulation of the results.
 int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, const double* xy, int P,
                const prism_optics* o, const prism_detector* d, double* out, float* cbed,
-               void* ws, size_t ws_bytes, void* stream) {
+               prism::OutAcc oa, void* ws, size_t ws_bytes, void* stream) {
   const std::vector<int32_t>* mn;
   if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
   if (P < 0) return fail(PRISM_EINVAL, "negative probe count");
@@ -516,9 +524,10 @@ int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, const doub
     if (want_cbed) {
       float* dst = cbed + (size_t)p0 * w * w;
       if (w == 256) {
-        LAUNCH(p, st, "window256_cbed", prism::launch_window256_cbed(pw.window, np, pw.twW, dst, st));
+        LAUNCH(p, st, "window256_cbed",
+               prism::launch_window256_cbed(pw.window, np, pw.twW, dst, oa, st));
       } else {
-        LAUNCH(p, st, "window_cbed", prism::launch_window_cbed(pw.window, np, w, pw.twW, dst, st));
+        LAUNCH(p, st, "window_cbed", prism::launch_window_cbed(pw.window, np, w, pw.twW, dst, oa, st));
       }
       return PRISM_OK;
     }
@@ -528,10 +537,10 @@ int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, const doub
              prism::launch_window256(pw.window, np, pw.twW, f, bins, pw.partial, st));
       LAUNCH(p, st, "reduce_partials",
              prism::launch_reduce_partials(pw.partial, np, prism::window256_tiles(), bins.n, dst,
-                                           st));
+                                           oa, st));
     } else {
       LAUNCH(p, st, "window_detect",
-             prism::launch_window_detect(pw.window, np, w, pw.twW, pw.pix, pl->lists, dst, st));
+             prism::launch_window_detect(pw.window, np, w, pw.twW, pw.pix, pl->lists, dst, oa, st));
     }
     return PRISM_OK;
   };
@@ -562,6 +571,56 @@ int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, const doub
     LAUNCH(p, st, "contract", prism::launch_contract(Sd, pw.act, n_act, pw.alpha, pw.origin, np, ns, w, G, pw.window,
                                    st));
     if (int r = window_stage(np, p0)) return r;
+  }
+  return PRISM_OK;
+}
+
+// Multislice STEM (Fig. 1a-c): one full-grid wave per probe, H slice steps,
+// detector sums of |Psi|^2; oa as in probe_step.
+int multislice_step(prism_plan* p, const double* xy, int P, const prism_optics* o,
+                    const prism_detector* d, double* out, prism::OutAcc oa, void* ws,
+                    size_t ws_bytes, void* stream) {
+  if (!p) return fail(PRISM_EINVAL, "null plan");
+  if (P < 0) return fail(PRISM_EINVAL, "negative probe count");
+  if (int r = check_optics(p, o)) return r;
+  prism::DetBins bins;
+  if (int r = make_bins(p, d, &bins)) return r;
+  if (P == 0) return PRISM_OK;
+  if (!xy || !out || !ws) return fail(PRISM_EINVAL, "null device buffer");
+  if (!p->phase) return fail(PRISM_ENOTREADY, "potential slices not set");
+  const int n = p->n;
+  void* base = aligned_base(ws);
+  const int chunk = choose_chunk(p, pref_wave_chunk(n, P), 0, bins.n, ws_bytes);
+  if (chunk < 1) return fail(PRISM_ENOSPACE, "workspace smaller than the multislice minimum");
+  SliceWs w;
+  slice_layout(p, chunk, 0, bins.n, &w, base);
+  prism::ProbeOptics po = probe_optics(p, o);
+  std::vector<int32_t>& rows = p->aper_rows[std::make_tuple(
+      dbits(o->alpha_mrad), dbits(o->tilt_x_mrad), dbits(o->tilt_y_mrad))];
+  const long long n_ap = aperture_rows(p, o, &rows);
+  if (n_ap < 1) return fail(PRISM_EINVAL, "the probe aperture holds no grid frequency");
+  po.norm = 1.0 / std::sqrt((double)n_ap);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int r = prepare_slices(p, w, st)) return r;
+  HIP_TRY(hipMemcpyAsync(w.aper, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                         st),
+          "copy aperture rows");
+  const int tiles = prism::col_tiles(n);
+  for (int p0 = 0; p0 < P; p0 += chunk) {
+    const int np = std::min(chunk, P - p0);
+    LAUNCH(p, st, "probe_init", prism::launch_probe_init(w.state, xy, p0, np, n, po, w.aper, w.twN, st));
+    for (int s = 0; s < p->H; ++s) {
+      LAUNCH(p, st, "row_pass", prism::launch_row_pass(w.state, np, n, w.trans + (size_t)s * n * n, w.twN, w.tw2, st));
+      if (s + 1 < p->H) {
+        LAUNCH(p, st, "col_pass", prism::launch_col_pass(w.state, np, n, w.prop + (size_t)s * n, w.twN, w.tw2, st));
+      } else {
+        LAUNCH(p, st, "col_detect", prism::launch_col_detect(w.state, np, n, w.prop + (size_t)s * n, w.twN, bins,
+                                         w.partial, st));
+      }
+    }
+    LAUNCH(p, st, "reduce_partials",
+           prism::launch_reduce_partials(w.partial, np, tiles, bins.n, out + (size_t)p0 * bins.n,
+                                         oa, st));
   }
   return PRISM_OK;
 }
@@ -802,61 +861,50 @@ int prism_build_smatrix(prism_plan* p, int f, double amax_mrad, void* S, void* w
 int prism_multislice_outputs(prism_plan* p, const double* xy, int P, const prism_optics* o,
                              const prism_detector* d, double* out, void* ws, size_t ws_bytes,
                              void* stream) {
-  if (!p) return fail(PRISM_EINVAL, "null plan");
-  if (P < 0) return fail(PRISM_EINVAL, "negative probe count");
-  if (int r = check_optics(p, o)) return r;
-  prism::DetBins bins;
-  if (int r = make_bins(p, d, &bins)) return r;
-  if (P == 0) return PRISM_OK;
-  if (!xy || !out || !ws) return fail(PRISM_EINVAL, "null device buffer");
-  if (!p->phase) return fail(PRISM_ENOTREADY, "potential slices not set");
-  const int n = p->n;
-  void* base = aligned_base(ws);
-  const int chunk = choose_chunk(p, pref_wave_chunk(n, P), 0, bins.n, ws_bytes);
-  if (chunk < 1) return fail(PRISM_ENOSPACE, "workspace smaller than the multislice minimum");
-  SliceWs w;
-  slice_layout(p, chunk, 0, bins.n, &w, base);
-  prism::ProbeOptics po = probe_optics(p, o);
-  std::vector<int32_t>& rows = p->aper_rows[std::make_tuple(
-      dbits(o->alpha_mrad), dbits(o->tilt_x_mrad), dbits(o->tilt_y_mrad))];
-  const long long n_ap = aperture_rows(p, o, &rows);
-  if (n_ap < 1) return fail(PRISM_EINVAL, "the probe aperture holds no grid frequency");
-  po.norm = 1.0 / std::sqrt((double)n_ap);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (int r = prepare_slices(p, w, st)) return r;
-  HIP_TRY(hipMemcpyAsync(w.aper, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                         st),
-          "copy aperture rows");
-  const int tiles = prism::col_tiles(n);
-  for (int p0 = 0; p0 < P; p0 += chunk) {
-    const int np = std::min(chunk, P - p0);
-    LAUNCH(p, st, "probe_init", prism::launch_probe_init(w.state, xy, p0, np, n, po, w.aper, w.twN, st));
-    for (int s = 0; s < p->H; ++s) {
-      LAUNCH(p, st, "row_pass", prism::launch_row_pass(w.state, np, n, w.trans + (size_t)s * n * n, w.twN, w.tw2, st));
-      if (s + 1 < p->H) {
-        LAUNCH(p, st, "col_pass", prism::launch_col_pass(w.state, np, n, w.prop + (size_t)s * n, w.twN, w.tw2, st));
-      } else {
-        LAUNCH(p, st, "col_detect", prism::launch_col_detect(w.state, np, n, w.prop + (size_t)s * n, w.twN, bins,
-                                         w.partial, st));
-      }
-    }
-    LAUNCH(p, st, "reduce_partials", prism::launch_reduce_partials(w.partial, np, tiles, bins.n, out + (size_t)p0 * bins.n,
-                                          st));
-  }
-  return PRISM_OK;
+  return multislice_step(p, xy, P, o, d, out, prism::OutAcc{0, 1.0}, ws, ws_bytes, stream);
+}
+
+int prism_multislice_outputs_accumulate(prism_plan* p, const double* xy, int P,
+                                        const prism_optics* o, const prism_detector* d,
+                                        double weight, double* out, void* ws, size_t ws_bytes,
+                                        void* stream) {
+  prism::OutAcc oa;
+  if (int r = out_mode(true, weight, &oa)) return r;
+  return multislice_step(p, xy, P, o, d, out, oa, ws, ws_bytes, stream);
 }
 
 int prism_probe_outputs(prism_plan* p, int f, double amax_mrad, const void* S, const double* xy,
                         int P, const prism_optics* o, const prism_detector* d, double* out,
                         void* ws, size_t ws_bytes, void* stream) {
   if (!d) return fail(PRISM_EINVAL, "null detector");
-  return probe_step(p, f, amax_mrad, S, xy, P, o, d, out, nullptr, ws, ws_bytes, stream);
+  return probe_step(p, f, amax_mrad, S, xy, P, o, d, out, nullptr, prism::OutAcc{0, 1.0}, ws,
+                    ws_bytes, stream);
+}
+
+int prism_probe_outputs_accumulate(prism_plan* p, int f, double amax_mrad, const void* S,
+                                   const double* xy, int P, const prism_optics* o,
+                                   const prism_detector* d, double weight, double* out, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  if (!d) return fail(PRISM_EINVAL, "null detector");
+  prism::OutAcc oa;
+  if (int r = out_mode(true, weight, &oa)) return r;
+  return probe_step(p, f, amax_mrad, S, xy, P, o, d, out, nullptr, oa, ws, ws_bytes, stream);
 }
 
 int prism_probe_cbed(prism_plan* p, int f, double amax_mrad, const void* S, const double* xy,
                      int P, const prism_optics* o, float* cbed, void* ws, size_t ws_bytes,
                      void* stream) {
-  return probe_step(p, f, amax_mrad, S, xy, P, o, nullptr, nullptr, cbed, ws, ws_bytes, stream);
+  return probe_step(p, f, amax_mrad, S, xy, P, o, nullptr, nullptr, cbed, prism::OutAcc{0, 1.0},
+                    ws, ws_bytes, stream);
+}
+
+int prism_probe_cbed_accumulate(prism_plan* p, int f, double amax_mrad, const void* S,
+                                const double* xy, int P, const prism_optics* o, double weight,
+                                float* cbed, void* ws, size_t ws_bytes, void* stream) {
+  prism::OutAcc oa;
+  if (int r = out_mode(true, weight, &oa)) return r;
+  return probe_step(p, f, amax_mrad, S, xy, P, o, nullptr, nullptr, cbed, oa, ws, ws_bytes,
+                    stream);
 }
 
 }  // extern "C"

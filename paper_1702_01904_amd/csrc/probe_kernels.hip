@@ -355,7 +355,8 @@ __global__ __launch_bounds__(256) void k_window_cols256_detect(const float2* __r
                                                                const float2* __restrict__ twW,
                                                                int f, DetBins bins,
                                                                double* __restrict__ partial,
-                                                               float* __restrict__ cbed) {
+                                                               float* __restrict__ cbed,
+                                                               OutAcc oa) {
   constexpr int R = kR4, LS = R + 1, TC = 16, TILES = kW4 / TC;
   constexpr int CS = R * LS + 1;  // column stride: 16 columns on distinct banks
   __shared__ float2 twl[R * R];
@@ -383,8 +384,8 @@ __global__ __launch_bounds__(256) void k_window_cols256_detect(const float2* __r
     float* dst = cbed + p * kW4 * kW4 + col;
 #pragma unroll
     for (int k2 = 0; k2 < R; ++k2)
-      dst[(size_t)(b + R * k2) * kW4] =
-          (float)(((double)v[k2].x * v[k2].x + (double)v[k2].y * v[k2].y) * inv_w2);
+      put_out(dst + (size_t)(b + R * k2) * kW4,
+              ((double)v[k2].x * v[k2].x + (double)v[k2].y * v[k2].y) * inv_w2, oa);
     return;
   }
   const long long kx = col < kW4 / 2 ? col : col - kW4;
@@ -442,7 +443,8 @@ __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __rest
                                                             const uint16_t* __restrict__ pix,
                                                             BinLists lists,
                                                             double* __restrict__ out,
-                                                            float* __restrict__ cbed) {
+                                                            float* __restrict__ cbed,
+                                                            OutAcc oa) {
   constexpr int NT = wd_nt(W);
   constexpr int NW = NT / 64;
   using Rows = RowBatch<W, W>;
@@ -487,7 +489,7 @@ __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __rest
       float* dst = cbed + (size_t)p * W * W;
       for (int e = tid; e < W * W; e += NT) {
         const float2 z = lds[lpad(e)];
-        dst[e] = (float)(((double)z.x * z.x + (double)z.y * z.y) * inv_w2);
+        put_out(dst + e, ((double)z.x * z.x + (double)z.y * z.y) * inv_w2, oa);
       }
     } else {
       for (int j0 = 0; j0 < lists.n; j0 += 8) {
@@ -512,7 +514,7 @@ __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __rest
         if (tid < 8 && j0 + tid < lists.n) {
           double sm = 0.0;
           for (int wv = 0; wv < NW; ++wv) sm += red[tid][wv];
-          out[(size_t)p * lists.n + j0 + tid] = sm * inv_w2;
+          put_out(out + (size_t)p * lists.n + j0 + tid, sm * inv_w2, oa);
         }
         __syncthreads();
       }
@@ -573,19 +575,19 @@ hipError_t launch_window256(float2* window, int np, const float2* twW, int f,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_window_cols256_detect<false>, dim3((unsigned)((size_t)np * window256_tiles())),
-                     dim3(256), 0, st, window, twW, f, bins, partial, (float*)nullptr);
+                     dim3(256), 0, st, window, twW, f, bins, partial, (float*)nullptr, OutAcc{});
   return hipGetLastError();
 }
 
 hipError_t launch_window256_cbed(float2* window, int np, const float2* twW, float* cbed,
-                                 hipStream_t st) {
+                                 OutAcc acc, hipStream_t st) {
   hipLaunchKernelGGL(k_window_rows256, dim3((unsigned)((size_t)np * kW4 / kR4)), dim3(256), 0, st,
                      window, twW);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   DetBins none{};
   hipLaunchKernelGGL(k_window_cols256_detect<true>, dim3((unsigned)((size_t)np * window256_tiles())),
-                     dim3(256), 0, st, window, twW, 1, none, (double*)nullptr, cbed);
+                     dim3(256), 0, st, window, twW, 1, none, (double*)nullptr, cbed, acc);
   return hipGetLastError();
 }
 
@@ -595,12 +597,12 @@ static unsigned window_grid(int np) { return (unsigned)std::min(np, PRISM_WD_GRI
 
 hipError_t launch_window_detect(const float2* window, int np, int w, const float2* twW,
                                 const uint16_t* pix, const BinLists& lists, double* out,
-                                hipStream_t st) {
+                                OutAcc acc, hipStream_t st) {
   if (np <= 0) return hipSuccess;
 #define WD(WW)                                                                                  \
   case WW:                                                                                      \
     hipLaunchKernelGGL((k_window_detect<WW, false>), dim3(window_grid(np)), dim3(wd_nt(WW)), 0, \
-                       st, window, np, twW, pix, lists, out, (float*)nullptr);                  \
+                       st, window, np, twW, pix, lists, out, (float*)nullptr, acc);             \
     break;
   switch (w) {
     WD(8)
@@ -616,14 +618,14 @@ hipError_t launch_window_detect(const float2* window, int np, int w, const float
 }
 
 hipError_t launch_window_cbed(const float2* window, int np, int w, const float2* twW,
-                              float* cbed, hipStream_t st) {
+                              float* cbed, OutAcc acc, hipStream_t st) {
   if (np <= 0) return hipSuccess;
   BinLists none{};
 #define WC(WW)                                                                                 \
   case WW:                                                                                     \
     hipLaunchKernelGGL((k_window_detect<WW, true>), dim3(window_grid(np)), dim3(wd_nt(WW)), 0, \
                        st, window, np, twW, (const uint16_t*)nullptr, none, (double*)nullptr,  \
-                       cbed);                                                                  \
+                       cbed, acc);                                                             \
     break;
   switch (w) {
     WC(8)

@@ -628,13 +628,13 @@ __global__ __launch_bounds__(256) void k_extract(const float2* __restrict__ stat
 }
 
 __global__ void k_reduce_partials(const double* __restrict__ partial, int nwaves, int tiles,
-                                  int n_det, double* __restrict__ out) {
+                                  int n_det, double* __restrict__ out, OutAcc acc) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nwaves * n_det) return;
   const int w = i / n_det, j = i % n_det;
   double s = 0.0;
   for (int t = 0; t < tiles; ++t) s += partial[((size_t)w * tiles + t) * n_det + j];
-  out[i] = s;
+  put_out(out + i, s, acc);
 }
 
 inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -775,9 +775,9 @@ hipError_t launch_probe_init(float2* state, const double* probe_xy, int p0, int 
 }
 
 hipError_t launch_reduce_partials(const double* partial, int nwaves, int tiles, int n_det,
-                                  double* out, hipStream_t st) {
+                                  double* out, OutAcc acc, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for((size_t)nwaves * n_det, 256)), dim3(256),
-                     0, st, partial, nwaves, tiles, n_det, out);
+                     0, st, partial, nwaves, tiles, n_det, out, acc);
   return hipGetLastError();
 }
 

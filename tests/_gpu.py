@@ -84,3 +84,57 @@ def multislice_outputs(plan, probes, optics, edges, ws_bytes=None):
     plan.multislice_outputs(xy, optics, edges, out, ws)
     torch.cuda.synchronize()
     return out.cpu().numpy()
+
+
+def upload(a, dtype=None):
+    """Host array to a device tensor (float64 unless dtype is given)."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.to(device(), dtype=dtype if dtype is not None else t.dtype)
+
+
+def frozen_phonon_prism(plan, f, amax, phase_configs, probes, optics, edges, cbed=False):
+    """Mean over configurations through the accumulating probe step: one
+    potential upload and S-matrix build per configuration, weight 1/K."""
+    import torch
+    K = len(phase_configs)
+    xy = upload(np.asarray(probes, dtype=np.float64))
+    B = plan.beam_count(f, amax)
+    ns = plan.n // 2
+    S = torch.empty((B, ns, ns), dtype=torch.complex64, device=device())
+    wsb = workspace(plan.build_workspace_bytes(f, amax)[0])
+    wsp = workspace(plan.probe_workspace_bytes(f, amax, optics)[0])
+    if cbed:
+        w = plan.n // (2 * f)
+        out = torch.zeros((len(probes), w, w), dtype=torch.float32, device=device())
+    else:
+        n_det = np.asarray(edges).reshape(-1, 2).shape[0]
+        out = torch.zeros((len(probes), n_det), dtype=torch.float64, device=device())
+    phases = [upload(np.asarray(ph, dtype=np.float32)) for ph in phase_configs]
+    for k, ph in enumerate(phases):
+        say(f"frozen phonon prism config {k + 1}/{K} n={plan.n} f={f} B={B} "
+            f"P={len(probes)} cbed={cbed}")
+        plan.set_potential_slices(ph)
+        plan.build_smatrix(f, amax, S, wsb)
+        if cbed:
+            plan.probe_cbed_accumulate(f, amax, S, xy, optics, 1.0 / K, out, wsp)
+        else:
+            plan.probe_outputs_accumulate(f, amax, S, xy, optics, edges, 1.0 / K, out, wsp)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def frozen_phonon_multislice(plan, phase_configs, probes, optics, edges):
+    import torch
+    K = len(phase_configs)
+    xy = upload(np.asarray(probes, dtype=np.float64))
+    n_det = np.asarray(edges).reshape(-1, 2).shape[0]
+    out = torch.zeros((len(probes), n_det), dtype=torch.float64, device=device())
+    ws = workspace(plan.multislice_workspace_bytes(n_det)[0])
+    phases = [upload(np.asarray(ph, dtype=np.float32)) for ph in phase_configs]
+    for k, ph in enumerate(phases):
+        say(f"frozen phonon multislice config {k + 1}/{K} n={plan.n} P={len(probes)}")
+        plan.set_potential_slices(ph)
+        plan.multislice_outputs_accumulate(xy, optics, edges, 1.0 / K, out, ws)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()

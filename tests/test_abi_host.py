@@ -226,6 +226,31 @@ def test_errors_before_any_launch():
     r = L.prism_probe_outputs(h, 2, amax, dummy, dummy, 4, ctypes.byref(optics), ctypes.byref(det),
                               dummy, dummy, 128, None)
     assert r == _native.PRISM_ENOSPACE
+    # accumulating forms: weight must be finite; otherwise the checks of the
+    # call they extend, and zero probes is a no-op
+    for wgt in (float("nan"), float("inf")):
+        r = L.prism_probe_outputs_accumulate(h, 2, amax, dummy, dummy, 4, ctypes.byref(optics),
+                                             ctypes.byref(det), wgt, dummy, dummy, 1 << 30, None)
+        assert r == _native.PRISM_EINVAL and b"weight" in L.prism_last_error()
+        r = L.prism_probe_cbed_accumulate(h, 2, amax, dummy, dummy, 4, ctypes.byref(optics), wgt,
+                                          dummy, dummy, 1 << 30, None)
+        assert r == _native.PRISM_EINVAL and b"weight" in L.prism_last_error()
+        r = L.prism_multislice_outputs_accumulate(h, dummy, 4, ctypes.byref(optics),
+                                                  ctypes.byref(det), wgt, dummy, dummy, 1 << 30,
+                                                  None)
+        assert r == _native.PRISM_EINVAL and b"weight" in L.prism_last_error()
+    r = L.prism_probe_outputs_accumulate(h, 2, amax, dummy, dummy, 4, ctypes.byref(optics),
+                                         None, 0.5, dummy, dummy, 1 << 30, None)
+    assert r == _native.PRISM_EINVAL
+    r = L.prism_probe_cbed_accumulate(h, 2, amax, dummy, dummy, 4, ctypes.byref(wider), 0.5,
+                                      dummy, dummy, 1 << 30, None)
+    assert r == _native.PRISM_EINVAL and b"alpha_max" in L.prism_last_error()
+    r = L.prism_multislice_outputs_accumulate(h, dummy, 4, ctypes.byref(optics), ctypes.byref(det),
+                                              0.5, dummy, dummy, 64, None)
+    assert r == _native.PRISM_ENOSPACE
+    assert L.prism_probe_outputs_accumulate(h, 2, amax, None, None, 0, ctypes.byref(optics),
+                                            ctypes.byref(det), 0.5, None, None, 0,
+                                            None) == _native.PRISM_OK
 
 
 def test_null_plan_and_pointers():
