@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--phonon-configs", type=int, default=2,
                     help="frozen-phonon configurations timed at the headline f (0: skip the "
                          "probe-side variants: resident-S step, CBED output, frozen phonons)")
+    ap.add_argument("--batch", default="batch32",
+                    help="mixed specimen batch timed with the batched build ('' none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--calibration-copy", action="store_true",
@@ -165,6 +167,84 @@ def cpu_baseline(d, f, amax, P_full):
                    f"probe step of {npr} of {P_full} probes ({t_probe * 1e3:.1f} ms/probe), "
                    f"scaled to the full build + scan"),
         "multislice_probes_per_s": round(1.0 / t_ms, 4),
+    }
+
+
+def run_batch(args, dev):
+    """Mixed batch of specimens: batched S-matrix build (shared launches)
+    against one build call per specimen, then every specimen's probe step."""
+    import torch
+    from synth import batch_workload
+    from paper_1702_01904_amd import (Plan, build_batch_workspace_bytes, build_smatrix_batch,
+                                      tile_order)
+    t0 = time.perf_counter()
+    specs = batch_workload(args.batch, args.seed)
+    log(f"batch {args.batch}: {len(specs)} specimens generated in {time.perf_counter() - t0:.1f} s")
+    ents = []
+    for d in specs:
+        f = d["f"]
+        p = Plan(d["n"], d["cell"], d["energy_keV"], d["thickness"])
+        ph = torch.from_numpy(d["phase"]).to(dev)
+        p.set_potential_slices(ph)
+        amax = p.alpha_max_default(d["optics"]["alpha_mrad"], f)
+        B = p.beam_count(f, amax)
+        S = torch.empty((B, d["n"] // 2, d["n"] // 2), dtype=torch.complex64, device=dev)
+        _, tx, ty = p.probe_group(f)
+        xy = torch.from_numpy(d["probes"][tile_order(d["n"] // 4, d["n"] // 4, tx, ty)]).to(dev)
+        out = torch.empty((len(d["probes"]), len(d["edges"])), dtype=torch.float64, device=dev)
+        ents.append(dict(d=d, f=f, plan=p, ph=ph, amax=amax, B=B, S=S, xy=xy, out=out))
+    items = [(e["plan"], e["f"], e["amax"], e["S"]) for e in ents]
+    wsb = torch.empty(build_batch_workspace_bytes(items)[0], dtype=torch.uint8, device=dev)
+    ws1 = torch.empty(max(e["plan"].build_workspace_bytes(e["f"], e["amax"])[0] for e in ents),
+                      dtype=torch.uint8, device=dev)
+    wsp = torch.empty(max(e["plan"].probe_workspace_bytes(e["f"], e["amax"], e["d"]["optics"])[0]
+                          for e in ents), dtype=torch.uint8, device=dev)
+
+    def ev_ms(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    ms_batched = ev_ms(lambda: build_smatrix_batch(items, wsb))
+    ms_single = ev_ms(lambda: [e["plan"].build_smatrix(e["f"], e["amax"], e["S"], ws1)
+                               for e in ents])
+    ms_probe = ev_ms(lambda: [e["plan"].probe_outputs(e["f"], e["amax"], e["S"], e["xy"],
+                                                      e["d"]["optics"], e["d"]["edges"],
+                                                      e["out"], wsp) for e in ents])
+    per_n = {}
+    for n in sorted({e["d"]["n"] for e in ents}):
+        sub = [e for e in ents if e["d"]["n"] == n]
+        its = [(e["plan"], e["f"], e["amax"], e["S"]) for e in sub]
+        mb = ev_ms(lambda: build_smatrix_batch(its, wsb))
+        m1 = ev_ms(lambda: [e["plan"].build_smatrix(e["f"], e["amax"], e["S"], ws1) for e in sub])
+        per_n[str(n)] = {"specimens": len(sub),
+                         "beam_slices": sum(e["B"] * len(e["d"]["thickness"]) for e in sub),
+                         "build_batched_ms": round(mb, 3), "build_per_specimen_ms": round(m1, 3)}
+    finite = all(bool(torch.isfinite(e["out"]).all()) for e in ents)
+    bsl = sum(e["B"] * len(e["d"]["thickness"]) for e in ents)
+    P = sum(len(e["d"]["probes"]) for e in ents)
+    log(f"batch: batched build {ms_batched:.1f} ms, one call per specimen {ms_single:.1f} ms, "
+        f"probe steps {ms_probe:.1f} ms")
+    del ents, items, wsb, ws1, wsp
+    torch.cuda.synchronize()
+    return {
+        "workload": f"{args.batch}: {len(specs)} random specimens, 0.1 A pixels, n in "
+                    f"{sorted({d['n'] for d in specs})}, 20-120 slices, f in "
+                    f"{sorted({d['f'] for d in specs})}, 80 keV, 20 mrad, (n/4)^2 probes each",
+        "specimens": len(specs), "beam_slices": bsl, "probes": P,
+        "build_batched_ms": round(ms_batched, 3), "build_per_specimen_ms": round(ms_single, 3),
+        "beam_slices_per_s_batched": round(bsl / (ms_batched * 1e-3), 1),
+        "beam_slices_per_s_per_specimen": round(bsl / (ms_single * 1e-3), 1),
+        "probe_steps_ms": round(ms_probe, 3),
+        "probes_per_s_probe_steps": round(P / (ms_probe * 1e-3), 1),
+        "probes_per_s_end_to_end": round(P / ((ms_batched + ms_probe) * 1e-3), 1),
+        "by_grid": per_n,
+        "outputs_finite": finite,
     }
 
 
@@ -330,6 +410,8 @@ def main():
                          "beams": c["B"], "active_beams": c["BA"]}
         del c
 
+    batch = run_batch(args, dev) if args.batch else None
+
     # multislice baseline on the same GPU, seeded probe subset
     multi_rate = None
     if args.ms_probes > 0:
@@ -380,6 +462,7 @@ def main():
         "per_f": per_f,
         "precision_variants": variants,
         "probe_side": probe_side,
+        "batch": batch,
         "kernel_ms_per_step": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,

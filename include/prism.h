@@ -144,6 +144,35 @@ int prism_set_potential_slices(prism_plan* plan, const float* phase_dev);
 int prism_build_smatrix(prism_plan* plan, int f, double alpha_max_mrad, void* smatrix_dev,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* Batched S-matrix build (Fig. 1c for several specimens at once). Each item
+ * names a plan (its geometry and potential slices, set as for
+ * prism_build_smatrix), an interpolation factor, an alpha_max and the
+ * item's output S-matrix (c64 [B][n/2][n/2], sized by prism_smatrix_bytes).
+ * Items whose plans share the grid, cell, energy and the thicknesses of their
+ * common slices form one group: the waves of all their beams run through the
+ * same launches, slice by slice, each wave multiplying by its own specimen's
+ * transmission (specimens with fewer slices drop out of later launches);
+ * groups run one after another. The results equal prism_build_smatrix of
+ * each item alone, bit for bit.
+ * Workspace (prism_build_batch_workspace_bytes): per group the
+ * transmissions of every member (sum of H n^2 complex64), the beam lists and
+ * up to 4 GiB of wave state; the minimum holds one wave of state.
+ * Errors: PRISM_EINVAL (null or invalid item, negative count), the checks of
+ * prism_build_smatrix for every item (message prefixed by the item index),
+ * PRISM_ENOSPACE, PRISM_EHIP. count == 0 is a no-op. The plans must not be
+ * used concurrently on other streams while the batch is in flight. */
+typedef struct {
+  prism_plan* plan;
+  int f;
+  double alpha_max_mrad;
+  void* smatrix_dev;
+} prism_build_item;
+
+int prism_build_batch_workspace_bytes(const prism_build_item* items, int count,
+                                      size_t* preferred, size_t* minimum);
+int prism_build_smatrix_batch(const prism_build_item* items, int count, void* ws,
+                              size_t ws_bytes, void* stream);
+
 /* Fig. 1d-f: for each probe position r0 (probe_xy_dev float64 [P][2],
  * Angstrom) sum the A = 1 beams of the S-matrix, weighted by
  * alpha_{m,n}(r0) = A e^{-i chi} e^{-2 pi i q.r0} / (W sqrt(B_A)), over the

@@ -12,7 +12,8 @@ import numpy as np
 from . import _native
 from ._native import PrismError, PrismOptics, PrismDetector, PrismGeometry  # noqa: F401
 
-__all__ = ["Plan", "PrismError", "tile_order", "untile"]
+__all__ = ["Plan", "PrismError", "build_batch_workspace_bytes", "build_smatrix_batch",
+           "tile_order", "untile"]
 
 
 def _ptr(t):
@@ -262,6 +263,43 @@ class Plan:
             _native.check(self._L.prism_multislice_outputs(*head, *tail))
         else:
             _native.check(self._L.prism_multislice_outputs_accumulate(*head, weight, *tail))
+
+
+def _batch_items(items, with_outputs):
+    arr = (_native.PrismBuildItem * max(1, len(items)))()
+    for k, it in enumerate(items):
+        plan, f, amax = it[0], int(it[1]), float(it[2])
+        S = it[3] if with_outputs else None
+        if S is not None:
+            import torch
+            B = plan.beam_count(f, amax)
+            _check_dev(S, torch.complex64, B * (plan.n // 2) ** 2, f"smatrix of item {k}")
+        arr[k] = _native.PrismBuildItem(plan._h, f, amax, _ptr(S) if S is not None else None)
+    return arr
+
+
+def build_batch_workspace_bytes(items):
+    """(preferred, minimum) workspace bytes of build_smatrix_batch for items
+    [(plan, f, alpha_max_mrad), ...] (or the 4-tuples of that call)."""
+    arr = _batch_items(items, False)
+    pref, mn = ctypes.c_size_t(), ctypes.c_size_t()
+    _native.check(_native.lib().prism_build_batch_workspace_bytes(arr, len(items),
+                                                                  ctypes.byref(pref),
+                                                                  ctypes.byref(mn)))
+    return pref.value, mn.value
+
+
+def build_smatrix_batch(items, workspace, stream=None):
+    """S-matrices of several specimens in shared launches.
+
+    items: [(plan, f, alpha_max_mrad, smatrix), ...], smatrix a complex64
+    device tensor [B][n/2][n/2] per item; workspace: uint8 device tensor.
+    """
+    import torch
+    _check_dev(workspace, torch.uint8, None, "workspace")
+    arr = _batch_items(items, True)
+    _native.check(_native.lib().prism_build_smatrix_batch(arr, len(items), _ptr(workspace),
+                                                          workspace.numel(), _stream_ptr(stream)))
 
 
 def tile_order(nx, ny, tx, ty):

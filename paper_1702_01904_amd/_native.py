@@ -26,7 +26,8 @@ EXPORTS = (
     "prism_set_probe_precision", "prism_set_potential_slices", "prism_build_smatrix",
     "prism_probe_outputs", "prism_probe_cbed", "prism_multislice_outputs",
     "prism_probe_outputs_accumulate", "prism_probe_cbed_accumulate",
-    "prism_multislice_outputs_accumulate", "prism_profile_enable", "prism_profile_report",
+    "prism_multislice_outputs_accumulate", "prism_build_batch_workspace_bytes",
+    "prism_build_smatrix_batch", "prism_profile_enable", "prism_profile_report",
     "prism_last_error",
 )
 
@@ -44,6 +45,11 @@ class PrismOptics(ctypes.Structure):
 
 class PrismDetector(ctypes.Structure):
     _fields_ = [("n_det", ctypes.c_int), ("edges_mrad", ctypes.POINTER(ctypes.c_double))]
+
+
+class PrismBuildItem(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("f", ctypes.c_int),
+                ("alpha_max_mrad", ctypes.c_double), ("smatrix_dev", ctypes.c_void_p)]
 
 
 class PrismError(RuntimeError):
@@ -100,6 +106,9 @@ def lib():
         "prism_multislice_outputs_accumulate": (I, [P, P, I, ctypes.POINTER(PrismOptics),
                                                     ctypes.POINTER(PrismDetector), D, P, P,
                                                     ctypes.c_size_t, P]),
+        "prism_build_batch_workspace_bytes": (I, [ctypes.POINTER(PrismBuildItem), I, SZ, SZ]),
+        "prism_build_smatrix_batch": (I, [ctypes.POINTER(PrismBuildItem), I, P, ctypes.c_size_t,
+                                          P]),
         "prism_profile_enable": (I, [P, I]),
         "prism_profile_report": (I, [P, ctypes.c_char_p, ctypes.c_size_t]),
         "prism_last_error": (ctypes.c_char_p, []),

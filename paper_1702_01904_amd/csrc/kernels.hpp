@@ -70,8 +70,12 @@ hipError_t launch_probe_init(float2* state, const double* probe_xy, int p0, int 
 int four_step_radix(int n);
 // tw2[m][j] = exp(-2 pi i j m / n), j, m < R (n entries; nothing for R = 0).
 hipError_t launch_twiddles2(float2* tw2, int n, hipStream_t st);
+// wtrans != nullptr: wave w multiplies by wtrans[w] + soff instead of trans_p
+// (device table of per-wave transmission bases: waves of several specimens
+// in one launch).
 hipError_t launch_row_pass(float2* state, int nwaves, int n, const float2* trans_p,
-                           const float2* twN, const float2* tw2, hipStream_t st);
+                           const float2* twN, const float2* tw2, hipStream_t st,
+                           const float2* const* wtrans = nullptr, size_t soff = 0);
 hipError_t launch_col_pass(float2* state, int nwaves, int n, const float2* prop_p,
                            const float2* twN, const float2* tw2, hipStream_t st);
 // Last slice of multislice STEM: FFT_y, propagator, band limit, |Psi|^2/n^2

@@ -14,6 +14,8 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <numeric>
+#include <set>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -114,6 +116,9 @@ struct prism_plan {
   // multislice aperture rows per (alpha, tilt): kept here because the
   // asynchronous copy to the device reads them after the call returns
   std::map<std::tuple<uint64_t, uint64_t, uint64_t>, std::vector<int32_t>> aper_rows;
+  // per-wave tables of batched builds led by this plan (same reason: the
+  // asynchronous copies read them later); set nodes keep their addresses
+  std::set<std::vector<uint64_t>> batch_tables;
 
   // scattering angle (rad) of integer full-grid |k|^2
   double theta(long long k2) const { return (lam * dq) * std::sqrt((double)k2); }
@@ -905,6 +910,250 @@ int prism_probe_cbed_accumulate(prism_plan* p, int f, double amax_mrad, const vo
   if (int r = out_mode(true, weight, &oa)) return r;
   return probe_step(p, f, amax_mrad, S, xy, P, o, nullptr, nullptr, cbed, oa, ws, ws_bytes,
                     stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched S-matrix build over several specimens.
+
+namespace {
+
+// Specimens whose waves can share launches: same grid, cell and energy, and
+// slice thicknesses that agree on their common slices (so one propagator
+// table serves all of them). Members are sorted by slice count, largest
+// first: the waves still running at slice s are then a prefix.
+struct BatchGroup {
+  std::vector<int> items;  // indices into the caller's item list
+  const prism_plan* ref;   // member with the most slices (its thicknesses)
+};
+
+bool same_medium(const prism_plan* a, const prism_plan* b) {
+  if (a->n != b->n || dbits(a->cell) != dbits(b->cell) || dbits(a->energy) != dbits(b->energy))
+    return false;
+  const int h = std::min(a->H, b->H);
+  for (int s = 0; s < h; ++s)
+    if (dbits(a->thick[s]) != dbits(b->thick[s])) return false;
+  return true;
+}
+
+int batch_groups(const prism_build_item* items, int count, std::vector<BatchGroup>* groups) {
+  groups->clear();
+  for (int i = 0; i < count; ++i) {
+    const prism_plan* p = items[i].plan;
+    if (!p) return fail(PRISM_EINVAL, "batch item " + std::to_string(i) + ": null plan");
+    const std::vector<int32_t>* mn;
+    if (int r = beams_checked(p, items[i].f, items[i].alpha_max_mrad, &mn))
+      return fail(r, "batch item " + std::to_string(i) + ": " + g_err);
+    BatchGroup* g = nullptr;
+    for (auto& cand : *groups) {
+      bool ok = true;
+      for (int j : cand.items) ok = ok && same_medium(items[j].plan, p);
+      if (ok) {
+        g = &cand;
+        break;
+      }
+    }
+    if (!g) {
+      groups->push_back(BatchGroup{{}, p});
+      g = &groups->back();
+    }
+    g->items.push_back(i);
+    if (p->H > g->ref->H) g->ref = p;
+  }
+  for (auto& g : *groups)
+    std::stable_sort(g.items.begin(), g.items.end(),
+                     [&](int a, int b) { return items[a].plan->H > items[b].plan->H; });
+  return PRISM_OK;
+}
+
+struct BatchWs {
+  float2* twN;
+  float2* twH;
+  float2* tw2;
+  double* thick;
+  float2* prop;
+  float2* trans;          // every member's slices, member after member
+  int32_t* mn;            // every member's beam list
+  const float2** wtab;    // per-wave transmission base of the current chunk
+  float2* state;
+};
+
+int item_beams(const prism_build_item& it) {
+  return (int)(it.plan->beams.at({it.f, dbits(it.alpha_max_mrad)}).size() / 2);
+}
+
+size_t batch_layout(const prism_build_item* items, const BatchGroup& g, int chunk, BatchWs* w,
+                    void* base) {
+  Carve c(base);
+  const int n = g.ref->n;
+  size_t slices = 0, beams = 0;
+  for (int i : g.items) {
+    slices += items[i].plan->H;
+    beams += item_beams(items[i]);
+  }
+  w->twN = c.take<float2>(n);
+  w->twH = c.take<float2>(n / 2);
+  w->tw2 = c.take<float2>(n);
+  w->thick = c.take<double>(g.ref->H);
+  w->prop = c.take<float2>((size_t)g.ref->H * n);
+  w->trans = c.take<float2>(slices * n * n);
+  w->mn = c.take<int32_t>(2 * beams);
+  w->wtab = c.take<const float2*>(chunk);
+  w->state = c.take<float2>((size_t)chunk * n * (n / 2));
+  return c.used + 256;
+}
+
+int batch_total_waves(const prism_build_item* items, const BatchGroup& g) {
+  int t = 0;
+  for (int i : g.items) t += item_beams(items[i]);
+  return t;
+}
+
+// Waves in flight per batched launch: up to 4 GiB of wave state.
+int batch_pref_chunk(int n, int total) {
+  const size_t cap = (size_t(1) << 32) / state_bytes(n);
+  return (int)std::max<size_t>(1, std::min<size_t>(cap, (size_t)total));
+}
+
+int batch_build_group(const prism_build_item* items, const BatchGroup& g, void* ws,
+                      size_t ws_bytes, hipStream_t st) {
+  prism_plan* lead = items[g.items.front()].plan;
+  const int n = g.ref->n, total = batch_total_waves(items, g);
+  BatchWs w;
+  int chunk = batch_pref_chunk(n, total);
+  while (chunk >= 1 && batch_layout(items, g, chunk, &w, nullptr) > ws_bytes)
+    chunk = chunk > 8 ? chunk * 3 / 4 : chunk - 1;
+  if (chunk < 1) return fail(PRISM_ENOSPACE, "workspace smaller than the batched build minimum");
+  batch_layout(items, g, chunk, &w, aligned_base(ws));
+  prism_plan* p = lead;  // profiling records go to the group's first plan
+  HIP_TRY(hipMemcpyAsync(w.thick, g.ref->thick.data(), g.ref->H * sizeof(double),
+                         hipMemcpyHostToDevice, st),
+          "copy slice thickness");
+  LAUNCH(p, st, "twiddles", prism::launch_twiddles(w.twN, n, st));
+  LAUNCH(p, st, "twiddles", prism::launch_twiddles(w.twH, n / 2, st));
+  LAUNCH(p, st, "twiddles", prism::launch_twiddles2(w.tw2, n, st));
+  LAUNCH(p, st, "prop_lut", prism::launch_prop_lut(w.prop, n, g.ref->H, w.thick, g.ref->lam, g.ref->dq, st));
+  // per member: transmissions and beam list; per wave: its member
+  struct Seg {
+    int item, first_beam, nb, H;
+    const float2* trans;
+    const int32_t* mn;
+  };
+  std::vector<Seg> waves_of;  // one segment per member, in wave order
+  size_t toff = 0, moff = 0;
+  for (int i : g.items) {
+    const prism_build_item& it = items[i];
+    const std::vector<int32_t>& mn = it.plan->beams.at({it.f, dbits(it.alpha_max_mrad)});
+    float2* tr = w.trans + toff;
+    LAUNCH(p, st, "transmission",
+           prism::launch_transmission(it.plan->phase, tr, (size_t)it.plan->H * n * n,
+                                      1.0f / (float)n, st));
+    HIP_TRY(hipMemcpyAsync(w.mn + moff, mn.data(), mn.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st),
+            "copy beam list");
+    waves_of.push_back(Seg{i, 0, (int)(mn.size() / 2), it.plan->H, tr, w.mn + moff});
+    toff += (size_t)it.plan->H * n * n;
+    moff += mn.size();
+  }
+  const size_t splane = (size_t)(n / 2) * (n / 2), wave = (size_t)n * (n / 2);
+  // walk the waves chunk by chunk (a member may span chunks)
+  size_t seg = 0;
+  int seg_b = 0;  // next beam of waves_of[seg]
+  while (seg < waves_of.size()) {
+    struct Part {
+      const Seg* s;
+      int b0, nb, w0;
+    };
+    std::vector<Part> parts;
+    std::vector<uint64_t> tab;
+    int used = 0;
+    while (used < chunk && seg < waves_of.size()) {
+      const Seg& sg = waves_of[seg];
+      const int take = std::min(chunk - used, sg.nb - seg_b);
+      parts.push_back(Part{&sg, seg_b, take, used});
+      for (int k = 0; k < take; ++k) tab.push_back((uint64_t)(uintptr_t)sg.trans);
+      used += take;
+      seg_b += take;
+      if (seg_b == sg.nb) {
+        ++seg;
+        seg_b = 0;
+      }
+    }
+    const std::vector<uint64_t>& kept = *lead->batch_tables.insert(tab).first;
+    HIP_TRY(hipMemcpyAsync(w.wtab, kept.data(), kept.size() * sizeof(uint64_t),
+                           hipMemcpyHostToDevice, st),
+            "copy wave table");
+    for (const Part& pt : parts) {
+      const prism_build_item& it = items[pt.s->item];
+      LAUNCH(p, st, "beam_init",
+             prism::launch_beam_init(w.state + (size_t)pt.w0 * wave, pt.s->mn, pt.b0, pt.nb, n,
+                                     it.f, w.twN, st));
+    }
+    // parts are in decreasing slice count: the first `active` waves still run
+    const int hmax = parts.front().s->H;
+    for (int s = 0; s < hmax; ++s) {
+      int active = 0;
+      for (const Part& pt : parts)
+        if (pt.s->H > s) active = pt.w0 + pt.nb;
+      LAUNCH(p, st, "row_pass",
+             prism::launch_row_pass(w.state, active, n, nullptr, w.twN, w.tw2, st,
+                                    w.wtab, (size_t)s * n * n));
+      LAUNCH(p, st, "col_pass",
+             prism::launch_col_pass(w.state, active, n, w.prop + (size_t)s * n, w.twN, w.tw2, st));
+    }
+    for (const Part& pt : parts) {
+      const prism_build_item& it = items[pt.s->item];
+      float2* S = static_cast<float2*>(it.smatrix_dev) + (size_t)pt.b0 * splane;
+      LAUNCH(p, st, "extract",
+             prism::launch_extract(w.state + (size_t)pt.w0 * wave, pt.nb, n, S, w.twH, st));
+    }
+  }
+  return PRISM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int prism_build_batch_workspace_bytes(const prism_build_item* items, int count, size_t* pref,
+                                      size_t* minimum) {
+  if (!pref || !minimum || (count > 0 && !items)) return fail(PRISM_EINVAL, "null argument");
+  if (count < 0) return fail(PRISM_EINVAL, "negative item count");
+  std::vector<BatchGroup> groups;
+  if (int r = batch_groups(items, count, &groups)) return r;
+  *pref = *minimum = 0;
+  for (const auto& g : groups) {
+    BatchWs w;
+    const int total = batch_total_waves(items, g);
+    *pref = std::max(*pref, batch_layout(items, g, batch_pref_chunk(g.ref->n, total), &w, nullptr));
+    *minimum = std::max(*minimum, batch_layout(items, g, 1, &w, nullptr));
+  }
+  return PRISM_OK;
+}
+
+int prism_build_smatrix_batch(const prism_build_item* items, int count, void* ws, size_t ws_bytes,
+                              void* stream) {
+  if (count < 0) return fail(PRISM_EINVAL, "negative item count");
+  if (count == 0) return PRISM_OK;
+  if (!items) return fail(PRISM_EINVAL, "null argument");
+  std::vector<BatchGroup> groups;
+  if (int r = batch_groups(items, count, &groups)) return r;
+  for (int i = 0; i < count; ++i) {
+    if (!items[i].smatrix_dev) return fail(PRISM_EINVAL, "batch item " + std::to_string(i) + ": null S-matrix");
+    if (!items[i].plan->phase)
+      return fail(PRISM_ENOTREADY, "batch item " + std::to_string(i) + ": potential slices not set");
+  }
+  if (!ws) return fail(PRISM_EINVAL, "null device buffer");
+  for (const auto& g : groups) {  // every group must fit before anything is enqueued
+    BatchWs w;
+    if (batch_layout(items, g, 1, &w, nullptr) > ws_bytes)
+      return fail(PRISM_ENOSPACE, "workspace smaller than the batched build minimum");
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (const auto& g : groups)
+    if (int r = batch_build_group(items, g, ws, ws_bytes, st)) return r;
+  return PRISM_OK;
 }
 
 }  // extern "C"

@@ -125,9 +125,13 @@ __global__ void k_beam_init(float2* __restrict__ state, const int32_t* __restric
 // straight from HBM (its inputs at |kx| >= n/4 are zero), its last stage
 // stays in registers, is multiplied by t_p / n and feeds the forward's first
 // stage, and the forward's last stage stores only the kept half band.
-template <int N>
+// WT: each wave w reads its own transmission wtrans[w] + soff (waves of
+// several specimens in one launch); otherwise every wave reads trans.
+template <int N, bool WT>
 __global__ __launch_bounds__(kRowNT) void k_row_pass(float2* __restrict__ state,
                                                      const float2* __restrict__ trans,
+                                                     const float2* const* __restrict__ wtrans,
+                                                     size_t soff,
                                                      const float2* __restrict__ twN) {
   constexpr int NT = kRowNT;
   constexpr int NSEQ = row_nseq(N);
@@ -167,7 +171,8 @@ __global__ __launch_bounds__(kRowNT) void k_row_pass(float2* __restrict__ state,
     int sq, j;
     stage_coords<B, SL::NB>(tid + p * NT, sq, j);
     dft<RL, true>(v[p]);
-    const float2* t = trans + (size_t)((row0 + sq) & (size_t)(N - 1)) * N + j;
+    const float2* tb = WT ? wtrans[(row0 + sq) / N] + soff : trans;
+    const float2* t = tb + (size_t)((row0 + sq) & (size_t)(N - 1)) * N + j;
 #pragma unroll
     for (int r = 0; r < RL; ++r) v[p][r] = cmul(v[p][r], t[r * NSL]);
   }
@@ -234,9 +239,11 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int R>
+template <int R, bool WT>
 __global__ __launch_bounds__(256) void k_row_pass4(float2* __restrict__ state,
                                                    const float2* __restrict__ trans,
+                                                   const float2* const* __restrict__ wtrans,
+                                                   size_t soff,
                                                    const float2* __restrict__ tw2, int iters) {
   constexpr int N = R * R, H2 = N / 2, Q = R / 4, LS = R + 1;
   constexpr int RPW = 64 / R;             // rows per wave
@@ -282,7 +289,8 @@ __global__ __launch_bounds__(256) void k_row_pass4(float2* __restrict__ state,
     load_src(min(it + 1, iters - 1), it + 1 < iters);
     float2 tt[R];
     {
-      const float2* t = trans + (row & (size_t)(N - 1)) * N + j;
+      const float2* tb = WT ? wtrans[row / N] + soff : trans;
+      const float2* t = tb + (row & (size_t)(N - 1)) * N + j;
 #pragma unroll
       for (int d = 0; d < R; ++d) tt[d] = t[R * d];
     }
@@ -699,25 +707,37 @@ static int pick_iters(int units, int maxit, int min_wgs) {
 }
 
 hipError_t launch_row_pass(float2* state, int nwaves, int n, const float2* trans_p,
-                           const float2* twN, const float2* tw2, hipStream_t st) {
+                           const float2* twN, const float2* tw2, hipStream_t st,
+                           const float2* const* wtrans, size_t soff) {
   // row groups of 4 waves x 64/R rows; the iteration count is the largest
   // power of two (up to kRow4Iter) that divides them and still leaves two
   // workgroups per compute unit
+  const bool wt = wtrans != nullptr;
   if (n == 1024 || n == 256) {
     const int R = n == 1024 ? 32 : 16;
     const int groups = nwaves * n / (4 * 64 / R);
     const int it = pick_iters(groups, kRow4Iter, 512);
-    if (R == 32)
-      hipLaunchKernelGGL(k_row_pass4<32>, dim3((unsigned)(groups / it)), dim3(256), 0, st, state,
-                         trans_p, tw2, it);
-    else
-      hipLaunchKernelGGL(k_row_pass4<16>, dim3((unsigned)(groups / it)), dim3(256), 0, st, state,
-                         trans_p, tw2, it);
+    const dim3 grid((unsigned)(groups / it));
+#define ROW4(RR, WW)                                                                            \
+  hipLaunchKernelGGL((k_row_pass4<RR, WW>), grid, dim3(256), 0, st, state, trans_p, wtrans, soff, \
+                     tw2, it)
+    if (R == 32) {
+      if (wt) ROW4(32, true); else ROW4(32, false);
+    } else {
+      if (wt) ROW4(16, true); else ROW4(16, false);
+    }
+#undef ROW4
     return hipGetLastError();
   }
 #define ROW(NN)                                                                                 \
-  hipLaunchKernelGGL(k_row_pass<NN>, dim3((unsigned)((size_t)nwaves * NN / row_nseq(NN))),     \
-                     dim3(kRowNT), 0, st, state, trans_p, twN)
+  if (wt)                                                                                       \
+    hipLaunchKernelGGL((k_row_pass<NN, true>),                                                  \
+                       dim3((unsigned)((size_t)nwaves * NN / row_nseq(NN))), dim3(kRowNT), 0,   \
+                       st, state, trans_p, wtrans, soff, twN);                                  \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_row_pass<NN, false>),                                                 \
+                       dim3((unsigned)((size_t)nwaves * NN / row_nseq(NN))), dim3(kRowNT), 0,   \
+                       st, state, trans_p, wtrans, soff, twN)
   PRISM_DISPATCH_N(n, ROW)
 #undef ROW
   return hipGetLastError();

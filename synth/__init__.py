@@ -17,7 +17,7 @@ each atom a 2D Gaussian of standard deviation 0.3 A and peak phase
 xy cell. The phase is rounded to float32 once here, so the oracle and the
 GPU see bit-identical slices.
 """
-from .configs import CONFIGS, get_config
+from .configs import BATCHES, CONFIGS, get_config
 from .specimen import (
     random_atoms,
     fcc_atoms,
@@ -27,6 +27,8 @@ from .specimen import (
     annular_edges,
     build_inputs,
     phonon_configurations,
+    batch_workload,
+    batch_shapes,
 )
 
 __all__ = [
@@ -40,4 +42,7 @@ __all__ = [
     "annular_edges",
     "build_inputs",
     "phonon_configurations",
+    "batch_workload",
+    "batch_shapes",
+    "BATCHES",
 ]

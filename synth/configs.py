@@ -70,6 +70,25 @@ CONFIGS = {
     ),
 }
 
+# Mixed batches of specimens (many small and large specimens built
+# together). Each entry is a recipe for ``batch_workload``: grid sizes with
+# 0.1 A pixels, slice counts drawn uniformly, interpolation factors drawn
+# among those the grid admits, random atoms at 0.015 A^-3.
+BATCHES = {
+    # 32 specimens on power-of-two grids, 20-120 slices, f in {4, 8, 16}.
+    "batch32": dict(count=32, sizes=(256, 512, 1024), h_range=(20, 120), f_choices=(4, 8, 16),
+                    pixel_A=0.1, density=0.015, slice_A=2.0, energy_keV=80.0,
+                    optics=dict(alpha_mrad=20.0, C1_A=0.0, C3_A=0.0),
+                    detectors=[(0.0, 20.0), (20.0, 40.0), (40.0, 100.0)],
+                    z_choices=(6, 14, 29, 79)),
+    # Small mix for parity against the oracle.
+    "batch_small": dict(count=6, sizes=(128, 256), h_range=(2, 6), f_choices=(1, 2, 4),
+                        pixel_A=0.1, density=0.015, slice_A=2.0, energy_keV=80.0,
+                        optics=dict(alpha_mrad=20.0, C1_A=0.0, C3_A=0.0),
+                        detectors=[(0.0, 20.0), (20.0, 40.0), (40.0, 100.0)],
+                        z_choices=(6, 14, 29, 79)),
+}
+
 
 def get_config(name):
     """Return a deep copy of a named workload definition."""

@@ -7,7 +7,7 @@ outside [0, H t) are clipped into the first or last slice.
 """
 import numpy as np
 
-from .configs import get_config
+from .configs import BATCHES, get_config
 
 GAUSS_SIGMA_A = 0.3          # standard deviation of each atom's phase blob
 
@@ -259,4 +259,54 @@ def phonon_configurations(name_or_cfg, seed, n_configs, jitter_A=None, n_slices=
     d["atom_configs"] = atoms
     d["jitter_A"] = float(jitter_A)
     return d
+
+
+def _batch_shape(rec, rng):
+    n = int(rng.choice(np.asarray(rec["sizes"])))
+    H = int(rng.integers(rec["h_range"][0], rec["h_range"][1] + 1))
+    fs = [f for f in rec["f_choices"] if n % (2 * f) == 0 and 8 <= n // (2 * f) <= 256]
+    return n, H, int(rng.choice(np.asarray(fs)))
+
+
+def batch_shapes(name_or_recipe, seed=0, count=None):
+    """(n, H, f) of every specimen of a batch, without generating atoms."""
+    rec = BATCHES[name_or_recipe] if isinstance(name_or_recipe, str) else name_or_recipe
+    count = rec["count"] if count is None else int(count)
+    return [_batch_shape(rec, np.random.default_rng([int(seed), i])) for i in range(count)]
+
+
+def batch_workload(name_or_recipe, seed=0, count=None, indices=None):
+    """A seeded mixed batch of specimens; returns a list of ``build_inputs``
+    dicts, each with its own ``f`` (the interpolation factor drawn for it).
+
+    Per specimen, from ``default_rng([seed, i])``: grid side n from the
+    recipe's sizes, slice count H uniform in h_range, f among the recipe's
+    factors with n % (2 f) == 0 and 8 <= n / (2 f) <= 256, then the atoms
+    (random, density atoms per A^3 in an n * pixel square cell of
+    thickness H * slice). The scan is the (n/4) x (n/4) raster at two
+    S-matrix pixels. ``indices`` builds only those specimens of the batch
+    (the others are not generated); ``batch_shapes`` lists (n, H, f) of all.
+    """
+    rec = BATCHES[name_or_recipe] if isinstance(name_or_recipe, str) else name_or_recipe
+    count = rec["count"] if count is None else int(count)
+    out = []
+    for i in (range(count) if indices is None else indices):
+        rng = np.random.default_rng([int(seed), i])
+        n, H, f = _batch_shape(rec, rng)
+        side = n * rec["pixel_A"]
+        depth = H * rec["slice_A"]
+        n_atoms = int(round(rec["density"] * side * side * depth))
+        cfg = dict(
+            specimen=dict(kind="random", cell=(side, side, depth), n_atoms=n_atoms,
+                          z_choices=tuple(rec["z_choices"])),
+            n=n, n_slices=H, slice_A=rec["slice_A"], energy_keV=rec["energy_keV"],
+            optics=dict(rec["optics"]),
+            scan=dict(nx=n // 4, ny=n // 4, step_A=4 * rec["pixel_A"], origin_A=(0.0, 0.0)),
+            detectors=list(rec["detectors"]), f_values=(f,),
+        )
+        d = build_inputs(cfg, int(rng.integers(0, 2 ** 31)))
+        d["name"] = f"{name_or_recipe if isinstance(name_or_recipe, str) else 'batch'}[{i}]"
+        d["f"] = f
+        out.append(d)
+    return out
 

@@ -270,3 +270,52 @@ def test_tile_order_roundtrip():
     assert np.array_equal(untile(vals, perm), np.arange(16 * 12) * 3)
     odd = tile_order(19, 7, 8, 8)
     assert sorted(odd.tolist()) == list(range(19 * 7))
+
+
+def test_batch_build_validation():
+    from paper_1702_01904_amd import build_batch_workspace_bytes
+    L = _native.lib()
+    a = Plan(128, 12.8, 80.0, [2.0] * 4)
+    b = Plan(128, 12.8, 80.0, [2.0] * 6)      # same medium, more slices: one group
+    c = Plan(128, 12.8, 120.0, [2.0] * 4)     # other energy: own group
+    fa, fb, fc = 2, 1, 2
+    items = [(a, fa, a.alpha_max_default(20.0, fa)), (b, fb, b.alpha_max_default(20.0, fb)),
+             (c, fc, c.alpha_max_default(20.0, fc))]
+    pref, mn = build_batch_workspace_bytes(items)
+    # one group's minimum: the transmissions of both members (10 slices of
+    # 128^2 complex64) dominate
+    assert mn >= 10 * 128 * 128 * 8 and pref >= mn
+    p1, m1 = build_batch_workspace_bytes(items[:2])
+    p2, m2 = build_batch_workspace_bytes(items[2:])
+    assert pref == max(p1, p2) and mn == max(m1, m2)
+    arr = (_native.PrismBuildItem * 3)()
+    dummy = ctypes.c_void_p(0x1000)
+    for k, (p, f, am) in enumerate(items):
+        arr[k] = _native.PrismBuildItem(p._h, f, am, dummy)
+    # potential slices not set (checked per item, before any launch)
+    r = L.prism_build_smatrix_batch(arr, 3, dummy, 1 << 30, None)
+    assert r == _native.PRISM_ENOTREADY and b"item 0" in L.prism_last_error()
+    # bad items
+    assert L.prism_build_smatrix_batch(arr, -1, dummy, 1 << 30, None) == _native.PRISM_EINVAL
+    assert L.prism_build_smatrix_batch(None, 2, dummy, 1 << 30, None) == _native.PRISM_EINVAL
+    assert L.prism_build_smatrix_batch(arr, 0, None, 0, None) == _native.PRISM_OK
+    bad = (_native.PrismBuildItem * 2)()
+    bad[0] = arr[0]
+    bad[1] = _native.PrismBuildItem(b._h, 3, 30.0, dummy)        # 128 % 6 != 0
+    r = L.prism_build_smatrix_batch(bad, 2, dummy, 1 << 30, None)
+    assert r == _native.PRISM_EINVAL and b"item 1" in L.prism_last_error()
+    bad[1] = _native.PrismBuildItem(None, 1, 30.0, dummy)
+    assert L.prism_build_smatrix_batch(bad, 2, dummy, 1 << 30, None) == _native.PRISM_EINVAL
+    pref_q, min_q = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.prism_build_batch_workspace_bytes(bad, 2, ctypes.byref(pref_q),
+                                               ctypes.byref(min_q)) == _native.PRISM_EINVAL
+    for p in (a, b, c):
+        L.prism_set_potential_slices(p._h, dummy)
+    nulls = (_native.PrismBuildItem * 1)()
+    nulls[0] = _native.PrismBuildItem(a._h, fa, items[0][2], None)
+    r = L.prism_build_smatrix_batch(nulls, 1, dummy, 1 << 30, None)
+    assert r == _native.PRISM_EINVAL and b"S-matrix" in L.prism_last_error()
+    assert L.prism_build_smatrix_batch(arr, 3, None, 1 << 30, None) == _native.PRISM_EINVAL
+    # workspace below the minimum of the first group
+    r = L.prism_build_smatrix_batch(arr, 3, dummy, mn // 2, None)
+    assert r == _native.PRISM_ENOSPACE
