@@ -66,6 +66,9 @@ def parse():
                          "probe-side variants: resident-S step, CBED output, frozen phonons)")
     ap.add_argument("--batch", default="batch32",
                     help="mixed specimen batch timed with the batched build ('' none)")
+    ap.add_argument("--serve-rates", default="50,150,250",
+                    help="query arrival rates (per s) of the serving run ('' none)")
+    ap.add_argument("--serve-queries", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--calibration-copy", action="store_true",
@@ -248,6 +251,120 @@ def run_batch(args, dev):
     }
 
 
+def run_serving(args, plan_fcc, d_fcc, dev):
+    """Poisson-arriving probe queries against resident S-matrices.
+
+    Resident: the fcc1024 specimen at f = 4, 8, 16 and the s512 specimen at
+    f = 2, 4. A query picks one of them, a probe count log-uniform in
+    [64, 65536] and that many seeded positions inside the cell; the driver
+    submits queries as they arrive, flushes whenever something arrived, and
+    polls for completions. Latency = completion seen - arrival.
+    """
+    import math
+    import torch
+    from synth import build_inputs
+    from paper_1702_01904_amd import Plan, Server, tile_order
+    d512 = build_inputs("s512", args.seed)
+    p512 = Plan(d512["n"], d512["cell"], d512["energy_keV"], d512["thickness"])
+    ph512 = torch.from_numpy(d512["phase"]).to(dev)
+    p512.set_potential_slices(ph512)
+    res = [(plan_fcc, d_fcc, f) for f in (4, 8, 16)] + [(p512, d512, f) for f in (2, 4)]
+    max_det = max(len(d_fcc["edges"]), len(d512["edges"]))
+    ents, probe_ws = [], 0
+    for p, dd, f in res:
+        amax = p.alpha_max_default(dd["optics"]["alpha_mrad"], f)
+        S = torch.empty((p.beam_count(f, amax), p.n // 2, p.n // 2), dtype=torch.complex64,
+                        device=dev)
+        ents.append(dict(p=p, d=dd, f=f, amax=amax, S=S))
+        probe_ws = max(probe_ws, p.probe_workspace_bytes(f, amax, dd["optics"])[0])
+    n_streams, max_probes = 4, 65536
+    ws = torch.empty(Server.workspace_bytes(n_streams, max_probes, max_det, probe_ws),
+                     dtype=torch.uint8, device=dev)
+    wsb = torch.empty(max(e["p"].build_workspace_bytes(e["f"], e["amax"])[0] for e in ents),
+                      dtype=torch.uint8, device=dev)
+    budget = sum(e["S"].numel() * 8 for e in ents)
+    srv = Server(budget, ws, n_streams=n_streams, max_probes=max_probes, max_det=max_det)
+    for e in ents:   # builds run one after another: they share one build workspace
+        e["id"] = srv.admit(e["p"], e["f"], e["amax"], e["S"], wsb)
+        torch.cuda.synchronize()
+    rng = np.random.default_rng(args.seed + 99)
+    pools = []
+    for e in ents:
+        # the (n/4) x (n/4) raster at two S-matrix pixels in probe-tile order,
+        # repeated up to max_probes: a query is a contiguous run of it (a
+        # region of a scan), so its probes share union windows
+        n4 = e["p"].n // 4
+        _, tx, ty = e["p"].probe_group(e["f"])
+        step = e["d"]["cell"] / n4
+        i = np.arange(n4, dtype=np.float64) * step
+        ras = np.stack([np.tile(i, n4), np.repeat(i, n4)], axis=1)[tile_order(n4, n4, tx, ty)]
+        reps = -(-max_probes // len(ras))
+        pools.append(torch.from_numpy(np.ascontiguousarray(np.tile(ras, (reps, 1))[:max_probes]))
+                     .to(dev))
+    nq = args.serve_queries
+
+    def run(rate, n_q, warm=False):
+        gaps = rng.exponential(1.0 / rate, n_q)
+        arr = np.cumsum(gaps) - gaps[0]
+        which = rng.integers(0, len(ents), n_q)
+        P = np.exp(rng.uniform(math.log(64), math.log(65536), n_q)).astype(np.int64)
+        starts = rng.integers(0, max_probes - P + 1)
+        nds = [len(ents[w]["d"]["edges"]) for w in which]
+        pool = torch.empty(int(sum(int(p) * nd for p, nd in zip(P, nds))), dtype=torch.float64,
+                           device=dev)
+        tickets, outs, off = [], [], 0
+        for k in range(n_q):
+            outs.append(pool[off:off + int(P[k]) * nds[k]].view(int(P[k]), nds[k]))
+            off += int(P[k]) * nds[k]
+        torch.cuda.synchronize()
+        done_at = {}
+        flushes = 0
+        t0 = time.perf_counter()
+        i = 0
+        while len(done_at) < n_q:
+            now = time.perf_counter() - t0
+            sub = False
+            while i < n_q and arr[i] <= now:
+                e = ents[which[i]]
+                xy = pools[which[i]][starts[i]:starts[i] + P[i]]
+                tickets.append(srv.submit(e["id"], xy, e["d"]["optics"], e["d"]["edges"],
+                                          outs[i]))
+                i += 1
+                sub = True
+            if sub:
+                srv.flush()
+                flushes += 1
+            for t in srv.poll():
+                done_at[t] = time.perf_counter() - t0
+        lat = np.array([done_at[tickets[k]] - arr[k] for k in range(n_q)]) * 1e3
+        span = max(done_at.values())
+        if warm:
+            return None
+        return {"offered_queries_per_s": rate, "queries": n_q, "probes": int(P.sum()),
+                "flushes": flushes,
+                "probes_per_s": round(float(P.sum()) / span, 1),
+                "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+                "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
+                "latency_ms_max": round(float(lat.max()), 3)}
+
+    run(1000.0, 20, warm=True)
+    rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
+    sweep = []
+    for r in rates:
+        rec = run(r, nq)
+        log(f"serving at {r:g} queries/s: p50 {rec['latency_ms_p50']} ms, p99 "
+            f"{rec['latency_ms_p99']} ms, {rec['probes_per_s']:.0f} probes/s")
+        sweep.append(rec)
+    srv.close()
+    del srv, ws, wsb, ents, pools, ph512
+    torch.cuda.synchronize()
+    return {"resident": "fcc1024 f=4,8,16 and s512 f=2,4 S-matrices "
+                        f"({budget / 1e9:.2f} GB), {n_streams} streams",
+            "queries": "Poisson arrivals, probes per query log-uniform in [64, 65536], "
+                       "a run of the (n/4)^2 scan raster in probe-tile order",
+            "sweep": sweep}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -412,6 +529,8 @@ def main():
 
     batch = run_batch(args, dev) if args.batch else None
 
+    serving = run_serving(args, plan, d, dev) if args.serve_rates else None
+
     # multislice baseline on the same GPU, seeded probe subset
     multi_rate = None
     if args.ms_probes > 0:
@@ -463,6 +582,7 @@ def main():
         "precision_variants": variants,
         "probe_side": probe_side,
         "batch": batch,
+        "serving": serving,
         "kernel_ms_per_step": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -236,6 +236,67 @@ int prism_multislice_outputs_accumulate(prism_plan* plan, const double* probe_xy
                                         double* out_dev, void* ws, size_t ws_bytes,
                                         void* stream);
 
+/* ---------------------------------------------------------------------
+ * Serving: resident S-matrices and merged probe queries.
+ *
+ * An S-matrix, once built, serves any probe positions and probe settings
+ * ("PRISM Simulations with Varying Probe Size": the S-matrix is re-used as
+ * long as the specimen and f stay the same). A server keeps admitted
+ * S-matrices under a byte budget and queues probe queries; a flush merges
+ * every queued query of one (specimen, optics, detector) into probe-step
+ * calls of up to max_probes positions and spreads them over n_streams HIP
+ * streams (created by the server, default priority). A query's result is
+ * the prism_probe_outputs result for its own positions.
+ *
+ * Workspace: the caller's device buffer, split into one region per stream;
+ * a region holds the staged positions (max_probes x 2 doubles) and outputs
+ * (max_probes x max_det doubles) of one merged call plus the probe-step
+ * workspace (probe_ws_bytes, at least the probe step's minimum for every
+ * admitted specimen and optics; prism_server_submit checks it).
+ * Buffers named in admit and submit (S-matrix, positions, outputs) must stay
+ * valid until the query is reported done by poll or wait (S-matrix: until
+ * evicted). A server is used by one host thread at a time.
+ * --------------------------------------------------------------------- */
+typedef struct prism_server prism_server;
+
+int prism_server_workspace_bytes(int n_streams, int max_probes, int max_det,
+                                 size_t probe_ws_bytes, size_t* bytes);
+/* n_streams in [1, 16], max_probes >= 1, max_det in [1, PRISM_MAX_DET].
+ * PRISM_ENOSPACE if ws_bytes is below the staging size. */
+int prism_server_create(prism_server** server, size_t smatrix_budget_bytes, int n_streams,
+                        int max_probes, int max_det, void* ws, size_t ws_bytes);
+/* Waits for the server's streams, then frees the host state (never the
+ * caller's device buffers). */
+void prism_server_destroy(prism_server* server);
+/* Admit one specimen's S-matrix (prism_smatrix_bytes of it must fit in the
+ * remaining budget, else PRISM_ENOSPACE). With build_ws != NULL the server
+ * builds it (prism_build_smatrix on one of its streams; the plan's
+ * potential slices must be set); with build_ws == NULL smatrix_dev must
+ * already hold it (built by the caller and synchronised). *id names it. */
+int prism_server_admit(prism_server* server, prism_plan* plan, int f, double alpha_max_mrad,
+                       void* smatrix_dev, void* build_ws, size_t build_ws_bytes, int* id);
+/* Release a specimen's budget after its dispatched queries have finished
+ * (waits for the server's streams). PRISM_EINVAL if queries are queued. */
+int prism_server_evict(prism_server* server, int id);
+/* Queue one query: n_probes in [0, max_probes] positions (device float64
+ * [P][2], A), optics and detector as in prism_probe_outputs (copied), out_dev
+ * float64 [P][n_det]. Returns a ticket. Nothing runs before the next flush. */
+int prism_server_submit(prism_server* server, int id, const double* probe_xy_dev, int n_probes,
+                        const prism_optics* optics, const prism_detector* detector,
+                        double* out_dev, long long* ticket);
+/* Dispatch every queued query (merged as above). */
+int prism_server_flush(prism_server* server);
+/* Report finished queries: up to capacity tickets into done, *count of them.
+ * A ticket is reported once (by poll or by wait). */
+int prism_server_poll(prism_server* server, long long* done, int capacity, int* count);
+/* Block until one flushed query is done (PRISM_EINVAL if it is still queued
+ * or unknown). */
+int prism_server_wait(prism_server* server, long long ticket);
+/* Admitted S-matrix bytes, queued queries and dispatched-but-unreported
+ * queries (any pointer may be NULL). */
+int prism_server_stats(const prism_server* server, size_t* smatrix_bytes_used, int* queued,
+                       int* in_flight);
+
 /* Per-kernel timing: while enabled, every kernel launch of this plan is
  * bracketed by HIP events recorded on its stream. prism_profile_report
  * waits for the recorded events, writes one line per kernel name

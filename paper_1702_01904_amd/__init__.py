@@ -12,7 +12,7 @@ import numpy as np
 from . import _native
 from ._native import PrismError, PrismOptics, PrismDetector, PrismGeometry  # noqa: F401
 
-__all__ = ["Plan", "PrismError", "build_batch_workspace_bytes", "build_smatrix_batch",
+__all__ = ["Plan", "PrismError", "Server", "build_batch_workspace_bytes", "build_smatrix_batch",
            "tile_order", "untile"]
 
 
@@ -300,6 +300,102 @@ def build_smatrix_batch(items, workspace, stream=None):
     arr = _batch_items(items, True)
     _native.check(_native.lib().prism_build_smatrix_batch(arr, len(items), _ptr(workspace),
                                                           workspace.numel(), _stream_ptr(stream)))
+
+
+class Server:
+    """Resident S-matrices and merged probe queries (prism_server_*).
+
+    Device buffers handed to admit/submit are kept referenced here until
+    their queries are reported done (poll / wait) or the specimen evicted.
+    """
+
+    @staticmethod
+    def workspace_bytes(n_streams, max_probes, max_det, probe_ws_bytes):
+        b = ctypes.c_size_t()
+        _native.check(_native.lib().prism_server_workspace_bytes(
+            int(n_streams), int(max_probes), int(max_det), int(probe_ws_bytes), ctypes.byref(b)))
+        return b.value
+
+    def __init__(self, budget_bytes, workspace, n_streams=4, max_probes=65536, max_det=16):
+        import torch
+        _check_dev(workspace, torch.uint8, None, "workspace")
+        self._L = _native.lib()
+        h = ctypes.c_void_p()
+        _native.check(self._L.prism_server_create(ctypes.byref(h), int(budget_bytes),
+                                                  int(n_streams), int(max_probes), int(max_det),
+                                                  _ptr(workspace), workspace.numel()))
+        self._h = h
+        self._ws = workspace
+        self._spec = {}
+        self._live = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.prism_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def admit(self, plan, f, alpha_max_mrad, smatrix, build_workspace=None):
+        """Admit (and with build_workspace, build) one specimen's S-matrix; returns its id."""
+        import torch
+        B = plan.beam_count(f, alpha_max_mrad)
+        _check_dev(smatrix, torch.complex64, B * (plan.n // 2) ** 2, "smatrix")
+        i = ctypes.c_int()
+        wp, wn = (None, 0)
+        if build_workspace is not None:
+            _check_dev(build_workspace, torch.uint8, None, "build_workspace")
+            wp, wn = _ptr(build_workspace), build_workspace.numel()
+        _native.check(self._L.prism_server_admit(self._h, plan._h, int(f), float(alpha_max_mrad),
+                                                 _ptr(smatrix), wp, wn, ctypes.byref(i)))
+        self._spec[i.value] = (plan, smatrix, build_workspace)
+        return i.value
+
+    def evict(self, sid):
+        _native.check(self._L.prism_server_evict(self._h, int(sid)))
+        self._spec.pop(sid, None)
+
+    def submit(self, sid, probe_xy, optics, edges_mrad, out):
+        """Queue one query; returns its ticket (runs at the next flush)."""
+        import torch
+        det = _Det(edges_mrad)
+        P = probe_xy.shape[0]
+        _check_dev(probe_xy, torch.float64, 2 * P, "probe_xy")
+        _check_dev(out, torch.float64, P * det.edges.shape[0], "out")
+        o = _optics(optics)
+        t = ctypes.c_longlong()
+        _native.check(self._L.prism_server_submit(self._h, int(sid), _ptr(probe_xy), int(P),
+                                                  ctypes.byref(o), ctypes.byref(det.struct),
+                                                  _ptr(out), ctypes.byref(t)))
+        self._live[t.value] = (probe_xy, out)
+        return t.value
+
+    def flush(self):
+        _native.check(self._L.prism_server_flush(self._h))
+
+    def poll(self, capacity=4096):
+        """Tickets of queries that finished since the last poll / wait."""
+        buf = (ctypes.c_longlong * int(capacity))()
+        n = ctypes.c_int()
+        _native.check(self._L.prism_server_poll(self._h, buf, int(capacity), ctypes.byref(n)))
+        done = [buf[k] for k in range(n.value)]
+        for t in done:
+            self._live.pop(t, None)
+        return done
+
+    def wait(self, ticket):
+        _native.check(self._L.prism_server_wait(self._h, int(ticket)))
+        self._live.pop(ticket, None)
+
+    def stats(self):
+        b, q, f = ctypes.c_size_t(), ctypes.c_int(), ctypes.c_int()
+        _native.check(self._L.prism_server_stats(self._h, ctypes.byref(b), ctypes.byref(q),
+                                                 ctypes.byref(f)))
+        return b.value, q.value, f.value
 
 
 def tile_order(nx, ny, tx, ty):

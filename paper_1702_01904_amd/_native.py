@@ -27,7 +27,10 @@ EXPORTS = (
     "prism_probe_outputs", "prism_probe_cbed", "prism_multislice_outputs",
     "prism_probe_outputs_accumulate", "prism_probe_cbed_accumulate",
     "prism_multislice_outputs_accumulate", "prism_build_batch_workspace_bytes",
-    "prism_build_smatrix_batch", "prism_profile_enable", "prism_profile_report",
+    "prism_build_smatrix_batch", "prism_server_workspace_bytes", "prism_server_create",
+    "prism_server_destroy", "prism_server_admit", "prism_server_evict", "prism_server_submit",
+    "prism_server_flush", "prism_server_poll", "prism_server_wait", "prism_server_stats",
+    "prism_profile_enable", "prism_profile_report",
     "prism_last_error",
 )
 
@@ -109,6 +112,19 @@ def lib():
         "prism_build_batch_workspace_bytes": (I, [ctypes.POINTER(PrismBuildItem), I, SZ, SZ]),
         "prism_build_smatrix_batch": (I, [ctypes.POINTER(PrismBuildItem), I, P, ctypes.c_size_t,
                                           P]),
+        "prism_server_workspace_bytes": (I, [I, I, I, ctypes.c_size_t, SZ]),
+        "prism_server_create": (I, [ctypes.POINTER(P), ctypes.c_size_t, I, I, I, P,
+                                    ctypes.c_size_t]),
+        "prism_server_destroy": (None, [P]),
+        "prism_server_admit": (I, [P, P, I, D, P, P, ctypes.c_size_t, ctypes.POINTER(I)]),
+        "prism_server_evict": (I, [P, I]),
+        "prism_server_submit": (I, [P, I, P, I, ctypes.POINTER(PrismOptics),
+                                    ctypes.POINTER(PrismDetector), P,
+                                    ctypes.POINTER(ctypes.c_longlong)]),
+        "prism_server_flush": (I, [P]),
+        "prism_server_poll": (I, [P, ctypes.POINTER(ctypes.c_longlong), I, ctypes.POINTER(I)]),
+        "prism_server_wait": (I, [P, ctypes.c_longlong]),
+        "prism_server_stats": (I, [P, SZ, ctypes.POINTER(I), ctypes.POINTER(I)]),
         "prism_profile_enable": (I, [P, I]),
         "prism_profile_report": (I, [P, ctypes.c_char_p, ctypes.c_size_t]),
         "prism_last_error": (ctypes.c_char_p, []),

@@ -20,6 +20,7 @@
 #include <tuple>
 #include <vector>
 
+#include "host_util.hpp"
 #include "kernels.hpp"
 
 namespace {
@@ -30,6 +31,12 @@ int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
 }
+
+}  // namespace
+
+int prism::set_error(int code, const std::string& msg) { return fail(code, msg); }
+
+namespace {
 
 int hip_fail(hipError_t e, const char* where) {
   return fail(PRISM_EHIP, std::string(where) + ": " + hipGetErrorString(e));

@@ -319,3 +319,32 @@ def test_batch_build_validation():
     # workspace below the minimum of the first group
     r = L.prism_build_smatrix_batch(arr, 3, dummy, mn // 2, None)
     assert r == _native.PRISM_ENOSPACE
+
+
+def test_server_sizes_and_checks_before_any_stream():
+    from paper_1702_01904_amd import Server
+    L = _native.lib()
+    b = Server.workspace_bytes(4, 1000, 16, 1 << 20)
+    # four regions of staged positions (16 B each), outputs (128 B each) and
+    # the probe-step workspace, 256-byte aligned
+    assert b >= 4 * (1000 * 16 + 1000 * 128 + (1 << 20))
+    assert Server.workspace_bytes(1, 1000, 16, 0) < b
+    out = ctypes.c_size_t()
+    assert L.prism_server_workspace_bytes(0, 10, 1, 0, ctypes.byref(out)) == _native.PRISM_EINVAL
+    assert L.prism_server_workspace_bytes(17, 10, 1, 0, ctypes.byref(out)) == _native.PRISM_EINVAL
+    assert L.prism_server_workspace_bytes(1, 0, 1, 0, ctypes.byref(out)) == _native.PRISM_EINVAL
+    assert L.prism_server_workspace_bytes(1, 10, 33, 0, ctypes.byref(out)) == _native.PRISM_EINVAL
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(0x1000)
+    assert L.prism_server_create(None, 1 << 30, 2, 10, 1, dummy, 1 << 20) == _native.PRISM_EINVAL
+    assert L.prism_server_create(ctypes.byref(h), 1 << 30, 2, 10, 1, None,
+                                 1 << 20) == _native.PRISM_EINVAL
+    r = L.prism_server_create(ctypes.byref(h), 1 << 30, 2, 1000, 16, dummy, 1024)
+    assert r == _native.PRISM_ENOSPACE and not h.value
+    # calls on a null server fail cleanly
+    assert L.prism_server_flush(None) == _native.PRISM_EINVAL
+    assert L.prism_server_wait(None, 1) == _native.PRISM_EINVAL
+    n = ctypes.c_int()
+    assert L.prism_server_poll(None, None, 0, ctypes.byref(n)) == _native.PRISM_EINVAL
+    assert L.prism_server_stats(None, None, None, None) == _native.PRISM_EINVAL
+    L.prism_server_destroy(None)
