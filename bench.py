@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--serve-rates", default="50,150,250",
                     help="query arrival rates (per s) of the serving run ('' none)")
     ap.add_argument("--serve-queries", type=int, default=200)
+    ap.add_argument("--np2048", type=int, default=1,
+                    help="time the precision forms on the np2048 nanoparticle case (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--calibration-copy", action="store_true",
@@ -172,6 +174,67 @@ def cpu_baseline(d, f, amax, P_full):
                    f"scaled to the full build + scan"),
         "multislice_probes_per_s": round(1.0 / t_ms, 4),
     }
+
+
+def run_precision_np2048(args, dev):
+    """Window-sum precision forms on the 2048^2 nanoparticle-on-carbon case
+    (1024 sub-pixel probes, f = 4 and 8): probe-step time per precision and
+    eps_rel of the 16-bit outputs against the FP32 outputs of the same S
+    (their FP64-oracle parity is a GPU test)."""
+    import torch
+    from synth import build_inputs
+    from paper_1702_01904_amd import Plan
+    d = build_inputs("np2048", args.seed)
+    p = Plan(d["n"], d["cell"], d["energy_keV"], d["thickness"])
+    ph = torch.from_numpy(d["phase"]).to(dev)
+    p.set_potential_slices(ph)
+    xy = torch.from_numpy(d["probes"]).to(dev)
+    P, nd = len(d["probes"]), len(d["edges"])
+    res = {}
+    for f in (4, 8):
+        amax = p.alpha_max_default(d["optics"]["alpha_mrad"], f)
+        B = p.beam_count(f, amax)
+        S = torch.empty((B, d["n"] // 2, d["n"] // 2), dtype=torch.complex64, device=dev)
+        wsb = torch.empty(p.build_workspace_bytes(f, amax)[0], dtype=torch.uint8, device=dev)
+        p.build_smatrix(f, amax, S, wsb)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        p.build_smatrix(f, amax, S, wsb)
+        e1.record()
+        torch.cuda.synchronize()
+        ent = {"beams": B, "window": d["n"] // (2 * f), "build_ms": round(e0.elapsed_time(e1), 3)}
+        del wsb
+        outs = {}
+        for prec in ("fp32", "bf16", "fp16"):
+            p.set_probe_precision(prec)
+            wsp = torch.empty(p.probe_workspace_bytes(f, amax, d["optics"])[0],
+                              dtype=torch.uint8, device=dev)
+            out = torch.empty((P, nd), dtype=torch.float64, device=dev)
+            p.probe_outputs(f, amax, S, xy, d["optics"], d["edges"], out, wsp)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                p.probe_outputs(f, amax, S, xy, d["optics"], d["edges"], out, wsp)
+            e1.record()
+            torch.cuda.synchronize()
+            outs[prec] = out.cpu().numpy()
+            ent[f"{prec}_probe_ms"] = round(e0.elapsed_time(e1) / args.steps, 3)
+            del wsp
+        p.set_probe_precision("fp32")
+        for prec in ("bf16", "fp16"):
+            ref = outs["fp32"]
+            ent[f"eps_rel_{prec}_vs_fp32"] = float(np.linalg.norm(outs[prec] - ref)
+                                                   / np.linalg.norm(ref))
+        res[str(f)] = ent
+        log(f"np2048 f={f}: build {ent['build_ms']} ms, probe step fp32/bf16/fp16 "
+            f"{ent['fp32_probe_ms']}/{ent['bf16_probe_ms']}/{ent['fp16_probe_ms']} ms")
+        del S
+    del ph
+    torch.cuda.synchronize()
+    return {"workload": "np2048: Au r=20 A particle on 30 A carbon, 2048^2, 35 slices, 80 keV, "
+                        "20 mrad, 1024 sub-pixel probes, one bin [40,150) mrad",
+            "per_f": res, "tolerance": "eps_rel <= 1e-2 vs FP64 oracle (tests/test_parity_gpu.py)"}
 
 
 def run_batch(args, dev):
@@ -528,6 +591,7 @@ def main():
                          "beams": c["B"], "active_beams": c["BA"]}
         del c
 
+    prec2048 = run_precision_np2048(args, dev) if args.np2048 else None
     batch = run_batch(args, dev) if args.batch else None
 
     serving = run_serving(args, plan, d, dev) if args.serve_rates else None
@@ -582,6 +646,7 @@ def main():
         "per_f": per_f,
         "precision_variants": variants,
         "probe_side": probe_side,
+        "precision_np2048": prec2048,
         "batch": batch,
         "serving": serving,
         "kernel_ms_per_step": kernels,
