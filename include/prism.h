@@ -119,6 +119,18 @@ int prism_probe_workspace_bytes(const prism_plan* plan, int f, double alpha_max_
  * scattered tiles cost more but still give the same results. */
 int prism_probe_group(const prism_plan* plan, int f, int* group, int* tile_x, int* tile_y);
 
+/* A processing order for scattered probe positions: perm (host int32 [P])
+ * such that probe_xy[perm[0]], probe_xy[perm[1]], ... visits the probes in
+ * spatially compact runs, so that consecutive probes share union windows.
+ * Probes are sorted by the Morton index of their window centre pixel (the
+ * centre of Eq. RegionBounds) on cells of min(16, W/8) S-matrix pixels, ties
+ * in input order; a raster at two S-pixels per step comes out in 8 x 8
+ * tiles. probe_xy_host: float64 [P][2] (Angstrom), read during the call.
+ * Results of the probe step do not depend on the order, only its time.
+ * Errors: PRISM_EINVAL (null pointers, P < 0, invalid f). */
+int prism_probe_order(const prism_plan* plan, int f, const double* probe_xy_host, int n_probes,
+                      int32_t* perm);
+
 /* Select the operand precision of prism_probe_outputs for this plan
  * (PRISM_PREC_*; PRISM_EINVAL otherwise). With BF16/FP16 each call first
  * packs the active beams of the S-matrix into a pixel-major 16-bit copy in

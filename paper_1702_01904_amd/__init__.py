@@ -140,6 +140,15 @@ class Plan:
         return g.value, tx.value, ty.value
 
     # ------------------------------------------------------------ kernel timing
+    def probe_order(self, f, probes):
+        """Permutation (int64) visiting host probe positions [P][2] in compact runs."""
+        xy = np.ascontiguousarray(np.asarray(probes, dtype=np.float64).reshape(-1, 2))
+        perm = np.empty(xy.shape[0], dtype=np.int32)
+        _native.check(self._L.prism_probe_order(
+            self._h, int(f), xy.ctypes.data_as(ctypes.c_void_p), int(xy.shape[0]),
+            perm.ctypes.data_as(ctypes.c_void_p)))
+        return perm.astype(np.int64)
+
     def profile(self, enable=True):
         """Bracket every kernel launch of this plan with HIP events on its stream."""
         _native.check(self._L.prism_profile_enable(self._h, 1 if enable else 0))

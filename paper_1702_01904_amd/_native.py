@@ -23,6 +23,7 @@ EXPORTS = (
     "prism_plan_create", "prism_plan_destroy", "prism_wavelength", "prism_beam_count",
     "prism_beams", "prism_smatrix_bytes", "prism_build_workspace_bytes",
     "prism_multislice_workspace_bytes", "prism_probe_workspace_bytes", "prism_probe_group",
+    "prism_probe_order",
     "prism_set_probe_precision", "prism_set_potential_slices", "prism_build_smatrix",
     "prism_probe_outputs", "prism_probe_cbed", "prism_multislice_outputs",
     "prism_probe_outputs_accumulate", "prism_probe_cbed_accumulate",
@@ -92,6 +93,7 @@ def lib():
         "prism_multislice_workspace_bytes": (I, [P, I, SZ, SZ]),
         "prism_probe_workspace_bytes": (I, [P, I, D, ctypes.POINTER(PrismOptics), SZ, SZ]),
         "prism_probe_group": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "prism_probe_order": (I, [P, I, P, I, P]),
         "prism_set_probe_precision": (I, [P, I]),
         "prism_set_potential_slices": (I, [P, P]),
         "prism_build_smatrix": (I, [P, I, D, P, P, ctypes.c_size_t, P]),

@@ -739,6 +739,31 @@ int prism_probe_group(const prism_plan* p, int f, int* group, int* tx, int* ty) 
   return PRISM_OK;
 }
 
+int prism_probe_order(const prism_plan* p, int f, const double* xy, int P, int32_t* perm) {
+  if (!p || (P > 0 && (!xy || !perm))) return fail(PRISM_EINVAL, "null argument");
+  if (P < 0) return fail(PRISM_EINVAL, "negative probe count");
+  if (int r = check_f(p, f)) return r;
+  const int ns = p->n / 2, w = ns / f;
+  const int cell = std::max(1, std::min(16, w / 8));
+  const double dxs = p->cell / ns;
+  std::vector<std::pair<uint64_t, int32_t>> key((size_t)P);
+  for (int i = 0; i < P; ++i) {
+    // window centre pixel of Eq. RegionBounds, as the coefficient kernel takes it
+    long long cx = (long long)std::floor(xy[2 * i] / dxs + 0.5) % ns;
+    long long cy = (long long)std::floor(xy[2 * i + 1] / dxs + 0.5) % ns;
+    if (cx < 0) cx += ns;
+    if (cy < 0) cy += ns;
+    const uint32_t gx = (uint32_t)(cx / cell), gy = (uint32_t)(cy / cell);
+    uint64_t m = 0;
+    for (int b = 0; b < 16; ++b)
+      m |= (uint64_t)((gx >> b) & 1u) << (2 * b) | (uint64_t)((gy >> b) & 1u) << (2 * b + 1);
+    key[(size_t)i] = {m, i};
+  }
+  std::sort(key.begin(), key.end());  // ties keep the input order (second member)
+  for (int i = 0; i < P; ++i) perm[i] = key[(size_t)i].second;
+  return PRISM_OK;
+}
+
 int prism_probe_workspace_bytes(const prism_plan* cp, int f, double amax_mrad,
                                 const prism_optics* o, size_t* pref, size_t* minimum) {
   if (!pref || !minimum) return fail(PRISM_EINVAL, "null argument");

@@ -379,8 +379,11 @@ __global__ __launch_bounds__(kNT16) __attribute__((amdgpu_waves_per_eu(2))) void
       offy[tid] = ry - miny;
     }
     if (tid == 0) {
-      const int smax = w / 2;
-      ginfo[0] = (maxx - minx <= smax && maxy - miny <= smax) ? 0 : 1;
+      // one pass over the union of the windows costs (w + sx)(w + sy)
+      // pixels, one pass per probe costs gcount w^2: take the cheaper (each
+      // output pixel gets the same sum either way)
+      const long long uni = (long long)(w + maxx - minx) * (w + maxy - miny);
+      ginfo[0] = uni <= (long long)gcount * w * w ? 0 : 1;
       ginfo[1] = wrap_mod16((long long)o0.y + miny, ns);
       ginfo[2] = wrap_mod16((long long)o0.x + minx, ns);
       ginfo[3] = w + (maxy - miny);

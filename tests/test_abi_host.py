@@ -348,3 +348,33 @@ def test_server_sizes_and_checks_before_any_stream():
     assert L.prism_server_poll(None, None, 0, ctypes.byref(n)) == _native.PRISM_EINVAL
     assert L.prism_server_stats(None, None, None, None) == _native.PRISM_EINVAL
     L.prism_server_destroy(None)
+
+
+def test_probe_order():
+    from synth import build_inputs
+    d = build_inputs("fcc1024", 0, n_slices=1)
+    p = Plan(d["n"], d["cell"], d["energy_keV"], d["thickness"])
+    ns = d["n"] // 2
+    for f, (tx, ty) in ((4, (8, 8)), (8, (8, 4)), (16, (4, 4))):
+        perm = p.probe_order(f, d["probes"])
+        assert sorted(perm.tolist()) == list(range(len(d["probes"])))
+        # the 256 x 256 raster at two S-pixels comes out as the probe tiles
+        G = tx * ty
+        t = tile_order(256, 256, tx, ty)
+        chunks = lambda q: sorted(tuple(sorted(q[i:i + G])) for i in range(0, len(q), G))
+        assert chunks(perm) == chunks(t)
+    # scattered positions: runs of 64 consecutive probes get tighter
+    rng = np.random.default_rng(3)
+    xy = rng.uniform(0.0, d["cell"], (4096, 2))
+    perm = p.probe_order(4, xy)
+    dxs = d["cell"] / ns
+
+    def spread(q):
+        c = np.floor(q / dxs + 0.5)
+        return np.mean([np.ptp(c[i:i + 64], axis=0).max() for i in range(0, len(c), 64)])
+    assert spread(xy[perm]) < 0.35 * spread(xy)
+    assert len(p.probe_order(4, np.zeros((0, 2)))) == 0
+    L = _native.lib()
+    assert L.prism_probe_order(p._h, 3, None, 0, None) == _native.PRISM_EINVAL   # 1024 % 6
+    assert L.prism_probe_order(p._h, 4, None, 5, None) == _native.PRISM_EINVAL
+    assert L.prism_probe_order(p._h, 4, None, -1, None) == _native.PRISM_EINVAL

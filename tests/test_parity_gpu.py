@@ -486,6 +486,12 @@ def test_np2048_prism_all_precisions(np2048, f):
         e = eps(D[p], D32)
         print(f"np2048 f={f} {p} vs fp32 over {len(D32)} probes eps_rel={e:.3e}")
         assert e <= TOL16
+    # the same probes in the library's compact order: the same outputs, bit
+    # for bit (only the grouping into union windows changes)
+    perm = plan.probe_order(f, d["probes"])
+    D32o = untile(G.probe_outputs(plan, f, amax, S, d["probes"][perm], d["optics"], d["edges"]),
+                  perm)
+    assert np.array_equal(D32o, D32)
     for i in (0, 517):
         x0, y0 = d["probes"][i]
         ref = O.prism_probe_direct(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax,
