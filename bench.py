@@ -207,7 +207,15 @@ def run_precision_np2048(args, dev):
         p.build_smatrix(f, amax, S, wsb)
         e1.record()
         torch.cuda.synchronize()
-        ent = {"beams": B, "window": d["n"] // (2 * f), "build_ms": round(e0.elapsed_time(e1), 3)}
+        n = d["n"]
+        bms = e0.elapsed_time(e1)
+        gbs = B * len(d["thickness"]) * 16.0 * n * n / (bms * 1e-3) / 1e9
+        ent = {"beams": B, "window": n // (2 * f), "build_ms": round(bms, 3),
+               "build_hbm_GBps": round(gbs, 1), "build_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        lam = p.wavelength
+        ba = int(np.sum(lam * np.hypot(*(p.beams(f, amax) * f).T) / d["cell"]
+                        <= d["optics"]["alpha_mrad"] * 1e-3))
+        flops = 8.0 * ba * (n // (2 * f)) ** 2 * P     # useful window-sum flops per probe step
         del wsb
         outs = {}
         for prec in ("fp32", "bf16", "fp16"):
@@ -232,6 +240,12 @@ def run_precision_np2048(args, dev):
                 ent["fp32_probe_ms_input_order"] = round(e0.elapsed_time(e1), 3)
             del wsp
         p.set_probe_precision("fp32")
+        ent["active_beams"] = ba
+        for prec, peak in (("fp32", FP32_MFMA_PEAK_TFLOPS), ("bf16", F16_MFMA_PEAK_TFLOPS),
+                           ("fp16", F16_MFMA_PEAK_TFLOPS)):
+            tf = flops / (ent[f"{prec}_probe_ms"] * 1e-3) / 1e12
+            ent[f"{prec}_window_sum_TFLOPs_whole_step"] = round(tf, 2)
+            ent[f"{prec}_mfma_frac_whole_step"] = round(tf / peak, 4)
         for prec in ("bf16", "fp16"):
             ref = outs["fp32"]
             ent[f"eps_rel_{prec}_vs_fp32"] = float(np.linalg.norm(outs[prec] - ref)
@@ -300,9 +314,12 @@ def run_batch(args, dev):
         its = [(e["plan"], e["f"], e["amax"], e["S"]) for e in sub]
         mb = ev_ms(lambda: build_smatrix_batch(its, wsb))
         m1 = ev_ms(lambda: [e["plan"].build_smatrix(e["f"], e["amax"], e["S"], ws1) for e in sub])
-        per_n[str(n)] = {"specimens": len(sub),
-                         "beam_slices": sum(e["B"] * len(e["d"]["thickness"]) for e in sub),
-                         "build_batched_ms": round(mb, 3), "build_per_specimen_ms": round(m1, 3)}
+        bs_n = sum(e["B"] * len(e["d"]["thickness"]) for e in sub)
+        gbs = bs_n * 16.0 * n * n / (mb * 1e-3) / 1e9   # two passes, 4 n^2 B each way
+        per_n[str(n)] = {"specimens": len(sub), "beam_slices": bs_n,
+                         "build_batched_ms": round(mb, 3), "build_per_specimen_ms": round(m1, 3),
+                         "build_hbm_GBps": round(gbs, 1),
+                         "build_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     finite = all(bool(torch.isfinite(e["out"]).all()) for e in ents)
     bsl = sum(e["B"] * len(e["d"]["thickness"]) for e in ents)
     P = sum(len(e["d"]["probes"]) for e in ents)
