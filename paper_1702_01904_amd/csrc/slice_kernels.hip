@@ -34,7 +34,7 @@ constexpr int kRowNT = PRISM_ROW_ELEMS / 8;
 __host__ __device__ constexpr int row_nseq(int n) {
   return PRISM_ROW_ELEMS / n > 0 ? PRISM_ROW_ELEMS / n : 1;
 }
-__host__ __device__ constexpr int col_tc(int n) { return n >= 2048 ? 4 : 8; }
+__host__ __device__ constexpr int col_tc(int n) { return 8; }
 __host__ __device__ constexpr int col_nt(int n) {
   return (col_tc(n) * n / PRISM_COL_E) < 64
              ? 64

@@ -504,6 +504,18 @@ def test_np2048_prism_all_precisions(np2048, f):
             assert eps(D[p][i], ref) <= TOL16
 
 
+def test_np2048_multislice_sampled(np2048):
+    # the n = 2048 column pass with detector partials (8-column tiles)
+    d, plan = np2048
+    pr = d["probes"][[5, 700]]
+    D = G.multislice_outputs(plan, pr, d["optics"], d["edges"])
+    ref = O.multislice_stem(d["phase"], d["thickness"], d["cell"], d["energy_keV"], d["optics"],
+                            pr, d["edges"])
+    e = eps(D, ref)
+    print(f"np2048 multislice eps_rel={e:.3e}")
+    assert e <= TOL
+
+
 def test_np2048_cbed_w256(np2048):
     # W = 256 diffraction patterns: one probe against the oracle's direct route
     d, plan = np2048
