@@ -547,3 +547,46 @@ def test_fcc1024_empty_cell_prism_closed_form():
         edges = np.asarray(d["edges"]) * 1e-3
         frac = [np.sum(act & (th >= lo) & (th < hi)) / act.sum() for lo, hi in edges]
         assert eps(Dp, np.broadcast_to(frac, Dp.shape)) <= TOL
+
+
+def test_max_bins_and_probes_outside_the_cell():
+    # 32 detector bins (the limit; eight per pass in the window kernels) and
+    # probe positions outside [0, d) (the window centre wraps, the phase
+    # e^{-2 pi i q.r0} does not care): PRISM f = 1, 2 (W = 64, 32) and
+    # multislice on the tiny case, W = 256 on s512 against multislice (PRISM
+    # at f = 1 is multislice)
+    d = build_inputs("tiny", 2)
+    plan = G.make_plan(d)
+    edges = np.array([(4.0 * j, 4.0 * (j + 1)) for j in range(31)] + [(124.0, 200.0)])
+    pr = np.array([[-3.3, 1.6], [12.9, -0.4], [25.7, 30.1], [-12.8, -12.8], [6.4, 6.4]])
+    Dm = G.multislice_outputs(plan, pr, d["optics"], edges)
+    ref_m = O.multislice_stem(d["phase"], d["thickness"], d["cell"], d["energy_keV"], d["optics"],
+                              pr, edges)
+    e = eps(Dm, ref_m)
+    print(f"32 bins, outside probes: multislice eps_rel={e:.3e}")
+    assert e <= TOL
+    for f in (1, 2):
+        amax = _amax(d, f)
+        S = G.build_smatrix(plan, f, amax)
+        D = G.probe_outputs(plan, f, amax, S, pr, d["optics"], edges)
+        beams, Sref = O.smatrix(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax)
+        ref = O.prism_outputs(Sref, beams, f, d["cell"], d["energy_keV"], d["optics"], pr, edges)
+        e = eps(D, ref)
+        print(f"32 bins, outside probes: prism f={f} eps_rel={e:.3e}")
+        assert e <= TOL
+        # a probe moved by whole cells gives the same outputs
+        Dw = G.probe_outputs(plan, f, amax, S, pr[-1:] + [[d["cell"], -2 * d["cell"]]],
+                             d["optics"], edges)
+        assert np.abs(Dw - D[-1:]).max() <= 1e-5 * np.abs(D[-1:]).max()
+    d5 = build_inputs("s512", 2)
+    plan5 = G.make_plan(d5)
+    f = 1
+    amax = _amax(d5, f)
+    S = G.build_smatrix(plan5, f, amax)
+    pr5 = np.array([[-7.7, 3.1], [60.0, 55.5]])
+    D = G.probe_outputs(plan5, f, amax, S, pr5, d5["optics"], edges)
+    ref = O.multislice_stem(d5["phase"], d5["thickness"], d5["cell"], d5["energy_keV"],
+                            d5["optics"], pr5, edges)
+    e = eps(D, ref)
+    print(f"32 bins, outside probes: s512 prism f=1 (W=256) eps_rel={e:.3e}")
+    assert e <= TOL
