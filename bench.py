@@ -38,10 +38,10 @@ CONFIG = "fcc1024"
 # workload (f = 4), calibrated with a 256 MiB device copy (fetch x2.0,
 # write x1.0); see profiles/fcc1024_prism_f4_hbm_traffic.md. Valid only for
 # the kernel sources with this hash; reported as null otherwise.
-TRAFFIC_SRC_SHA = "10d09c1e0920a6d7"
-TRAFFIC_BYTES = {"row_pass": 531739089, "col_pass": 522040871, "contract": 1381204883,
-                 "s32_pack": 1310726692, "window_detect": 270024625, "contract16": 815436130,
-                 "s16_pack": 975178149}
+TRAFFIC_SRC_SHA = "3c49cc76af770e9d"
+TRAFFIC_BYTES = {"row_pass": 531718600, "col_pass": 522040827, "contract": 1382004766,
+                 "s32_pack": 1310725186, "window_detect": 270024313, "contract16": 815579685,
+                 "s16_pack": 975179458}
 
 
 def kernel_source_sha():
