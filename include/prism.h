@@ -292,7 +292,9 @@ int prism_server_admit(prism_server* server, prism_plan* plan, int f, double alp
 int prism_server_evict(prism_server* server, int id);
 /* Queue one query: n_probes in [0, max_probes] positions (device float64
  * [P][2], A), optics and detector as in prism_probe_outputs (copied), out_dev
- * float64 [P][n_det]. Returns a ticket. Nothing runs before the next flush. */
+ * float64 [P][n_det]. Returns a ticket. Nothing runs before the next flush.
+ * Every check of the probe step (optics, alpha_max, detector edges, window
+ * size, workspace region) runs here, so a queued query cannot fail a flush. */
 int prism_server_submit(prism_server* server, int id, const double* probe_xy_dev, int n_probes,
                         const prism_optics* optics, const prism_detector* detector,
                         double* out_dev, long long* ticket);

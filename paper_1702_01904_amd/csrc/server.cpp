@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <string>
@@ -310,8 +311,16 @@ int prism_server_submit(prism_server* s, int id, const double* probe_xy_dev, int
     return set_error(PRISM_EINVAL, "probe count must be 0..max_probes");
   if (detector->n_det < 1 || detector->n_det > s->max_det || !detector->edges_mrad)
     return set_error(PRISM_EINVAL, "detector bins must be 1..max_det");
+  // the probe step's bin checks, here so that a bad query never reaches a flush
+  for (int j = 0; j < detector->n_det; ++j) {
+    const double lo = detector->edges_mrad[2 * j], hi = detector->edges_mrad[2 * j + 1];
+    if (!std::isfinite(lo) || !std::isfinite(hi) || lo < 0.0 || hi < lo)
+      return set_error(PRISM_EINVAL, "detector edges must satisfy 0 <= inner <= outer");
+  }
   if (n_probes > 0 && (!probe_xy_dev || !out_dev)) return set_error(PRISM_EINVAL, "null device buffer");
   const Specimen& sp = s->specs[id];
+  if (optics->alpha_mrad + std::hypot(optics->tilt_x_mrad, optics->tilt_y_mrad) > sp.amax)
+    return set_error(PRISM_EINVAL, "probe semi-angle plus tilt exceeds the beam set's alpha_max");
   // the probe step's own checks, and its workspace minimum against a region
   size_t pref, minimum;
   if (int r = prism_probe_workspace_bytes(sp.plan, sp.f, sp.amax, optics, &pref, &minimum)) return r;

@@ -69,6 +69,15 @@ def test_server_merged_queries_equal_alone_and_oracle(served):
         xy = G.upload(d["probes"][sel])
         out = torch.full((P, len(edges)), float("nan"), dtype=torch.float64, device=G.device())
         queries.append(dict(e=e, xy=xy, out=out, optics=optics, edges=edges, sel=sel))
+    # a query the probe step would reject is refused at submit, not queued
+    bad = torch.empty((3, 1), dtype=torch.float64, device=G.device())
+    with pytest.raises(PrismError):
+        srv.submit(ents[0]["id"], G.upload(ents[0]["d"]["probes"][:3]), ents[0]["d"]["optics"],
+                   [(50.0, 40.0)], bad)
+    with pytest.raises(PrismError):
+        srv.submit(ents[0]["id"], G.upload(ents[0]["d"]["probes"][:3]),
+                   dict(alpha_mrad=40.0, C1_A=0.0, C3_A=0.0), ents[0]["d"]["edges"], bad)
+    assert srv.stats()[1] == 0
     G.say(f"server submit {len(queries)} queries, flush, wait")
     for q in queries:
         q["t"] = srv.submit(q["e"]["id"], q["xy"], q["optics"], q["edges"], q["out"])
