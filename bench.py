@@ -38,17 +38,23 @@ CONFIG = "fcc1024"
 # workload (f = 4), calibrated with a 256 MiB device copy (fetch x2.0,
 # write x1.0); see profiles/fcc1024_prism_f4_hbm_traffic.md. Valid only for
 # the kernel sources with this hash; reported as null otherwise.
-TRAFFIC_SRC_SHA = "3c49cc76af770e9d"
+TRAFFIC_SRC_SHA = "f2a37dac0f7a6a86"
 TRAFFIC_BYTES = {"row_pass": 531718600, "col_pass": 522040827, "contract": 1382004766,
                  "s32_pack": 1310725186, "window_detect": 270024313, "contract16": 815579685,
                  "s16_pack": 975179458}
 
 
+# Sources that decide the profiled kernels and their launch shapes (the
+# serving layer and the binding do not).
+KERNEL_SOURCES = ("slice_kernels.hip", "probe_kernels.hip", "probe16_kernels.hip", "fft_lds.hpp",
+                  "fft_reg.hpp", "kernels.hpp", "plan.cpp")
+
+
 def kernel_source_sha():
-    import glob
     import hashlib
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1702_01904_amd", "csrc", "*")))
-    return hashlib.sha256("".join(open(p).read() for p in files).encode()).hexdigest()[:16]
+    src = os.path.join(ROOT, "paper_1702_01904_amd", "csrc")
+    return hashlib.sha256("".join(open(os.path.join(src, f)).read()
+                                  for f in KERNEL_SOURCES).encode()).hexdigest()[:16]
 
 
 def parse():
