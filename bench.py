@@ -182,6 +182,37 @@ def cpu_baseline(d, f, amax, P_full):
     }
 
 
+def measured_peaks(dev):
+    """What this GPU reaches on plain work: a 1 GiB device copy (GB/s, bytes
+    read + written) and square FP32 / BF16 library GEMMs (TFLOP/s)."""
+    import torch
+
+    def ev(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    x = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    copy_gbs = 2.0 * x.numel() * 4 / (ev(lambda: y.copy_(x)) * 1e-3) / 1e9
+    del x, y
+    out = {"copy_GBps": round(copy_gbs, 1)}
+    n = 8192
+    for name, dt in (("gemm_fp32_TFLOPs", torch.float32), ("gemm_bf16_TFLOPs", torch.bfloat16)):
+        a = torch.randn(n, n, dtype=dt, device=dev)
+        b = torch.randn(n, n, dtype=dt, device=dev)
+        out[name] = round(2.0 * n ** 3 / (ev(lambda: torch.mm(a, b)) * 1e-3) / 1e12, 1)
+        del a, b
+    torch.cuda.synchronize()
+    return out
+
+
 def run_precision_np2048(args, dev):
     """Window-sum precision forms on the 2048^2 nanoparticle-on-carbon case
     (1024 sub-pixel probes, f = 4 and 8): probe-step time per precision and
@@ -520,22 +551,25 @@ def main():
         if profile:
             plan.profile(True)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         t0 = time.perf_counter()
-        e0.record()
-        for _ in range(steps):
+        evs[0].record()
+        for i in range(steps):
             step(c)
-        e1.record()
+            evs[i + 1].record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         prof = plan.profile_report() if profile else None
         plan.profile(False)
-        ms = e0.elapsed_time(e1) / steps
+        ms = evs[0].elapsed_time(evs[-1]) / steps
+        per = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
         log(f"f={c['f']} timed {steps} steps: {ms:.2f} ms/step (wall {wall:.2f} s)")
+        timed.median = float(np.median(per))
         return ms, prof
 
     main_c = setup_f(args.f)
     ms, prof = timed(main_c, args.steps, args.warmup, True)
+    ms_median = timed.median
     value = P / (ms * 1e-3)
     geo = dict(N=N, NS=N // 2, H=H, B=main_c["B"], BA=main_c["BA"], P=P, W=N // (2 * args.f),
                n_det=n_det)
@@ -565,6 +599,8 @@ def main():
 
         ms_res = ev_time(lambda: plan.probe_outputs(c["f"], c["amax"], c["S"], c["xy"], optics,
                                                     edges, c["out"], c["wsp"]), args.steps)
+        ms_build = ev_time(lambda: plan.build_smatrix(c["f"], c["amax"], c["S"], c["wsb"]),
+                           args.steps)
         log(f"resident-S probe step: {ms_res:.2f} ms")
         W = N // (2 * args.f)
         cb = torch.empty((P, W, W), dtype=torch.float32, device=dev)
@@ -593,6 +629,8 @@ def main():
         del phases, acc
         log(f"frozen phonons, {K} configurations: {ms_ph:.2f} ms")
         probe_side = {
+            "phases_ms": {"build": round(ms_build, 3), "probe_step": round(ms_res, 3),
+                          "end_to_end": round(ms, 3)},
             "resident_smatrix": {"ms": round(ms_res, 3), "probes_per_s": round(P / (ms_res * 1e-3), 1)},
             "cbed": {"ms": round(ms_cb, 3), "probes_per_s": round(P / (ms_cb * 1e-3), 1),
                      "window": W, "bytes_out": P * W * W * 4},
@@ -650,6 +688,16 @@ def main():
         multi_rate = len(sub) / (ms_multi * 1e-3)
         log(f"multislice: {len(sub)} probes in {ms_multi:.1f} ms -> {multi_rate:.1f} probes/s")
 
+    peaks = measured_peaks(dev)
+    log(f"measured peaks: {peaks}")
+    mp = peaks["copy_GBps"] if roof["unit"] == "GB/s" else peaks["gemm_fp32_TFLOPs"]
+    roof["measured_peak"] = mp
+    roof["frac_of_measured"] = round(roof["achieved"] / mp, 4)
+    for v in variants.values():   # 16-bit window sums against the BF16 library GEMM
+        rv = v["contract16_roofline"]
+        rv["measured_peak"] = peaks["gemm_bf16_TFLOPs"]
+        rv["frac_of_measured"] = round(rv["achieved"] / peaks["gemm_bf16_TFLOPs"], 4)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a bounded sample ...")
@@ -664,6 +712,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 3),
+        "ms_per_step_median": round(ms_median, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -685,6 +734,7 @@ def main():
         "serving": serving,
         "kernel_ms_per_step": kernels,
         "roofline": roof,
+        "measured_peaks": peaks,
         "cpu_baseline": cpu,
         "outputs_finite": finite,
     }
