@@ -346,6 +346,33 @@ def test_prism_mid_small_windows(mid, f):
     assert e <= TOL
     D16 = _outputs_at(plan, "bf16", f, amax, S, d["probes"], d["optics"], d["edges"])
     assert eps(D16, ref) <= TOL16
+    # full diffraction patterns at these windows
+    pr = d["probes"][::9]
+    C = G.probe_cbed(plan, f, amax, S, pr, d["optics"])
+    _, Cref = O.prism_outputs(Sref, beams, f, d["cell"], d["energy_keV"], d["optics"], pr,
+                              d["edges"], return_cbed=True)
+    e = eps(C, Cref)
+    print(f"cbed mid f={f} W={plan.n // (2 * f)} eps_rel={e:.3e}")
+    assert e <= TOL
+
+
+def test_tilted_probe_16bit(tiny):
+    # tilt in the 16-bit coefficient layout (aperture and chi centred on the
+    # tilt, entrance offset h tan(theta)), f = 1 and 2
+    d, plan = tiny
+    optics = dict(alpha_mrad=18.0, C1_A=-25.0, C3_A=1e4, tilt_x_mrad=-3.0, tilt_y_mrad=5.0)
+    h = float(np.sum(d["thickness"]))
+    for f in (1, 2):
+        amax = _amax(d, f, alpha_mrad=18.0 + np.hypot(3.0, 5.0))
+        S = G.build_smatrix(plan, f, amax)
+        beams, Sref = O.smatrix(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax)
+        ref = O.prism_outputs(Sref, beams, f, d["cell"], d["energy_keV"], optics, d["probes"],
+                              d["edges"], height=h)
+        for prec in ("bf16", "fp16"):
+            D = _outputs_at(plan, prec, f, amax, S, d["probes"], optics, d["edges"])
+            e = eps(D, ref)
+            print(f"tilt {prec} tiny f={f} eps_rel={e:.3e}")
+            assert e <= TOL16
 
 
 # ------------------------------------------------------------------ 512^2 (Stockham slice kernels)
