@@ -118,9 +118,11 @@ __host__ __device__ constexpr int prec_words(Prec p) { return p == Prec::kF32 ? 
 // Beam rows of the packed S-matrix are padded to a whole pair of K blocks.
 __host__ __device__ constexpr int prec_beam_pad(Prec p) { return 2 * prec_block_beams(p); }
 // scale[a] = 2^-e with e the smallest integer such that every |Re|, |Im| of
-// active beam a's plane is < 2^e (1 for an all-zero plane).
+// active beam a's plane is < 2^e (1 for an all-zero plane); partial holds
+// n_act * kScaleSplit floats of per-block maxima (ns >= 64).
+constexpr int kScaleSplit = 32;
 hipError_t launch_s16_scale(const float2* smatrix, const ActiveBeam* act, int n_act, int ns,
-                            float* scale, hipStream_t st);
+                            float* partial, float* scale, hipStream_t st);
 // s16 [ns*ns][n_actp][2] 16-bit: (Re, Im) of scale[a] * S_a(pixel); zero for a >= n_act.
 hipError_t launch_s16_pack(const float2* smatrix, const ActiveBeam* act, int n_act, int n_actp,
                            int ns, const float* scale, void* s16, Prec prec, hipStream_t st);

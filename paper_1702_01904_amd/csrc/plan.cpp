@@ -374,6 +374,7 @@ struct ProbeWs {
   prism::ActiveBeam* act;
   float2* alpha;    // FP32: [n_act][chunk]
   float* scale;     // 16-bit: [n_act] power-of-two beam scales
+  float* scale_part;  // 16-bit: [n_act][kScaleSplit] per-block maxima
   uint32_t* s16;    // packed S: [ns^2][n_actp] (re, im), one word (16-bit) or two (FP32)
   uint32_t* a16;    // packed alpha: [chunk / G][K blocks][2G][32 words]
   int2* origin;
@@ -407,13 +408,15 @@ size_t probe_layout(int w, int ns, int n_act, int chunk, int prec, ProbeWs* pw, 
   pw->act = c.take<prism::ActiveBeam>(n_act);
   if (!packed_path(prec)) {
     pw->alpha = c.take<float2>((size_t)chunk * n_act);
-    pw->scale = nullptr;
+    pw->scale = pw->scale_part = nullptr;
     pw->s16 = pw->a16 = nullptr;
   } else {
     const prism::Prec pk = packed_prec(prec);
     const int n_actp = padded_beams(n_act, pk);
     pw->alpha = nullptr;
     pw->scale = pk == prism::Prec::kF32 ? nullptr : c.take<float>(n_act);
+    pw->scale_part =
+        pk == prism::Prec::kF32 ? nullptr : c.take<float>((size_t)n_act * prism::kScaleSplit);
     pw->s16 = c.take<uint32_t>((size_t)ns * ns * n_actp * prism::prec_words(pk));
     // per probe: n_actp / KB blocks x 2 rows x 32 words
     pw->a16 = c.take<uint32_t>((size_t)chunk * (n_actp / prism::prec_block_beams(pk)) * 64);
@@ -562,7 +565,7 @@ int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, const doub
     const float out_scale = (float)po.norm;
     po.norm = 1.0;
     if (pr != prism::Prec::kF32)
-      LAUNCH(p, st, "s16_scale", prism::launch_s16_scale(Sd, pw.act, n_act, ns, pw.scale, st));
+      LAUNCH(p, st, "s16_scale", prism::launch_s16_scale(Sd, pw.act, n_act, ns, pw.scale_part, pw.scale, st));
     LAUNCH(p, st, pr == prism::Prec::kF32 ? "s32_pack" : "s16_pack",
            prism::launch_s16_pack(Sd, pw.act, n_act, n_actp, ns, pw.scale, pw.s16, pr, st));
     for (int p0 = 0; p0 < P; p0 += chunk) {

@@ -72,31 +72,43 @@ __device__ __forceinline__ floatx4 mfma16(u32x4 a, u32x4 b, floatx4 c) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_s16_scale(const float2* __restrict__ S,
-                                                   const ActiveBeam* __restrict__ act, int ns,
-                                                   float* __restrict__ scale) {
-  const int a = blockIdx.x, tid = threadIdx.x;
-  const float2* pl = S + (size_t)act[a].plane * ns * ns;
+// Largest |Re|, |Im| of each active plane: kScaleSplit blocks per plane
+// (enough blocks to fill the GPU even for a few beams), then one thread per
+// beam folds the partial maxima into the power-of-two scale.
+__global__ __launch_bounds__(256) void k_s16_absmax(const float2* __restrict__ S,
+                                                    const ActiveBeam* __restrict__ act, int ns,
+                                                    float* __restrict__ partial) {
+  const int a = blockIdx.x, part = blockIdx.y, tid = threadIdx.x;
+  const size_t per = (size_t)ns * ns / kScaleSplit;  // complex values per block (even)
+  const float4* pl = reinterpret_cast<const float4*>(S + (size_t)act[a].plane * ns * ns +
+                                                     (size_t)part * per);
   float m = 0.f;
-  for (size_t i = tid; i < (size_t)ns * ns; i += 256) {
-    const float2 v = pl[i];
-    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+  for (size_t i = tid; i < per / 2; i += 256) {
+    const float4 v = pl[i];
+    m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
   __shared__ float red[4];
   if ((tid & 63) == 0) red[tid >> 6] = m;
   __syncthreads();
-  if (tid == 0) {
-    const float mm = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    float sc = 1.f;
-    if (mm > 0.f) {
-      int e;
-      frexpf(mm, &e);  // mm = fr * 2^e with fr in [0.5, 1), so mm < 2^e
-      sc = ldexpf(1.f, -e);
-    }
-    scale[a] = sc;
+  if (tid == 0)
+    partial[(size_t)a * kScaleSplit + part] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void k_s16_scale(const float* __restrict__ partial, int n_act,
+                                                   float* __restrict__ scale) {
+  const int a = blockIdx.x * 256 + threadIdx.x;
+  if (a >= n_act) return;
+  float mm = 0.f;
+  for (int k = 0; k < kScaleSplit; ++k) mm = fmaxf(mm, partial[(size_t)a * kScaleSplit + k]);
+  float sc = 1.f;
+  if (mm > 0.f) {
+    int e;
+    frexpf(mm, &e);  // mm = fr * 2^e with fr in [0.5, 1), so mm < 2^e
+    sc = ldexpf(1.f, -e);
   }
+  scale[a] = sc;
 }
 
 // FP32: 16 beams x 64 pixels per workgroup, transposed through LDS; a pixel
@@ -415,8 +427,13 @@ inline unsigned blocks16(size_t n, unsigned bs) { return (unsigned)((n + bs - 1)
 }  // namespace
 
 hipError_t launch_s16_scale(const float2* smatrix, const ActiveBeam* act, int n_act, int ns,
-                            float* scale, hipStream_t st) {
-  hipLaunchKernelGGL(k_s16_scale, dim3((unsigned)n_act), dim3(256), 0, st, smatrix, act, ns, scale);
+                            float* partial, float* scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_s16_absmax, dim3((unsigned)n_act, (unsigned)kScaleSplit), dim3(256), 0, st,
+                     smatrix, act, ns, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_s16_scale, dim3((unsigned)((n_act + 255) / 256)), dim3(256), 0, st, partial,
+                     n_act, scale);
   return hipGetLastError();
 }
 
