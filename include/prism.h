@@ -20,9 +20,10 @@
  *     returns a thread-local message for the last failing call.
  *   - Complex values are interleaved float pairs (re, im) ("c64").
  *
- * Limits of this implementation: n is a power of two in [128, 2048]; the
- * PRISM window side W = n / (2 f) is a power of two in [8, 256]; at most
- * PRISM_MAX_DET detector bins.
+ * Limits of this implementation: n is 2^k or 3 * 2^k in [128, 2048] (128,
+ * 192, 256, 384, 512, 768, 1024, 1536, 2048); the PRISM window side
+ * W = n / (2 f) is a power of two in [8, 256] (so f = 3, 6, 12, 24 on the
+ * 3 * 2^k grids); at most PRISM_MAX_DET detector bins.
  */
 #ifndef PRISM_H
 #define PRISM_H
@@ -168,7 +169,8 @@ int prism_build_smatrix(prism_plan* plan, int f, double alpha_max_mrad, void* sm
  * each item alone, bit for bit.
  * Workspace (prism_build_batch_workspace_bytes): per group the
  * transmissions of every member (sum of H n^2 complex64), the beam lists and
- * up to 4 GiB of wave state; the minimum holds one wave of state.
+ * up to 256 MiB of wave state per launch (larger launches lose the cache
+ * reuse of the transmissions); the minimum holds one wave of state.
  * Errors: PRISM_EINVAL (null or invalid item, negative count), the checks of
  * prism_build_smatrix for every item (message prefixed by the item index),
  * PRISM_ENOSPACE, PRISM_EHIP. count == 0 is a no-op. The plans must not be

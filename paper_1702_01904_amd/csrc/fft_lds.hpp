@@ -98,10 +98,86 @@ __host__ __device__ __forceinline__ void dft8(float2 (&v)[8]) {
   v[7] = csub(e3, o3);
 }
 
+// 3-point DFT: X1, X2 = a - (b + c)/2 -+ i (sqrt(3)/2)(b - c) (forward).
+template <bool INV>
+__host__ __device__ __forceinline__ void dft3v(float2& a, float2& b, float2& c) {
+  constexpr float h = 0.86602540378443864676f;  // sqrt(3) / 2
+  const float2 t1 = cadd(b, c), t2 = csub(b, c);
+  const float2 m = make_float2(a.x - 0.5f * t1.x, a.y - 0.5f * t1.y);
+  const float2 r = mul_mi<INV>(make_float2(h * t2.x, h * t2.y));  // -+ i h (b - c)
+  a = cadd(a, t1);
+  b = cadd(m, r);
+  c = csub(m, r);
+}
+
+template <bool INV>
+__host__ __device__ __forceinline__ void dft3(float2 (&v)[3]) {
+  dft3v<INV>(v[0], v[1], v[2]);
+}
+
+// cos and sin of 2 pi m / 12 for any integer m.
+__host__ __device__ constexpr float cos12(int m) {
+  return (m % 12 + 12) % 12 == 0    ? 1.0f
+         : (m % 12 + 12) % 12 == 1  ? 0.86602540378443864676f
+         : (m % 12 + 12) % 12 == 2  ? 0.5f
+         : (m % 12 + 12) % 12 == 3  ? 0.0f
+         : (m % 12 + 12) % 12 == 4  ? -0.5f
+         : (m % 12 + 12) % 12 == 5  ? -0.86602540378443864676f
+         : (m % 12 + 12) % 12 == 6  ? -1.0f
+         : (m % 12 + 12) % 12 == 7  ? -0.86602540378443864676f
+         : (m % 12 + 12) % 12 == 8  ? -0.5f
+         : (m % 12 + 12) % 12 == 9  ? 0.0f
+         : (m % 12 + 12) % 12 == 10 ? 0.5f
+                                    : 0.86602540378443864676f;
+}
+__host__ __device__ constexpr float sin12(int m) { return cos12(m - 3); }
+
+// a * exp(-+2 pi i m / 12) (forward sign for INV = false), m a compile-time
+// constant after unrolling.
+template <bool INV>
+__host__ __device__ __forceinline__ float2 rot12(float2 a, int m) {
+  const int q = (m % 12 + 12) % 12;
+  if (q == 0) return a;
+  if (q == 6) return make_float2(-a.x, -a.y);
+  if (q == 3) return mul_mi<INV>(a);
+  if (q == 9) return mul_mi<!INV>(a);
+  const float c = cos12(q), s = INV ? sin12(q) : -sin12(q);
+  return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+}
+
+// R = R1 * R2 (6 = 2 * 3, 12 = 4 * 3): R2 DFTs of length R1 over a
+// (x = R2 a + b), twiddles w_R^{bc}, R1 DFTs of length R2 over b.
+template <int R1, int R2, bool INV>
+__host__ __device__ __forceinline__ void dft_ct12(float2 (&v)[R1 * R2]) {
+  constexpr int R = R1 * R2;
+  float2 y[R2][R1];
+#pragma unroll
+  for (int b = 0; b < R2; ++b) {
+#pragma unroll
+    for (int a = 0; a < R1; ++a) y[b][a] = v[R2 * a + b];
+    if constexpr (R1 == 2) dft2<INV>(y[b]);
+    else dft4<INV>(y[b]);
+#pragma unroll
+    for (int c = 1; c < R1; ++c) y[b][c] = rot12<INV>(y[b][c], (12 / R) * b * c);
+  }
+#pragma unroll
+  for (int c = 0; c < R1; ++c) {
+    float2 z[R2];
+#pragma unroll
+    for (int b = 0; b < R2; ++b) z[b] = y[b][c];
+    dft3<INV>(z);
+#pragma unroll
+    for (int d = 0; d < R2; ++d) v[c + R1 * d] = z[d];
+  }
+}
+
 template <int R, bool INV>
 __host__ __device__ __forceinline__ void dft(float2 (&v)[R]) {
   if constexpr (R == 2) dft2<INV>(v);
+  else if constexpr (R == 3) dft3<INV>(v);
   else if constexpr (R == 4) dft4<INV>(v);
+  else if constexpr (R == 6) dft_ct12<2, 3, INV>(v);
+  else if constexpr (R == 12) dft_ct12<4, 3, INV>(v);
   else dft8<INV>(v);
 }
 
@@ -175,7 +251,7 @@ __device__ __forceinline__ void stage_in(const float2* lds, const float2* tw, in
     if (!SS::GUARD || b < SS::TOT) {
       int s, j;
       stage_coords<B, SS::NB>(b, s, j);
-      const int k = j & (NS - 1);
+      const int k = j % NS;
       const int base = B::addr(s, j);
       const int pbase = lpad(base);
 #pragma unroll
@@ -187,15 +263,20 @@ __device__ __forceinline__ void stage_in(const float2* lds, const float2* tw, in
         // FP32 path's error roughly doubles, ~1.7e-5 relative at 1024^2 and
         // 50 slices).
         float2 w[R];
-        w[1] = tw[k * TWS];
-        if constexpr (R >= 4) w[2] = tw[2 * k * TWS];
-        if constexpr (R == 4) w[3] = cmul(w[1], w[2]);
-        if constexpr (R == 8) {
-          w[4] = tw[4 * k * TWS];
-          w[3] = cmul(w[1], w[2]);
-          w[5] = cmul(w[1], w[4]);
-          w[6] = cmul(w[2], w[4]);
-          w[7] = cmul(w[3], w[4]);
+        if constexpr (R == 2 || R == 4 || R == 8) {
+          w[1] = tw[k * TWS];
+          if constexpr (R >= 4) w[2] = tw[2 * k * TWS];
+          if constexpr (R == 4) w[3] = cmul(w[1], w[2]);
+          if constexpr (R == 8) {
+            w[4] = tw[4 * k * TWS];
+            w[3] = cmul(w[1], w[2]);
+            w[5] = cmul(w[1], w[4]);
+            w[6] = cmul(w[2], w[4]);
+            w[7] = cmul(w[3], w[4]);
+          }
+        } else {  // radix 3, 6, 12: every power from the table
+#pragma unroll
+          for (int r = 1; r < R; ++r) w[r] = tw[r * k * TWS];
         }
 #pragma unroll
         for (int r = 1; r < R; ++r) v[p][r] = INV ? cmulc(v[p][r], w[r]) : cmul(v[p][r], w[r]);
@@ -215,7 +296,7 @@ __device__ __forceinline__ void stage_out(float2* lds, int tid,
       int s, j;
       stage_coords<B, SS::NB>(b, s, j);
       dft<R, INV>(v[p]);
-      const int k = j & (NS - 1);
+      const int k = j % NS;
       const int o = (j - k) * R + k;
       constexpr int STEP = NS * B::ESTR;
       const int base = B::addr(s, o);
@@ -245,27 +326,39 @@ __device__ __forceinline__ void fft_radix8_run(float2* lds, const float2* tw, in
   }
 }
 
-// Radix plan of a length-L transform split as 8 * 8^MID * RL (RL in 2, 4, 8):
-// the inverse runs 8, 8^MID, RL and the forward the reverse RL, 8^MID, 8, so
-// that the inverse's last stage and the forward's first stage pair up on
-// the same elements (j + r L/RL) and can stay in registers.
+// Lengths handled by the LDS transforms: 2^k, or 3 * 2^k.
+__host__ __device__ constexpr bool fft_len_ok(int L) {
+  return L > 0 && ((1 << ilog2(L)) == L || (L % 3 == 0 && (1 << ilog2(L / 3)) == L / 3));
+}
+
+// Radix plan of a length-L transform split as 8 * 8^MID * RL (RL in 2, 4, 8
+// for L = 2^k; 3, 6, 12 for L = 3 * 2^k): the inverse runs 8, 8^MID, RL and
+// the forward the reverse RL, 8^MID, 8, so that the inverse's last stage
+// and the forward's first stage pair up on the same elements (j + r L/RL)
+// and can stay in registers.
 template <int L>
 struct PairedPlan {
-  static constexpr int K = ilog2(L);
-  static constexpr int RL = (K % 3 == 1) ? 2 : ((K % 3 == 2) ? 4 : 8);
-  static constexpr int MID = (K - 3 - ilog2(RL)) / 3;
+  static constexpr bool T3 = L % 3 == 0;
+  static constexpr int K = ilog2(T3 ? L / 3 : L);
+  static constexpr int RL = T3 ? 3 * (1 << ((K - 3) % 3))
+                               : ((K % 3 == 1) ? 2 : ((K % 3 == 2) ? 4 : 8));
+  static constexpr int MID = (K - 3 - ilog2(T3 ? RL / 3 : RL)) / 3;
 };
 
 template <class B, int NT, bool INV, int NS>
 __device__ __forceinline__ void fft_from(float2* lds, const float2* tw, int tid) {
   constexpr int REM = B::L / NS;  // product of the radices still to apply
-  if constexpr (REM >= 8) {
+  if constexpr (REM % 8 == 0) {
     fft_stage<B, 8, NS, NT, INV>(lds, tw, tid);
     fft_from<B, NT, INV, NS * 8>(lds, tw, tid);
-  } else if constexpr (REM == 4) {
+  } else if constexpr (REM % 4 == 0) {
     fft_stage<B, 4, NS, NT, INV>(lds, tw, tid);
-  } else if constexpr (REM == 2) {
+    fft_from<B, NT, INV, NS * 4>(lds, tw, tid);
+  } else if constexpr (REM % 2 == 0) {
     fft_stage<B, 2, NS, NT, INV>(lds, tw, tid);
+    fft_from<B, NT, INV, NS * 2>(lds, tw, tid);
+  } else if constexpr (REM == 3) {
+    fft_stage<B, 3, NS, NT, INV>(lds, tw, tid);
   }
 }
 
@@ -274,7 +367,7 @@ __device__ __forceinline__ void fft_from(float2* lds, const float2* tw, int tid)
 // return the result is in LDS and visible to all threads.
 template <class B, int NT, bool INV>
 __device__ __forceinline__ void fft_lds(float2* lds, const float2* tw, int tid) {
-  static_assert((1 << ilog2(B::L)) == B::L, "power-of-two lengths only");
+  static_assert(fft_len_ok(B::L), "lengths 2^k or 3 * 2^k only");
   fft_from<B, NT, INV, 1>(lds, tw, tid);
 }
 

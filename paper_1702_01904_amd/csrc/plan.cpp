@@ -654,8 +654,10 @@ const char* prism_last_error(void) { return g_err.c_str(); }
 int prism_plan_create(prism_plan** out, const prism_geometry* g) {
   if (!out || !g) return fail(PRISM_EINVAL, "null argument");
   *out = nullptr;
-  if (!is_pow2(g->n) || g->n < 128 || g->n > 2048)
-    return fail(PRISM_EINVAL, "n must be a power of two in [128, 2048]");
+  // grids 2^k or 3 * 2^k (the LDS transforms have radices 2, 4, 8 and 3)
+  const bool grid_ok = is_pow2(g->n) || (g->n % 3 == 0 && is_pow2(g->n / 3));
+  if (!grid_ok || g->n < 128 || g->n > 2048)
+    return fail(PRISM_EINVAL, "n must be 2^k or 3 * 2^k in [128, 2048]");
   if (!(g->cell_A > 0.0) || !std::isfinite(g->cell_A)) return fail(PRISM_EINVAL, "cell must be > 0");
   if (!(g->energy_keV > 0.0) || !std::isfinite(g->energy_keV))
     return fail(PRISM_EINVAL, "energy must be > 0");
@@ -1045,9 +1047,11 @@ int batch_total_waves(const prism_build_item* items, const BatchGroup& g) {
   return t;
 }
 
-// Waves in flight per batched launch: up to 4 GiB of wave state.
+#ifndef PRISM_BATCH_CHUNK_SHIFT
+#define PRISM_BATCH_CHUNK_SHIFT 28  // wave state per batched launch: 2^shift bytes at most
+#endif
 int batch_pref_chunk(int n, int total) {
-  const size_t cap = (size_t(1) << 32) / state_bytes(n);
+  const size_t cap = (size_t(1) << PRISM_BATCH_CHUNK_SHIFT) / state_bytes(n);
   return (int)std::max<size_t>(1, std::min<size_t>(cap, (size_t)total));
 }
 

@@ -31,16 +31,19 @@ namespace {
 
 constexpr int kRowNT = PRISM_ROW_ELEMS / 8;
 
-__host__ __device__ constexpr int row_nseq(int n) {
-  return PRISM_ROW_ELEMS / n > 0 ? PRISM_ROW_ELEMS / n : 1;
+// Largest power of two p with p n <= cap (at least 1): rows per workgroup
+// that divide every wave's n rows (n = 2^k or 3 2^k).
+__host__ __device__ constexpr int pow2_rows(int n, int cap) {
+  return 2 * n <= cap ? 2 * pow2_rows(2 * n, cap) : 1;
 }
+__host__ __device__ constexpr int row_nseq(int n) { return pow2_rows(n, PRISM_ROW_ELEMS); }
 __host__ __device__ constexpr int col_tc(int n) { return 8; }
 __host__ __device__ constexpr int col_nt(int n) {
   return (col_tc(n) * n / PRISM_COL_E) < 64
              ? 64
              : (col_tc(n) * n / PRISM_COL_E > 1024 ? 1024 : col_tc(n) * n / PRISM_COL_E);
 }
-__host__ __device__ constexpr int ext_nseq(int n) { return 4096 / n; }
+__host__ __device__ constexpr int ext_nseq(int n) { return pow2_rows(n, 4096); }
 
 // Map launch order onto tiles so that consecutive tiles run on the same
 // XCD (workgroups are dealt to the 8 XCDs round-robin) and share its L2.
@@ -151,12 +154,14 @@ __global__ __launch_bounds__(kRowNT) void k_row_pass(float2* __restrict__ state,
     float2 v[S8::PER][8];
 #pragma unroll
     for (int p = 0; p < S8::PER; ++p) {
+      const int b = tid + p * NT;
+      v[p][2] = v[p][3] = v[p][4] = v[p][5] = make_float2(0.f, 0.f);
+      if (S8::GUARD && b >= S8::TOT) continue;  // no butterfly (stage_out skips it too)
       int sq, j;
-      stage_coords<B, S8::NB>(tid + p * NT, sq, j);
+      stage_coords<B, S8::NB>(b, sq, j);
       const float2* src = state + (row0 + sq) * H2 + j;
       v[p][0] = src[0];
       v[p][1] = src[E8];
-      v[p][2] = v[p][3] = v[p][4] = v[p][5] = make_float2(0.f, 0.f);
       v[p][6] = src[2 * E8];
       v[p][7] = src[3 * E8];
     }
@@ -168,11 +173,13 @@ __global__ __launch_bounds__(kRowNT) void k_row_pass(float2* __restrict__ state,
   stage_in<B, RL, NSL, NT, true>(lds, tw, tid, v);
 #pragma unroll
   for (int p = 0; p < SL::PER; ++p) {
+    const int b = tid + p * NT;
+    if (SL::GUARD && b >= SL::TOT) continue;
     int sq, j;
-    stage_coords<B, SL::NB>(tid + p * NT, sq, j);
+    stage_coords<B, SL::NB>(b, sq, j);
     dft<RL, true>(v[p]);
     const float2* tb = WT ? wtrans[(row0 + sq) / N] + soff : trans;
-    const float2* t = tb + (size_t)((row0 + sq) & (size_t)(N - 1)) * N + j;
+    const float2* t = tb + (size_t)((row0 + sq) % (size_t)N) * N + j;
 #pragma unroll
     for (int r = 0; r < RL; ++r) v[p][r] = cmul(v[p][r], t[r * NSL]);
   }
@@ -186,8 +193,10 @@ __global__ __launch_bounds__(kRowNT) void k_row_pass(float2* __restrict__ state,
     stage_in<B, 8, E8, NT, false>(lds, tw, tid, w);
 #pragma unroll
     for (int p = 0; p < S8::PER; ++p) {
+      const int b = tid + p * NT;
+      if (S8::GUARD && b >= S8::TOT) continue;
       int sq, j;
-      stage_coords<B, S8::NB>(tid + p * NT, sq, j);
+      stage_coords<B, S8::NB>(b, sq, j);
       dft8<false>(w[p]);
       float2* dst = state + (row0 + sq) * H2 + j;
       dst[0] = w[p][0];
@@ -459,8 +468,10 @@ void k_col_pass(float2* __restrict__ state, const float2* __restrict__ prop,
     float2 v[S8::PER][8];
 #pragma unroll
     for (int p = 0; p < S8::PER; ++p) {
+      const int b = tid + p * NT;
+      if (S8::GUARD && b >= S8::TOT) continue;  // no butterfly (stage_out skips it too)
       int c, j;
-      stage_coords<B, S8::NB>(tid + p * NT, c, j);
+      stage_coords<B, S8::NB>(b, c, j);
 #pragma unroll
       for (int r = 0; r < 8; ++r) v[p][r] = base[(size_t)(j + r * E8) * H2 + c];
     }
@@ -473,12 +484,14 @@ void k_col_pass(float2* __restrict__ state, const float2* __restrict__ prop,
   const float inv_n = 1.0f / (float)N;
 #pragma unroll
   for (int p = 0; p < SL::PER; ++p) {
+    const int b = tid + p * NT;
+    if (SL::GUARD && b >= SL::TOT) continue;
     int c, j;
-    stage_coords<B, SL::NB>(tid + p * NT, c, j);
+    stage_coords<B, SL::NB>(b, c, j);
     dft<RL, false>(v[p]);
     const int jj = c0 + c;
     const int kx = jj < Q ? jj : jj - H2;
-    const float2 px = prop[kx & (N - 1)];
+    const float2 px = prop[kx < 0 ? kx + N : kx];
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
       const int yi = j + r * NSL;
@@ -501,8 +514,10 @@ void k_col_pass(float2* __restrict__ state, const float2* __restrict__ prop,
     stage_in<B, 8, E8, NT, true>(lds, tw, tid, u);
 #pragma unroll
     for (int p = 0; p < S8::PER; ++p) {
+      const int b = tid + p * NT;
+      if (S8::GUARD && b >= S8::TOT) continue;
       int c, j;
-      stage_coords<B, S8::NB>(tid + p * NT, c, j);
+      stage_coords<B, S8::NB>(b, c, j);
       dft8<true>(u[p]);
 #pragma unroll
       for (int r = 0; r < 8; ++r) base[(size_t)(j + r * E8) * H2 + c] = u[p][r];
@@ -516,8 +531,10 @@ void k_col_pass(float2* __restrict__ state, const float2* __restrict__ prop,
       for (int q = 0; q < 8; ++q) acc[q] = 0.0;
 #pragma unroll
       for (int p = 0; p < SL::PER; ++p) {
+        const int b = tid + p * NT;
+        if (SL::GUARD && b >= SL::TOT) continue;
         int c, j;
-        stage_coords<B, SL::NB>(tid + p * NT, c, j);
+        stage_coords<B, SL::NB>(b, c, j);
         const int jj = c0 + c;
         const int kx = jj < Q ? jj : jj - H2;
 #pragma unroll
@@ -682,9 +699,13 @@ hipError_t launch_beam_init(float2* state, const int32_t* beams_mn, int b0, int 
 #define PRISM_DISPATCH_N(n, CALL) \
   switch (n) {                    \
     case 128: CALL(128); break;   \
+    case 192: CALL(192); break;   \
     case 256: CALL(256); break;   \
+    case 384: CALL(384); break;   \
     case 512: CALL(512); break;   \
+    case 768: CALL(768); break;   \
     case 1024: CALL(1024); break; \
+    case 1536: CALL(1536); break; \
     case 2048: CALL(2048); break; \
     default: return hipErrorInvalidValue; \
   }

@@ -56,6 +56,28 @@ CONFIGS = {
         detectors=[(0.0, 20.0), (20.0, 50.0), (50.0, 100.0)],
         f_values=(2, 4),
     ),
+    # Grids with a factor 3 (radix-3 FFT stages): 192^2 and 384^2 with
+    # 0.1 A pixels; windows stay powers of two at f = 3, 6, 12.
+    "tiny192": dict(
+        specimen=dict(kind="random", cell=(19.2, 19.2, 8.0), n_atoms=30,
+                      z_choices=(6, 14, 29, 79)),
+        n=192, n_slices=4, slice_A=2.0,
+        energy_keV=80.0,
+        optics=dict(alpha_mrad=20.0, C1_A=0.0, C3_A=0.0),
+        scan=dict(nx=12, ny=12, step_A=1.6, origin_A=(0.0, 0.0)),
+        detectors=[(0.0, 20.0), (40.0, 100.0)],
+        f_values=(3, 6),
+    ),
+    "mid384": dict(
+        specimen=dict(kind="random", cell=(38.4, 38.4, 12.0), n_atoms=160,
+                      z_choices=(6, 14, 29, 79)),
+        n=384, n_slices=6, slice_A=2.0,
+        energy_keV=80.0,
+        optics=dict(alpha_mrad=20.0, C1_A=20.0, C3_A=0.0),
+        scan=dict(nx=17, ny=9, step_A=0.8, origin_A=(5.0, 5.0)),
+        detectors=[(0.0, 20.0), (20.0, 50.0), (50.0, 100.0)],
+        f_values=(3, 6, 12),
+    ),
     # Precision case (nanoparticle on an amorphous carbon slab, 2048^2).
     "np2048": dict(
         specimen=dict(kind="np_on_carbon", cell=(80.0, 80.0, 70.0),
@@ -73,16 +95,19 @@ CONFIGS = {
 # Mixed batches of specimens (many small and large specimens built
 # together). Each entry is a recipe for ``batch_workload``: grid sizes with
 # 0.1 A pixels, slice counts drawn uniformly, interpolation factors drawn
-# among those the grid admits, random atoms at 0.015 A^-3.
+# among those the grid admits (power-of-two windows of 8..256 pixels),
+# random atoms at 0.015 A^-3.
 BATCHES = {
-    # 32 specimens on power-of-two grids, 20-120 slices, f in {4, 8, 16}.
-    "batch32": dict(count=32, sizes=(256, 512, 1024), h_range=(20, 120), f_choices=(4, 8, 16),
+    # 32 specimens on 2^k and 3 * 2^k grids, 20-120 slices, f in
+    # {4, 6, 8, 12, 16} (4, 8, 16 on 2^k grids; 6, 12 on 3 * 2^k grids).
+    "batch32": dict(count=32, sizes=(256, 384, 512, 768, 1024, 1536), h_range=(20, 120),
+                    f_choices=(4, 6, 8, 12, 16),
                     pixel_A=0.1, density=0.015, slice_A=2.0, energy_keV=80.0,
                     optics=dict(alpha_mrad=20.0, C1_A=0.0, C3_A=0.0),
                     detectors=[(0.0, 20.0), (20.0, 40.0), (40.0, 100.0)],
                     z_choices=(6, 14, 29, 79)),
     # Small mix for parity against the oracle.
-    "batch_small": dict(count=6, sizes=(128, 256), h_range=(2, 6), f_choices=(1, 2, 4),
+    "batch_small": dict(count=6, sizes=(128, 192, 256), h_range=(2, 6), f_choices=(1, 2, 3, 4, 6),
                         pixel_A=0.1, density=0.015, slice_A=2.0, energy_keV=80.0,
                         optics=dict(alpha_mrad=20.0, C1_A=0.0, C3_A=0.0),
                         detectors=[(0.0, 20.0), (20.0, 40.0), (40.0, 100.0)],

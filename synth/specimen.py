@@ -264,7 +264,10 @@ def phonon_configurations(name_or_cfg, seed, n_configs, jitter_A=None, n_slices=
 def _batch_shape(rec, rng):
     n = int(rng.choice(np.asarray(rec["sizes"])))
     H = int(rng.integers(rec["h_range"][0], rec["h_range"][1] + 1))
-    fs = [f for f in rec["f_choices"] if n % (2 * f) == 0 and 8 <= n // (2 * f) <= 256]
+    def window_ok(f):
+        w = n // (2 * f)
+        return n % (2 * f) == 0 and 8 <= w <= 256 and (w & (w - 1)) == 0
+    fs = [f for f in rec["f_choices"] if window_ok(f)]
     return n, H, int(rng.choice(np.asarray(fs)))
 
 
@@ -284,7 +287,8 @@ def batch_workload(name_or_recipe, seed=0, count=None, indices=None):
     factors with n % (2 f) == 0 and 8 <= n / (2 f) <= 256, then the atoms
     (random, density atoms per A^3 in an n * pixel square cell of
     thickness H * slice). The scan is the (n/4) x (n/4) raster at two
-    S-matrix pixels. ``indices`` builds only those specimens of the batch
+    S-matrix pixels. Factors are kept only where the window n / (2 f) is a
+    power of two in [8, 256]. ``indices`` builds only those specimens of the batch
     (the others are not generated); ``batch_shapes`` lists (n, H, f) of all.
     """
     rec = BATCHES[name_or_recipe] if isinstance(name_or_recipe, str) else name_or_recipe

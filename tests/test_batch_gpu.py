@@ -113,11 +113,12 @@ def test_batch_groups_by_medium():
 
 def test_batch_full_size_members():
     # members of the 32-specimen mix at their real sizes (n = 1024 with
-    # f = 4, n = 512, n = 256): batched S equals single builds, and sampled
+    # f = 4, n = 512, n = 768, n = 256): batched S equals single builds, and sampled
     # probes of the n = 256 member through the batched S against the oracle
     shapes = batch_shapes("batch32", 0)
     pick = [i for i, (n, _, f) in enumerate(shapes) if n == 1024 and f == 4][:1]
     pick += [i for i, (n, _, _) in enumerate(shapes) if n == 512][:1]
+    pick += [i for i, (n, _, _) in enumerate(shapes) if n == 768][:1]   # a 3 * 2^k grid
     pick += [i for i, (n, _, _) in enumerate(shapes) if n == 256][:2]
     chosen = batch_workload("batch32", 0, indices=pick)
     entries = _plans(chosen)

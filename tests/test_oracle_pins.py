@@ -384,6 +384,20 @@ def test_p8_prism_two_pixel_shift():
     assert np.abs(D1 - D0).max() <= 1e-10 * np.abs(D0).max()
 
 
+def test_p6_prism_f1_equals_multislice_on_a_3x2k_grid():
+    # the same identity on a grid with a factor 3 (192 = 3 * 64), the oracle's
+    # FFTs being mixed radix there
+    d = build_inputs("tiny192", 1)
+    cell, E = d["cell"], d["energy_keV"]
+    lam = O.wavelength(E)
+    amax = O.default_alpha_max(0.020, 1, lam, 1 / cell) * 1e3
+    pr = d["probes"][::29]
+    beams, S = O.smatrix(d["phase"], d["thickness"], cell, E, 1, amax)
+    Dp = O.prism_outputs(S, beams, 1, cell, E, d["optics"], pr, d["edges"])
+    Dm = O.multislice_stem(d["phase"], d["thickness"], cell, E, d["optics"], pr, d["edges"])
+    assert O.rel_l2(Dp, Dm) < 1e-12
+
+
 # ---------------------------------------------------------------- frozen phonons
 
 def test_frozen_phonon_prism_f1_equals_multislice_average():
