@@ -20,10 +20,10 @@
  *     returns a thread-local message for the last failing call.
  *   - Complex values are interleaved float pairs (re, im) ("c64").
  *
- * Limits of this implementation: n is 2^k or 3 * 2^k in [128, 2048] (128,
- * 192, 256, 384, 512, 768, 1024, 1536, 2048); the PRISM window side
- * W = n / (2 f) is a power of two in [8, 256] (so f = 3, 6, 12, 24 on the
- * 3 * 2^k grids); at most PRISM_MAX_DET detector bins.
+ * Limits of this implementation: n is 2^k, 3 * 2^k or 9 * 2^k in
+ * [128, 2048] (128, 192, 256, 384, 512, 576, 768, 1024, 1152, 1536, 2048);
+ * the PRISM window side W = n / (2 f) is a power of two in [8, 256] or one
+ * of 24, 48, 72, 96; at most PRISM_MAX_DET detector bins.
  */
 #ifndef PRISM_H
 #define PRISM_H

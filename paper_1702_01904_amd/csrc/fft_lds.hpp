@@ -145,6 +145,66 @@ __host__ __device__ __forceinline__ float2 rot12(float2 a, int m) {
   return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
 }
 
+// cos(2 pi m / 36) for m in [0, 9], and cos / sin of 2 pi m / 36 for any m.
+__host__ __device__ constexpr float cos36_q1(int m) {
+  return m == 0 ? 1.0f
+         : m == 1 ? 0.98480775301220802032f
+         : m == 2 ? 0.93969262078590842791f
+         : m == 3 ? 0.86602540378443870761f
+         : m == 4 ? 0.76604444311897801345f
+         : m == 5 ? 0.64278760968653936292f
+         : m == 6 ? 0.50000000000000011102f
+         : m == 7 ? 0.34202014332566882393f
+         : m == 8 ? 0.17364817766693041445f
+         : m == 9 ? 0.00000000000000006123f
+                : 0.0f;
+}
+__host__ __device__ constexpr float cos36(int m) {
+  return (m % 36 + 36) % 36 <= 9    ? cos36_q1((m % 36 + 36) % 36)
+         : (m % 36 + 36) % 36 <= 18 ? -cos36_q1(18 - (m % 36 + 36) % 36)
+         : (m % 36 + 36) % 36 <= 27 ? -cos36_q1((m % 36 + 36) % 36 - 18)
+                                    : cos36_q1(36 - (m % 36 + 36) % 36);
+}
+__host__ __device__ constexpr float sin36(int m) { return cos36(m - 9); }
+
+// a * exp(-+2 pi i m / 36), m a compile-time constant after unrolling.
+template <bool INV>
+__host__ __device__ __forceinline__ float2 rot36(float2 a, int m) {
+  const int q = (m % 36 + 36) % 36;
+  if (q == 0) return a;
+  if (q == 18) return make_float2(-a.x, -a.y);
+  if (q == 9) return mul_mi<INV>(a);
+  if (q == 27) return mul_mi<!INV>(a);
+  const float c = cos36(q), s = INV ? sin36(q) : -sin36(q);
+  return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+}
+
+// 9-point DFT as 3 x 3 and 18-point as 2 x 9 (Cooley-Tukey, x = R2 a + b).
+template <int R1, int R2, bool INV>
+__host__ __device__ __forceinline__ void dft_ct36(float2 (&v)[R1 * R2]) {
+  constexpr int R = R1 * R2;
+  float2 y[R2][R1];
+#pragma unroll
+  for (int b = 0; b < R2; ++b) {
+#pragma unroll
+    for (int a = 0; a < R1; ++a) y[b][a] = v[R2 * a + b];
+    if constexpr (R1 == 2) dft2<INV>(y[b]);
+    else dft3<INV>(y[b]);
+#pragma unroll
+    for (int c = 1; c < R1; ++c) y[b][c] = rot36<INV>(y[b][c], (36 / R) * b * c);
+  }
+#pragma unroll
+  for (int c = 0; c < R1; ++c) {
+    float2 z[R2];
+#pragma unroll
+    for (int b = 0; b < R2; ++b) z[b] = y[b][c];
+    if constexpr (R2 == 3) dft3<INV>(z);
+    else dft_ct36<3, 3, INV>(z);
+#pragma unroll
+    for (int d = 0; d < R2; ++d) v[c + R1 * d] = z[d];
+  }
+}
+
 // R = R1 * R2 (6 = 2 * 3, 12 = 4 * 3): R2 DFTs of length R1 over a
 // (x = R2 a + b), twiddles w_R^{bc}, R1 DFTs of length R2 over b.
 template <int R1, int R2, bool INV>
@@ -173,11 +233,15 @@ __host__ __device__ __forceinline__ void dft_ct12(float2 (&v)[R1 * R2]) {
 
 template <int R, bool INV>
 __host__ __device__ __forceinline__ void dft(float2 (&v)[R]) {
+  static_assert(R == 2 || R == 3 || R == 4 || R == 6 || R == 8 || R == 9 || R == 12 || R == 18,
+                "register DFT lengths 2, 3, 4, 6, 8, 9, 12, 18");
   if constexpr (R == 2) dft2<INV>(v);
   else if constexpr (R == 3) dft3<INV>(v);
   else if constexpr (R == 4) dft4<INV>(v);
   else if constexpr (R == 6) dft_ct12<2, 3, INV>(v);
   else if constexpr (R == 12) dft_ct12<4, 3, INV>(v);
+  else if constexpr (R == 9) dft_ct36<3, 3, INV>(v);
+  else if constexpr (R == 18) dft_ct36<2, 9, INV>(v);
   else dft8<INV>(v);
 }
 
@@ -274,7 +338,7 @@ __device__ __forceinline__ void stage_in(const float2* lds, const float2* tw, in
             w[6] = cmul(w[2], w[4]);
             w[7] = cmul(w[3], w[4]);
           }
-        } else {  // radix 3, 6, 12: every power from the table
+        } else {  // radix 3, 6, 9, 12, 18: every power from the table
 #pragma unroll
           for (int r = 1; r < R; ++r) w[r] = tw[r * k * TWS];
         }
@@ -326,9 +390,10 @@ __device__ __forceinline__ void fft_radix8_run(float2* lds, const float2* tw, in
   }
 }
 
-// Lengths handled by the LDS transforms: 2^k, or 3 * 2^k.
+// Lengths handled by the LDS transforms: 2^k, 3 * 2^k or 9 * 2^k.
+__host__ __device__ constexpr bool pow2_len(int L) { return L > 0 && (1 << ilog2(L)) == L; }
 __host__ __device__ constexpr bool fft_len_ok(int L) {
-  return L > 0 && ((1 << ilog2(L)) == L || (L % 3 == 0 && (1 << ilog2(L / 3)) == L / 3));
+  return pow2_len(L) || (L % 3 == 0 && pow2_len(L / 3)) || (L % 9 == 0 && pow2_len(L / 9));
 }
 
 // Radix plan of a length-L transform split as 8 * 8^MID * RL (RL in 2, 4, 8
@@ -338,11 +403,12 @@ __host__ __device__ constexpr bool fft_len_ok(int L) {
 // and can stay in registers.
 template <int L>
 struct PairedPlan {
-  static constexpr bool T3 = L % 3 == 0;
-  static constexpr int K = ilog2(T3 ? L / 3 : L);
-  static constexpr int RL = T3 ? 3 * (1 << ((K - 3) % 3))
-                               : ((K % 3 == 1) ? 2 : ((K % 3 == 2) ? 4 : 8));
-  static constexpr int MID = (K - 3 - ilog2(T3 ? RL / 3 : RL)) / 3;
+  static constexpr int T = L % 9 == 0 ? 9 : (L % 3 == 0 ? 3 : 1);  // odd factor
+  static constexpr int K = ilog2(L / T);
+  // RL = T * 2^((K - 3) mod 3) for T > 1 (3, 6, 12 or 9, 18, 36)
+  static constexpr int RL = T > 1 ? T * (1 << ((K - 3) % 3))
+                                  : ((K % 3 == 1) ? 2 : ((K % 3 == 2) ? 4 : 8));
+  static constexpr int MID = (K - 3 - ilog2(RL / T)) / 3;
 };
 
 template <class B, int NT, bool INV, int NS>
@@ -357,8 +423,9 @@ __device__ __forceinline__ void fft_from(float2* lds, const float2* tw, int tid)
   } else if constexpr (REM % 2 == 0) {
     fft_stage<B, 2, NS, NT, INV>(lds, tw, tid);
     fft_from<B, NT, INV, NS * 2>(lds, tw, tid);
-  } else if constexpr (REM == 3) {
+  } else if constexpr (REM % 3 == 0) {
     fft_stage<B, 3, NS, NT, INV>(lds, tw, tid);
+    fft_from<B, NT, INV, NS * 3>(lds, tw, tid);
   }
 }
 
@@ -367,7 +434,7 @@ __device__ __forceinline__ void fft_from(float2* lds, const float2* tw, int tid)
 // return the result is in LDS and visible to all threads.
 template <class B, int NT, bool INV>
 __device__ __forceinline__ void fft_lds(float2* lds, const float2* tw, int tid) {
-  static_assert(fft_len_ok(B::L), "lengths 2^k or 3 * 2^k only");
+  static_assert(fft_len_ok(B::L), "lengths 2^k, 3 * 2^k or 9 * 2^k only");
   fft_from<B, NT, INV, 1>(lds, tw, tid);
 }
 

@@ -150,6 +150,13 @@ hipError_t launch_window256(float2* window, int np, const float2* twW, int f,
 // W = 256 CBED: cbed[p][ky][kx] = |Psi|^2 / W^2 (float32, fftfreq order).
 hipError_t launch_window256_cbed(float2* window, int np, const float2* twW, float* cbed,
                                  OutAcc acc, hipStream_t st);
+// Window sides of the LDS window kernels: powers of two 8..128 and the
+// 3 * 2^k / 9 * 2^k sides 24, 48, 72, 96 (multiples of 8 for the first
+// radix-8 stage, at most 96^2 values in LDS); W = 256 has its own passes.
+__host__ __device__ constexpr bool window_side_ok(int w) {
+  return w == 8 || w == 16 || w == 32 || w == 64 || w == 128 || w == 256 || w == 24 ||
+         w == 48 || w == 72 || w == 96;
+}
 // Full CBED output: cbed[p][ky][kx] = |FFT_W window_p|^2 / W^2 (float32,
 // window fftfreq order), W <= 128.
 hipError_t launch_window_cbed(const float2* window, int np, int w, const float2* twW,

@@ -503,7 +503,8 @@ int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, const doub
   if (!want_cbed)
     if (int r = make_bins(p, d, &bins)) return r;
   const int n = p->n, ns = n / 2, w = n / (2 * f);
-  if (!is_pow2(w) || w < 8 || w > 256) return fail(PRISM_EINVAL, "window side n/(2f) must be 8..256");
+  if (!prism::window_side_ok(w))
+    return fail(PRISM_EINVAL, "window side n/(2f) must be 8..256, a power of two or 24, 48, 72, 96");
   const auto* act = get_active(p, f, amax_mrad, *mn, o);
   const int n_act = (int)act->size();
   if (n_act < 1) return fail(PRISM_EINVAL, "no beam of the set lies inside the probe aperture");
@@ -654,10 +655,12 @@ const char* prism_last_error(void) { return g_err.c_str(); }
 int prism_plan_create(prism_plan** out, const prism_geometry* g) {
   if (!out || !g) return fail(PRISM_EINVAL, "null argument");
   *out = nullptr;
-  // grids 2^k or 3 * 2^k (the LDS transforms have radices 2, 4, 8 and 3)
-  const bool grid_ok = is_pow2(g->n) || (g->n % 3 == 0 && is_pow2(g->n / 3));
+  // grids 2^k, 3 * 2^k or 9 * 2^k (the LDS transforms have radices 2, 4, 8,
+  // 3 and 9)
+  const bool grid_ok = is_pow2(g->n) || (g->n % 3 == 0 && is_pow2(g->n / 3)) ||
+                       (g->n % 9 == 0 && is_pow2(g->n / 9));
   if (!grid_ok || g->n < 128 || g->n > 2048)
-    return fail(PRISM_EINVAL, "n must be 2^k or 3 * 2^k in [128, 2048]");
+    return fail(PRISM_EINVAL, "n must be 2^k, 3 * 2^k or 9 * 2^k in [128, 2048]");
   if (!(g->cell_A > 0.0) || !std::isfinite(g->cell_A)) return fail(PRISM_EINVAL, "cell must be > 0");
   if (!(g->energy_keV > 0.0) || !std::isfinite(g->energy_keV))
     return fail(PRISM_EINVAL, "energy must be > 0");
@@ -777,7 +780,8 @@ int prism_probe_workspace_bytes(const prism_plan* cp, int f, double amax_mrad,
   if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
   if (int r = check_optics(p, o)) return r;
   const int w = p->n / (2 * f);
-  if (!is_pow2(w) || w < 8 || w > 256) return fail(PRISM_EINVAL, "window side n/(2f) must be 8..256");
+  if (!prism::window_side_ok(w))
+    return fail(PRISM_EINVAL, "window side n/(2f) must be 8..256, a power of two or 24, 48, 72, 96");
   const auto* act = get_active(p, f, amax_mrad, *mn, o);
   const int G = prism::contract_group(w);
   ProbeWs pw;

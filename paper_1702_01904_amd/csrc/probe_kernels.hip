@@ -425,8 +425,9 @@ __global__ __launch_bounds__(256) void k_window_cols256_detect(const float2* __r
 #ifndef PRISM_WD128_NT
 #define PRISM_WD128_NT 1024  // threads per W = 128 window workgroup
 #endif
+// Threads per window workgroup: W^2 / 16 rounded up to whole waves.
 __host__ __device__ constexpr int wd_nt(int w) {
-  return w == 128 ? PRISM_WD128_NT : ((w * w / 16) < 64 ? 64 : w * w / 16);
+  return w == 128 ? PRISM_WD128_NT : ((w * w / 16) < 64 ? 64 : (w * w / 16 + 63) / 64 * 64);
 }
 
 // 2D FFT of each W x W window in LDS, then either I(kw) = |Psi(kw)|^2 / W^2
@@ -610,6 +611,10 @@ hipError_t launch_window_detect(const float2* window, int np, int w, const float
     WD(32)
     WD(64)
     WD(128)
+    WD(24)
+    WD(48)
+    WD(72)
+    WD(96)
     default:
       return hipErrorInvalidValue;
   }
@@ -633,6 +638,10 @@ hipError_t launch_window_cbed(const float2* window, int np, int w, const float2*
     WC(32)
     WC(64)
     WC(128)
+    WC(24)
+    WC(48)
+    WC(72)
+    WC(96)
     default:
       return hipErrorInvalidValue;
   }

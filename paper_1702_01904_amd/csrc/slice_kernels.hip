@@ -703,8 +703,10 @@ hipError_t launch_beam_init(float2* state, const int32_t* beams_mn, int b0, int 
     case 256: CALL(256); break;   \
     case 384: CALL(384); break;   \
     case 512: CALL(512); break;   \
+    case 576: CALL(576); break;   \
     case 768: CALL(768); break;   \
     case 1024: CALL(1024); break; \
+    case 1152: CALL(1152); break; \
     case 1536: CALL(1536); break; \
     case 2048: CALL(2048); break; \
     default: return hipErrorInvalidValue; \

@@ -95,13 +95,14 @@ CONFIGS = {
 # Mixed batches of specimens (many small and large specimens built
 # together). Each entry is a recipe for ``batch_workload``: grid sizes with
 # 0.1 A pixels, slice counts drawn uniformly, interpolation factors drawn
-# among those the grid admits (power-of-two windows of 8..256 pixels),
-# random atoms at 0.015 A^-3.
+# among those the grid admits (windows of 8..256 pixels that the window
+# kernels take: powers of two and 24, 48, 72, 96), random atoms at
+# 0.015 A^-3.
 BATCHES = {
-    # 32 specimens on 2^k and 3 * 2^k grids, 20-120 slices, f in
-    # {4, 6, 8, 12, 16} (4, 8, 16 on 2^k grids; 6, 12 on 3 * 2^k grids).
-    "batch32": dict(count=32, sizes=(256, 384, 512, 768, 1024, 1536), h_range=(20, 120),
-                    f_choices=(4, 6, 8, 12, 16),
+    # 32 specimens on 2^k, 3 * 2^k and 9 * 2^k grids, 20-120 slices, f in
+    # {4, 6, 8, 12, 16}.
+    "batch32": dict(count=32, sizes=(256, 384, 512, 576, 768, 1024, 1152, 1536),
+                    h_range=(20, 120), f_choices=(4, 6, 8, 12, 16),
                     pixel_A=0.1, density=0.015, slice_A=2.0, energy_keV=80.0,
                     optics=dict(alpha_mrad=20.0, C1_A=0.0, C3_A=0.0),
                     detectors=[(0.0, 20.0), (20.0, 40.0), (40.0, 100.0)],

@@ -1,6 +1,6 @@
-"""Grids with a factor 3 (n = 3 * 2^k: radix-3 LDS FFT stages in the slice
-passes, the exit extraction and the multislice probe) against the FP64
-oracle. Windows W = n / (2 f) stay powers of two (f = 3, 6, 12).
+"""Grids with a factor 3 or 9 (n = 3 * 2^k, 9 * 2^k: radix-3/9 LDS FFT
+stages in the slice passes, the exit extraction and the multislice probe)
+and windows of 24, 48, 72 and 96 pixels, against the FP64 oracle.
 
 Gate: eps_rel <= 1e-4 (FP32), <= 1e-2 (BF16), per S-matrix beam and over the
 outputs.
@@ -53,7 +53,7 @@ def test_multislice_192(t192):
     assert e <= TOL
 
 
-@pytest.mark.parametrize("f", [3, 6])
+@pytest.mark.parametrize("f", [3, 4, 6])
 def test_smatrix_and_prism_192(t192, f):
     d, plan = t192
     amax = _amax(d, f)
@@ -85,7 +85,7 @@ def test_multislice_384_sampled(m384):
     assert e <= TOL
 
 
-@pytest.mark.parametrize("f", [3, 6, 12])
+@pytest.mark.parametrize("f", [3, 4, 6, 8, 12])
 def test_prism_384(m384, f):
     d, plan = m384
     amax = _amax(d, f)
@@ -109,10 +109,12 @@ def test_prism_384(m384, f):
     assert eps(D16, ref) <= TOL16
 
 
-@pytest.mark.parametrize("n,f,H", [(768, 6, 5), (1536, 12, 3)])
+@pytest.mark.parametrize("n,f,H", [(768, 6, 5), (768, 4, 3), (1536, 12, 3), (576, 4, 3),
+                                   (576, 12, 3), (1152, 8, 3), (1152, 6, 2)])
 def test_large_3x2k_grids_sampled(n, f, H):
-    # 768^2 and 1536^2 (0.1 A pixels, random atoms): one multislice probe and
-    # PRISM probes (two at 768^2, one at 1536^2) against one-probe oracle runs
+    # 576^2 .. 1536^2 (0.1 A pixels, random atoms; windows 24 .. 96): one
+    # multislice probe and PRISM probes (two at 768^2, one elsewhere)
+    # against one-probe oracle runs
     cfg = dict(
         specimen=dict(kind="random", cell=(0.1 * n, 0.1 * n, 2.0 * H),
                       n_atoms=int(0.015 * (0.1 * n) ** 2 * 2.0 * H), z_choices=(6, 14, 29, 79)),
@@ -130,7 +132,7 @@ def test_large_3x2k_grids_sampled(n, f, H):
     amax = _amax(d, f)
     S = G.build_smatrix(plan, f, amax)
     D = G.probe_outputs(plan, f, amax, S, d["probes"], d["optics"], d["edges"])
-    for k in ((0, 9) if n == 768 else (9,)):
+    for k in ((0, 9) if (n, f) == (768, 6) else (9,)):
         x0, y0 = d["probes"][k]
         ref = O.prism_probe_direct(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f,
                                    amax, d["optics"], x0, y0, d["edges"])
