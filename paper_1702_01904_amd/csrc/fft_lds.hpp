@@ -397,7 +397,8 @@ __host__ __device__ constexpr bool fft_len_ok(int L) {
 }
 
 // Radix plan of a length-L transform split as 8 * 8^MID * RL (RL in 2, 4, 8
-// for L = 2^k; 3, 6, 12 for L = 3 * 2^k): the inverse runs 8, 8^MID, RL and
+// for L = 2^k; 3, 6, 12 for L = 3 * 2^k; 9, 18 for L = 9 * 2^k up to 1152):
+// the inverse runs 8, 8^MID, RL and
 // the forward the reverse RL, 8^MID, 8, so that the inverse's last stage
 // and the forward's first stage pair up on the same elements (j + r L/RL)
 // and can stay in registers.

@@ -32,7 +32,7 @@ namespace {
 constexpr int kRowNT = PRISM_ROW_ELEMS / 8;
 
 // Largest power of two p with p n <= cap (at least 1): rows per workgroup
-// that divide every wave's n rows (n = 2^k or 3 2^k).
+// that divide every wave's n rows (n = 2^k, 3 2^k or 9 2^k).
 __host__ __device__ constexpr int pow2_rows(int n, int cap) {
   return 2 * n <= cap ? 2 * pow2_rows(2 * n, cap) : 1;
 }
