@@ -3,13 +3,14 @@
 // The multislice step (Eq. 5) needs a forward and an inverse 2D FFT per
 // slice; the PRISM probe step (Fig. 1f) needs one small 2D FFT per probe.
 // Both are done here as batches of 1D transforms held in LDS:
-//   * Stockham auto-sort formulation, radix-8 stages followed by one
-//     radix-4 or radix-2 stage, so the output is in natural order with no
-//     bit-reversal pass;
+//   * Stockham auto-sort formulation, radix-8 stages followed by radix-4,
+//     radix-2 and (for lengths 3 * 2^k and 9 * 2^k) radix-3 stages, so the
+//     output is in natural order with no digit-reversal pass;
 //   * each stage reads every butterfly input into registers, barriers,
 //     then writes the outputs in place (one barrier pair per stage);
 //   * twiddles come from a per-length table of exp(-2 pi i k / L), rounded
-//     once from FP64, staged in LDS by the caller;
+//     once from FP64, staged in LDS by the caller (the register DFTs of 3,
+//     6, 9, 12 and 18 points use constants of cos(2 pi m / 36));
 //   * LDS addresses are padded by one complex every 16 (lpad) to spread
 //     the strided writes of early stages over the banks.
 //
