@@ -269,7 +269,10 @@ int prism_multislice_outputs_accumulate(prism_plan* plan, const double* probe_xy
  * admitted specimen and optics; prism_server_submit checks it).
  * Buffers named in admit and submit (S-matrix, positions, outputs) must stay
  * valid until the query is reported done by poll or wait (S-matrix: until
- * evicted). A server is used by one host thread at a time.
+ * evicted). The server's streams are non-blocking and wait for no other
+ * stream: a query's positions must be written (their stream synchronised)
+ * before the flush that dispatches it, and its outputs are complete only once
+ * poll or wait reports it. A server is used by one host thread at a time.
  * --------------------------------------------------------------------- */
 typedef struct prism_server prism_server;
 
