@@ -499,7 +499,7 @@ def run_serving(args, plan_fcc, d_fcc, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the library runs on one GPU (sharding over several is a design only); --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
