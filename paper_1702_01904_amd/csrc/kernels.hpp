@@ -135,12 +135,16 @@ hipError_t launch_alpha16(const double* probe_xy, int p0, int np, const ActiveBe
 hipError_t launch_contract16(const void* s16, int n_actp, const void* a16, const int2* origin,
                              int np, int ns, int w, int group, float out_scale, float2* window,
                              Prec prec, hipStream_t st);
-// Detector bins as lists of window pixels: bin j holds the pixel indices
-// pix[off[j] .. off[j+1]) (v * W + u) of the W x W window.
+// Detector bins as lists of window pixels (v * W + u of the W x W window),
+// cut into chunks of kWdListChunk entries: bin j owns the chunks
+// off[j] .. off[j+1]), i.e. pix[off[j] 64 .. off[j+1] 64), its last chunk
+// padded with kNoPix.
 struct BinLists {
   int n;
   int off[kMaxDet + 1];
 };
+constexpr int kWdListChunk = 64;  // one entry per lane of a wave
+constexpr uint16_t kNoPix = 0xFFFF;
 // W = 256: window FFT in two passes (rows in place, then columns fused with
 // |Psi|^2 / W^2 and bin sums) into partial[probe][tile][n_det], tiles =
 // window256_tiles(); reduce with launch_reduce_partials.

@@ -293,7 +293,8 @@ const std::vector<prism::ActiveBeam>* get_active(prism_plan* p, int f, double am
 }
 
 // Per-bin pixel lists of the W x W PRISM window: pixel (v, u) has full-grid
-// frequency f * (kx, ky) with (kx, ky) the window's fftfreq indices.
+// frequency f * (kx, ky) with (kx, ky) the window's fftfreq indices. Each
+// bin's list is padded to whole chunks of kWdListChunk entries.
 const prism_plan::PixLists* get_pixlists(prism_plan* p, int w, int f, const prism::DetBins& b) {
   std::string key = std::to_string(w) + ":" + std::to_string(f);
   for (int j = 0; j < b.n; ++j) key += ":" + std::to_string(b.lo[j]) + "-" + std::to_string(b.hi[j]);
@@ -302,8 +303,9 @@ const prism_plan::PixLists* get_pixlists(prism_plan* p, int w, int f, const pris
   prism_plan::PixLists pl;
   std::memset(&pl.lists, 0, sizeof pl.lists);
   pl.lists.n = b.n;
+  const size_t chunk = prism::kWdListChunk;
   for (int j = 0; j < b.n; ++j) {
-    pl.lists.off[j] = (int)pl.pix.size();
+    pl.lists.off[j] = (int)(pl.pix.size() / chunk);
     for (int v = 0; v < w; ++v) {
       const long long ky = v < w / 2 ? v : v - w;
       for (int u = 0; u < w; ++u) {
@@ -312,8 +314,9 @@ const prism_plan::PixLists* get_pixlists(prism_plan* p, int w, int f, const pris
         if (k2 >= b.lo[j] && k2 < b.hi[j]) pl.pix.push_back((uint16_t)(v * w + u));
       }
     }
+    pl.pix.resize((pl.pix.size() + chunk - 1) / chunk * chunk, prism::kNoPix);
   }
-  pl.lists.off[b.n] = (int)pl.pix.size();
+  pl.lists.off[b.n] = (int)(pl.pix.size() / chunk);
   return &(p->pixlists[key] = std::move(pl));
 }
 
@@ -403,8 +406,10 @@ int padded_beams(int n_act, prism::Prec pk) {
 size_t probe_layout(int w, int ns, int n_act, int chunk, int prec, ProbeWs* pw, void* base) {
   Carve c(base);
   pw->twW = c.take<float2>(w);
-  // per-bin pixel lists (W <= 128), worst case: overlapping bins
-  pw->pix = c.take<uint16_t>(w == 256 ? 0 : (size_t)PRISM_MAX_DET * w * w);
+  // per-bin pixel lists (W <= 128), worst case: every bin holds every pixel
+  // and a padded last chunk
+  pw->pix = c.take<uint16_t>(
+      w == 256 ? 0 : (size_t)PRISM_MAX_DET * ((size_t)w * w + prism::kWdListChunk));
   pw->act = c.take<prism::ActiveBeam>(n_act);
   if (!packed_path(prec)) {
     pw->alpha = c.take<float2>((size_t)chunk * n_act);

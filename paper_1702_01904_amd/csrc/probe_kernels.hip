@@ -425,6 +425,8 @@ __global__ __launch_bounds__(256) void k_window_cols256_detect(const float2* __r
 #ifndef PRISM_WD128_NT
 #define PRISM_WD128_NT 1024  // threads per W = 128 window workgroup
 #endif
+constexpr int kWdChunks = 16;  // bin-list chunks whose pixel indices load together
+
 // Threads per window workgroup: W^2 / 16 rounded up to whole waves.
 __host__ __device__ constexpr int wd_nt(int w) {
   return w == 128 ? PRISM_WD128_NT : ((w * w / 16) < 64 ? 64 : (w * w / 16 + 63) / 64 * 64);
@@ -437,6 +439,16 @@ __host__ __device__ constexpr int wd_nt(int w) {
 // next probe is loaded into registers while the current one is transformed
 // (one window fills most of a compute unit's LDS, so this overlap is the
 // only one there is).
+//
+// Bin sums: the lists are cut into chunks of kWdListChunk = 64 entries (one
+// per lane, kNoPix padding at the end of each bin); chunk k belongs to the
+// bin j with off[j] <= k < off[j + 1]. Wave w takes the contiguous chunks
+// [K w / NW, K (w + 1) / NW) of the K in all, so it meets only a few bins:
+// each lane sums its entry of the wave's chunks of a bin in order, one wave
+// sum per bin met goes to red[j][w] (zero for the bins a wave does not
+// meet), and the bin total adds red[j][0 .. NW) in order. The pixel indices
+// of kWdChunks chunks are loaded together, so the load latency is paid once
+// per group of chunks.
 template <int W, bool CBED>
 __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __restrict__ window,
                                                             int np,
@@ -453,7 +465,7 @@ __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __rest
   using S8 = StageShape<Rows, 8, NT>;
   __shared__ float2 lds[lds_padded(W * W)];
   __shared__ float2 tw[W];
-  __shared__ double red[8][NW];
+  __shared__ double red[CBED ? 1 : kMaxDet][NW];
   const int tid = threadIdx.x;
   load_twiddles<W, NT>(tw, twW, tid);
   float2 nxt[S8::PER][8];
@@ -493,31 +505,45 @@ __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __rest
         put_out(dst + e, ((double)z.x * z.x + (double)z.y * z.y) * inv_w2, oa);
       }
     } else {
-      for (int j0 = 0; j0 < lists.n; j0 += 8) {
-        double acc[8];
+      const int K = lists.off[lists.n];  // chunks of kWdListChunk entries
+      const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+      for (int i = tid; i < lists.n * NW; i += NT) red[i / NW][i % NW] = 0.0;
+      __syncthreads();
+      const int c0 = (int)((long long)K * wv / NW), c1 = (int)((long long)K * (wv + 1) / NW);
+      int j = 0;  // bin of the current chunk (uniform in the wave)
+      while (j < lists.n && c0 >= lists.off[j + 1]) ++j;
+      double acc = 0.0;
+      for (int k0 = c0; k0 < c1; k0 += kWdChunks) {
+        int px[kWdChunks];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          acc[q] = 0.0;
-          const int j = j0 + q;
-          if (j < lists.n) {
-            for (int i = lists.off[j] + tid; i < lists.off[j + 1]; i += NT) {
-              const float2 z = lds[lpad(pix[i])];
-              acc[q] += (double)z.x * z.x + (double)z.y * z.y;
-            }
+        for (int c = 0; c < kWdChunks; ++c)
+          px[c] = k0 + c < c1 ? (int)pix[(size_t)(k0 + c) * kWdListChunk + lane] : (int)kNoPix;
+#pragma unroll
+        for (int c = 0; c < kWdChunks; ++c) {
+          const int k = k0 + c;
+          if (k >= c1) break;
+          if (k >= lists.off[j + 1]) {  // bin j ends: its wave sum, then the bin of chunk k
+            const double sm = wave_sum(acc);
+            if (lane == 0) red[j][wv] = sm;
+            acc = 0.0;
+            do ++j;
+            while (k >= lists.off[j + 1]);
           }
+          const bool ok = px[c] != (int)kNoPix;
+          const float2 z = lds[lpad(ok ? px[c] : 0)];
+          const double I = (double)z.x * z.x + (double)z.y * z.y;
+          acc += ok ? I : 0.0;
         }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const double sm = wave_sum(acc[q]);
-          if ((tid & 63) == 0) red[q][tid >> 6] = sm;
-        }
-        __syncthreads();
-        if (tid < 8 && j0 + tid < lists.n) {
-          double sm = 0.0;
-          for (int wv = 0; wv < NW; ++wv) sm += red[tid][wv];
-          put_out(out + (size_t)p * lists.n + j0 + tid, sm * inv_w2, oa);
-        }
-        __syncthreads();
+      }
+      if (c1 > c0) {
+        const double sm = wave_sum(acc);
+        if (lane == 0) red[j][wv] = sm;
+      }
+      __syncthreads();
+      if (tid < lists.n) {
+        double sm = 0.0;
+        for (int w = 0; w < NW; ++w) sm += red[tid][w];
+        put_out(out + (size_t)p * lists.n + tid, sm * inv_w2, oa);
       }
     }
     __syncthreads();  // LDS free for the next probe

@@ -577,7 +577,7 @@ def test_fcc1024_empty_cell_prism_closed_form():
 
 
 def test_max_bins_and_probes_outside_the_cell():
-    # 32 detector bins (the limit; eight per pass in the window kernels) and
+    # 32 detector bins (the limit) and
     # probe positions outside [0, d) (the window centre wraps, the phase
     # e^{-2 pi i q.r0} does not care): PRISM f = 1, 2 (W = 64, 32) and
     # multislice on the tiny case, W = 256 on s512 against multislice (PRISM
@@ -617,3 +617,33 @@ def test_max_bins_and_probes_outside_the_cell():
     e = eps(D, ref)
     print(f"32 bins, outside probes: s512 prism f=1 (W=256) eps_rel={e:.3e}")
     assert e <= TOL
+
+
+def test_overlapping_and_empty_bins():
+    # Detector bins that overlap, nest, repeat one another or hold no pixel
+    # (outside the window's angles, or inner == outer): each bin is summed on
+    # its own, as the oracle does. PRISM f = 1, 2 (W = 64, 32: the bin-list
+    # window kernels) and multislice.
+    d = build_inputs("tiny", 3)
+    plan = G.make_plan(d)
+    edges = np.array([(0.0, 200.0), (10.0, 30.0), (20.0, 40.0), (20.0, 40.0), (300.0, 400.0),
+                      (50.0, 50.0), (0.0, 3.0), (35.0, 90.0)])
+    pr = np.array([[1.1, 2.2], [6.4, 9.9], [11.0, 0.3]])
+    Dm = G.multislice_outputs(plan, pr, d["optics"], edges)
+    ref_m = O.multislice_stem(d["phase"], d["thickness"], d["cell"], d["energy_keV"], d["optics"],
+                              pr, edges)
+    e = eps(Dm, ref_m)
+    print(f"overlapping / empty bins: multislice eps_rel={e:.3e}")
+    assert e <= TOL
+    for f in (1, 2):
+        amax = _amax(d, f)
+        S = G.build_smatrix(plan, f, amax)
+        D = G.probe_outputs(plan, f, amax, S, pr, d["optics"], edges)
+        beams, Sref = O.smatrix(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax)
+        ref = O.prism_outputs(Sref, beams, f, d["cell"], d["energy_keV"], d["optics"], pr, edges)
+        e = eps(D, ref)
+        print(f"overlapping / empty bins: prism f={f} eps_rel={e:.3e}")
+        assert e <= TOL
+        assert np.all(D[:, 4] == 0.0) and np.all(D[:, 5] == 0.0)
+        assert np.array_equal(D[:, 2], D[:, 3])
+        assert np.all(D[:, 6] > 0.0)  # the zero-frequency pixel alone
