@@ -38,10 +38,10 @@ CONFIG = "fcc1024"
 # workload (f = 4), calibrated with a 256 MiB device copy (fetch x2.0,
 # write x1.0); see profiles/fcc1024_prism_f4_hbm_traffic.md. Valid only for
 # the kernel sources with this hash; reported as null otherwise.
-TRAFFIC_SRC_SHA = "9241401b9cea4859"
-TRAFFIC_BYTES = {"row_pass": 531727865, "col_pass": 522053798, "contract": 1380602623,
-                 "s32_pack": 1310725472, "window_detect": 270024866, "contract16": 815805266,
-                 "s16_pack": 975189599}
+TRAFFIC_SRC_SHA = "160a8372ae1770de"
+TRAFFIC_BYTES = {"row_pass": 531764974, "col_pass": 522055905, "contract": 1384671618,
+                 "s32_pack": 1310726093, "window_detect": 269994175, "contract16": 815190998,
+                 "s16_pack": 975187084}
 
 
 # Sources that decide the profiled kernels and their launch shapes (the
