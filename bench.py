@@ -20,6 +20,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -37,8 +38,9 @@ CONFIG = "fcc1024"
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE on this
 # workload (f = 4), calibrated with a 256 MiB device copy (fetch x2.0,
 # write x1.0); see profiles/fcc1024_prism_f4_hbm_traffic.md. Valid only for
-# the kernel sources with this hash; reported as null otherwise.
-TRAFFIC_SRC_SHA = "160a8372ae1770de"
+# the kernel sources with this hash (of their code, comments aside); reported
+# as null otherwise.
+TRAFFIC_SRC_SHA = "f087492bed298b3f"
 TRAFFIC_BYTES = {"row_pass": 531764974, "col_pass": 522055905, "contract": 1384671618,
                  "s32_pack": 1310726093, "window_detect": 269994175, "contract16": 815190998,
                  "s16_pack": 975187084}
@@ -50,10 +52,20 @@ KERNEL_SOURCES = ("slice_kernels.hip", "probe_kernels.hip", "probe16_kernels.hip
                   "fft_reg.hpp", "kernels.hpp", "plan.cpp")
 
 
+_TOKENS = re.compile(r'("(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\')|//[^\n]*|/\*.*?\*/', re.S)
+
+
+def _code_only(text):
+    """C++ source without comments, trailing blanks and empty lines (string
+    and character literals kept), so that comment edits keep the hash."""
+    text = _TOKENS.sub(lambda m: m.group(1) or "", text)
+    return "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
+
+
 def kernel_source_sha():
     import hashlib
     src = os.path.join(ROOT, "paper_1702_01904_amd", "csrc")
-    return hashlib.sha256("".join(open(os.path.join(src, f)).read()
+    return hashlib.sha256("".join(_code_only(open(os.path.join(src, f)).read())
                                   for f in KERNEL_SOURCES).encode()).hexdigest()[:16]
 
 

@@ -435,10 +435,11 @@ __host__ __device__ constexpr int wd_nt(int w) {
 // 2D FFT of each W x W window in LDS, then either I(kw) = |Psi(kw)|^2 / W^2
 // summed over each bin's pixel list in FP64 (the lists encode the angle test
 // at full-grid frequency f kw), or (CBED) I written out in full. Workgroups
-// walk probes p = blockIdx.x, + gridDim.x, ...: the first row stage of the
-// next probe is loaded into registers while the current one is transformed
-// (one window fills most of a compute unit's LDS, so this overlap is the
-// only one there is).
+// walk probes p = blockIdx.x, + gridDim.x, ... (one probe each unless there
+// are more than PRISM_WD_GRID); with PRISM_WD_PREFETCH the first row stage
+// of the next probe is loaded into registers while the current one is
+// transformed (one window fills most of a compute unit's LDS, so this is the
+// only overlap there is within a workgroup).
 //
 // Bin sums: the lists are cut into chunks of kWdListChunk = 64 entries (one
 // per lane, kNoPix padding at the end of each bin); chunk k belongs to the
