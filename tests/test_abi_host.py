@@ -384,3 +384,17 @@ def test_probe_order():
     assert L.prism_probe_order(p._h, 3, None, 0, None) == _native.PRISM_EINVAL   # 1024 % 6
     assert L.prism_probe_order(p._h, 4, None, 5, None) == _native.PRISM_EINVAL
     assert L.prism_probe_order(p._h, 4, None, -1, None) == _native.PRISM_EINVAL
+
+
+def test_traffic_hash_ignores_comments_only():
+    # bench.py reports stored HBM traffic only while the kernel sources hash
+    # to the value the counters were taken at; comments do not count, code
+    # (string literals included) does
+    import bench
+    a = 'int a = 1;  // "x"\n/* block\n comment */\nconst char* s = "//kept /* too */";\n'
+    b = 'int a = 1;\n\n   \nconst char* s = "//kept /* too */";   \n'
+    c = 'int a = 2;\nconst char* s = "//kept /* too */";\n'
+    assert bench._code_only(a) == bench._code_only(b)
+    assert bench._code_only(a) != bench._code_only(c)
+    assert '"//kept /* too */"' in bench._code_only(a)
+    assert len(bench.kernel_source_sha()) == 16
