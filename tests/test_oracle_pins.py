@@ -581,3 +581,26 @@ def test_error_metrics():
     assert abs(O.rel_l2(2 * a, a) - 1.0) < 1e-15
     assert abs(O.one_minus_r2(a, 3 * a + 1)) < 1e-15
     assert O.one_minus_r2(a, a[::-1]) == pytest.approx(0.0, abs=1e-15)
+
+
+# ---------------------------------------------------------------- detectors
+
+def test_detector_bins_are_half_open_and_additive():
+    # A detector bin [inner, outer) counts every pixel whose scattering angle
+    # lies in it (the annular detectors of the probe-output step): adjacent
+    # bins add up to their union, a bin reaching past every angle holds the
+    # whole pattern, inner == outer holds nothing, overlapping bins are summed
+    # independently, and a pixel exactly on an edge goes to the upper bin.
+    rng = np.random.default_rng(7)
+    inten = rng.random((3, 9, 9))
+    theta = np.abs(rng.normal(0.0, 0.05, (9, 9)))
+    theta[4, 4] = 0.02  # exactly on the 20 mrad edge
+    D = O.detector_sums(inten, theta, [(0, 20), (20, 60), (0, 60), (10, 30), (30, 30),
+                                       (0, 1e9), (20, 20.000001)])
+    assert np.allclose(D[:, 0] + D[:, 1], D[:, 2], rtol=1e-13, atol=0)
+    assert np.allclose(D[:, 5], inten.sum(axis=(1, 2)), rtol=1e-13, atol=0)
+    assert np.all(D[:, 4] == 0.0)
+    brute = [sum(inten[p, i, j] for i in range(9) for j in range(9) if 0.01 <= theta[i, j] < 0.03)
+             for p in range(3)]
+    assert np.allclose(D[:, 3], brute, rtol=1e-13, atol=0)
+    assert np.allclose(D[:, 6], inten[:, 4, 4], rtol=0, atol=0)
