@@ -604,3 +604,15 @@ def test_detector_bins_are_half_open_and_additive():
              for p in range(3)]
     assert np.allclose(D[:, 3], brute, rtol=1e-13, atol=0)
     assert np.allclose(D[:, 6], inten[:, 4, 4], rtol=0, atol=0)
+
+
+def test_window_bounds_worked_cases():
+    # Eq. RegionBounds on an n_S = 16 grid with 0.5 A S-pixels and W = 4: the
+    # centre pixel is the nearest S-pixel (halves round up), the window runs
+    # from centre - W/2 for W pixels, and both wrap with the cell
+    cases = [(0.0, [14, 15, 0, 1]), (0.74, [15, 0, 1, 2]), (0.75, [0, 1, 2, 3]),
+             (-0.3, [13, 14, 15, 0]), (7.8, [14, 15, 0, 1]), (8.0 + 0.74, [15, 0, 1, 2])]
+    for x0, want in cases:
+        assert list(O.window_indices(x0, 16, 4, 0.5)) == want, x0
+    # a 3 * 2^k width: W = 24 on n_S = 48
+    assert list(O.window_indices(0.0, 48, 24, 1.0)) == list(range(36, 48)) + list(range(0, 12))
