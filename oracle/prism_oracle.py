@@ -363,7 +363,7 @@ def prism_probe_wave(S, beams, f, cell, lam, optics, x0, y0, height=0.0):
     act = np.nonzero(A)[0]                       # beams with alpha = 0 are skipped
     rows = window_indices(y0, ns, w, dxs)
     cols = window_indices(x0, ns, w, dxs)
-    win = S[act][:, rows][:, :, cols]
+    win = S[np.ix_(act, rows, cols)]
     coef = alpha[act] / (w * math.sqrt(BA))
     return np.tensordot(coef, win, axes=(0, 0))
 
