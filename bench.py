@@ -263,9 +263,7 @@ def run_precision_np2048(args, dev):
         gbs = B * len(d["thickness"]) * 16.0 * n * n / (bms * 1e-3) / 1e9
         ent = {"beams": B, "window": n // (2 * f), "build_ms": round(bms, 3),
                "build_hbm_GBps": round(gbs, 1), "build_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
-        lam = p.wavelength
-        ba = int(np.sum(lam * np.hypot(*(p.beams(f, amax) * f).T) / d["cell"]
-                        <= d["optics"]["alpha_mrad"] * 1e-3))
+        ba = p.active_beam_count(f, amax, d["optics"])
         flops = 8.0 * ba * (n // (2 * f)) ** 2 * P     # useful window-sum flops per probe step
         del wsb
         outs = {}
@@ -548,9 +546,7 @@ def main():
         perm = tile_order(256, 256, tx, ty)
         xy = torch.from_numpy(d["probes"][perm]).to(dev)
         out = torch.empty((P, n_det), dtype=torch.float64, device=dev)
-        lam = plan.wavelength
-        ba = int(np.sum(lam * np.hypot(*(plan.beams(f, amax) * f).T) / d["cell"]
-                        <= optics["alpha_mrad"] * 1e-3))
+        ba = plan.active_beam_count(f, amax, optics)
         return dict(f=f, amax=amax, B=B, BA=ba, S=S, wsb=wsb, wsp=wsp, perm=perm, xy=xy, out=out)
 
     def step(c):

@@ -19,6 +19,15 @@
  *     checks run on the host before anything is enqueued. prism_last_error()
  *     returns a thread-local message for the last failing call.
  *   - Complex values are interleaved float pairs (re, im) ("c64").
+ *   - Every call that takes an S-matrix pointer also takes the byte size of
+ *     the caller's buffer and rejects one smaller than prism_smatrix_bytes
+ *     for its f and alpha_max (PRISM_EINVAL), so no kernel can read or write
+ *     past it.
+ *   - The anti-aliasing aperture is the paper's half of the maximum
+ *     frequency (compact S-matrix paragraph of "The PRISM Algorithm"):
+ *     kx^2 + ky^2 < (n/4)^2. It is not a parameter: the quarter-size
+ *     S-matrix and the window side W = n / (2 f) follow from it, and a
+ *     wider band would no longer fit the n/2 x n/2 storage.
  *
  * Limits of this implementation: n is 2^k, 3 * 2^k or 9 * 2^k in
  * [128, 2048] (128, 192, 256, 384, 512, 576, 768, 1024, 1152, 1536, 2048);
@@ -90,15 +99,30 @@ void prism_plan_destroy(prism_plan* plan);
 /* Relativistic electron wavelength (Angstrom) used by the plan. */
 int prism_wavelength(const prism_plan* plan, double* lambda_A);
 
+/* The paper's choice of the beam-set limit ("The PRISM Algorithm", the
+ * paragraph on alpha_max): the largest probe semi-angle plus one
+ * interpolated beam spacing, alpha_max = alpha + f lambda dq (mrad), so
+ * that the set covers the aperture with a margin of one beam.
+ * Errors: PRISM_EINVAL for a null pointer, f < 1, n % (2 f) != 0, or alpha
+ * not positive and finite. */
+int prism_alpha_max(const prism_plan* plan, int f, double alpha_mrad, double* alpha_max_mrad);
+
 /* PRISM beam set (the plane-wave initial conditions): integer pairs (m, n)
  * with sqrt(m^2+n^2) f lambda dq <= alpha_max and (m f)^2 + (n f)^2 <
  * (n/4)^2 so that each survives the half-band anti-aliasing aperture, in
- * lexicographic (m, n) order. alpha_max_mrad must be positive; the paper's
- * rule alpha_max = alpha + f lambda dq (choice of alpha_max paragraph) is
- * the caller's to apply. Requires n % (2 f) == 0. */
+ * lexicographic (m, n) order. alpha_max_mrad must be positive (the paper's
+ * rule: prism_alpha_max). Requires n % (2 f) == 0. */
 int prism_beam_count(const prism_plan* plan, int f, double alpha_max_mrad, int* n_beams);
 /* Writes min(count, capacity) pairs to mn (host [capacity][2]). */
 int prism_beams(const prism_plan* plan, int f, double alpha_max_mrad, int32_t* mn, int capacity);
+
+/* Number B_A of beams of the set inside the probe aperture (the beams whose
+ * coefficient is non-zero; the probe step sums only these, as the paper's
+ * discussion of skipping zero coefficients allows). Aperture test as in
+ * prism_optics. Errors: those of prism_beam_count and the optics checks of
+ * the probe step. */
+int prism_active_beam_count(const prism_plan* plan, int f, double alpha_max_mrad,
+                            const prism_optics* optics, int* n_active);
 
 /* Bytes of the compact S-matrix: c64 [B][n/2][n/2] (quarter-size storage
  * enabled by the half-angle anti-aliasing aperture). */
@@ -152,15 +176,17 @@ int prism_set_potential_slices(prism_plan* plan, const float* phase_dev);
 
 /* Fig. 1c: multislice every beam of the set through all slices (Eq. 5 with
  * the half-band aperture in the propagator) and store each exit wave at
- * quarter size: smatrix_dev c64 [B][n/2][n/2], S(i', j') = psi_exit(2i', 2j').
+ * quarter size: smatrix_dev c64 [B][n/2][n/2], S(i', j') = psi_exit(2i', 2j'),
+ * smatrix_bytes the size of that buffer (at least prism_smatrix_bytes).
  * ws/ws_bytes: device workspace, at least the build minimum. */
 int prism_build_smatrix(prism_plan* plan, int f, double alpha_max_mrad, void* smatrix_dev,
-                        void* ws, size_t ws_bytes, void* stream);
+                        size_t smatrix_bytes, void* ws, size_t ws_bytes, void* stream);
 
 /* Batched S-matrix build (Fig. 1c for several specimens at once). Each item
  * names a plan (its geometry and potential slices, set as for
  * prism_build_smatrix), an interpolation factor, an alpha_max and the
- * item's output S-matrix (c64 [B][n/2][n/2], sized by prism_smatrix_bytes).
+ * item's output S-matrix (c64 [B][n/2][n/2]) with the byte size of its
+ * buffer (at least prism_smatrix_bytes).
  * Items whose plans share the grid, cell, energy and the thicknesses of their
  * common slices form one group: the waves of all their beams run through the
  * same launches, slice by slice, each wave multiplying by its own specimen's
@@ -180,6 +206,7 @@ typedef struct {
   int f;
   double alpha_max_mrad;
   void* smatrix_dev;
+  size_t smatrix_bytes;
 } prism_build_item;
 
 int prism_build_batch_workspace_bytes(const prism_build_item* items, int count,
@@ -192,15 +219,16 @@ int prism_build_smatrix_batch(const prism_build_item* items, int count, void* ws
  * alpha_{m,n}(r0) = A e^{-i chi} e^{-2 pi i q.r0} / (W sqrt(B_A)), over the
  * W x W window of Eq. RegionBounds (centre pixel floor(x0/dx_S + 1/2),
  * periodic wrap), Fourier transform, and integrate |Psi|^2 / W^2 over each
- * detector bin: out_dev float64 [P][n_det]. The S-matrix must come from
- * prism_build_smatrix with the same f and alpha_max_mrad, and the probe
+ * detector bin: out_dev float64 [P][n_det]. The S-matrix (smatrix_bytes: the
+ * size of its buffer) must come from prism_build_smatrix with the same f and
+ * alpha_max_mrad, and the probe
  * semi-angle plus the tilt magnitude may not exceed alpha_max_mrad
  * (PRISM_EINVAL): every beam inside the aperture must be in the set. Several optics (defocus, C3, semi-angle)
  * can be evaluated on one resident S-matrix. */
 int prism_probe_outputs(prism_plan* plan, int f, double alpha_max_mrad, const void* smatrix_dev,
-                        const double* probe_xy_dev, int n_probes, const prism_optics* optics,
-                        const prism_detector* detector, double* out_dev, void* ws,
-                        size_t ws_bytes, void* stream);
+                        size_t smatrix_bytes, const double* probe_xy_dev, int n_probes,
+                        const prism_optics* optics, const prism_detector* detector,
+                        double* out_dev, void* ws, size_t ws_bytes, void* stream);
 
 /* The same probe step with the full diffraction pattern as output (Fig. 1f:
  * the CBED alternative to virtual detectors): cbed_dev float32 [P][W][W],
@@ -208,8 +236,9 @@ int prism_probe_outputs(prism_plan* plan, int f, double alpha_max_mrad, const vo
  * frequency kw sits at full-grid frequency f kw). Workspace, precision and
  * errors as prism_probe_outputs; PRISM_EINVAL for a null cbed_dev. */
 int prism_probe_cbed(prism_plan* plan, int f, double alpha_max_mrad, const void* smatrix_dev,
-                     const double* probe_xy_dev, int n_probes, const prism_optics* optics,
-                     float* cbed_dev, void* ws, size_t ws_bytes, void* stream);
+                     size_t smatrix_bytes, const double* probe_xy_dev, int n_probes,
+                     const prism_optics* optics, float* cbed_dev, void* ws, size_t ws_bytes,
+                     void* stream);
 
 /* Conventional multislice STEM (Eq. 5 run once per probe): incident probe
  * iFFT[A e^{-i chi} e^{-2 pi i q.r0}] n / sqrt(N_A) (tilt as in prism_optics),
@@ -236,13 +265,15 @@ int prism_multislice_outputs(prism_plan* plan, const double* probe_xy_dev, int n
  * not finite. Calls that accumulate into the same output must be ordered
  * (same stream or events). */
 int prism_probe_outputs_accumulate(prism_plan* plan, int f, double alpha_max_mrad,
-                                   const void* smatrix_dev, const double* probe_xy_dev,
-                                   int n_probes, const prism_optics* optics,
+                                   const void* smatrix_dev, size_t smatrix_bytes,
+                                   const double* probe_xy_dev, int n_probes,
+                                   const prism_optics* optics,
                                    const prism_detector* detector, double weight,
                                    double* out_dev, void* ws, size_t ws_bytes, void* stream);
 int prism_probe_cbed_accumulate(prism_plan* plan, int f, double alpha_max_mrad,
-                                const void* smatrix_dev, const double* probe_xy_dev,
-                                int n_probes, const prism_optics* optics, double weight,
+                                const void* smatrix_dev, size_t smatrix_bytes,
+                                const double* probe_xy_dev, int n_probes,
+                                const prism_optics* optics, double weight,
                                 float* cbed_dev, void* ws, size_t ws_bytes, void* stream);
 int prism_multislice_outputs_accumulate(prism_plan* plan, const double* probe_xy_dev,
                                         int n_probes, const prism_optics* optics,
@@ -286,12 +317,17 @@ int prism_server_create(prism_server** server, size_t smatrix_budget_bytes, int 
  * caller's device buffers). */
 void prism_server_destroy(prism_server* server);
 /* Admit one specimen's S-matrix (prism_smatrix_bytes of it must fit in the
- * remaining budget, else PRISM_ENOSPACE). With build_ws != NULL the server
- * builds it (prism_build_smatrix on one of its streams; the plan's
- * potential slices must be set); with build_ws == NULL smatrix_dev must
+ * remaining budget, else PRISM_ENOSPACE; smatrix_bytes is the size of the
+ * caller's buffer, PRISM_EINVAL if smaller). With build_ws != NULL the
+ * server builds it with prism_build_smatrix on its first stream, where
+ * every admit's build runs, so builds are ordered among themselves and may
+ * share one build workspace; the plan's potential slices must be set and
+ * written (their stream synchronised) before the call, since the server's
+ * streams wait for no other stream. With build_ws == NULL smatrix_dev must
  * already hold it (built by the caller and synchronised). *id names it. */
 int prism_server_admit(prism_server* server, prism_plan* plan, int f, double alpha_max_mrad,
-                       void* smatrix_dev, void* build_ws, size_t build_ws_bytes, int* id);
+                       void* smatrix_dev, size_t smatrix_bytes, void* build_ws,
+                       size_t build_ws_bytes, int* id);
 /* Release a specimen's budget after its dispatched queries have finished
  * (waits for the server's streams). PRISM_EINVAL if queries are queued. */
 int prism_server_evict(prism_server* server, int id);

@@ -20,6 +20,10 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _nbytes(t):
+    return ctypes.c_size_t(t.numel() * t.element_size())
+
+
 def _stream_ptr(stream):
     if stream is None:
         import torch
@@ -91,8 +95,18 @@ class Plan:
         return v.value
 
     def alpha_max_default(self, alpha_mrad, f):
-        """alpha + f lambda dq in mrad (choice of alpha_max in the paper)."""
-        return float(alpha_mrad) + f * (self.wavelength * (1.0 / self.cell)) * 1e3
+        """The paper's beam-set limit for probe semi-angle alpha (prism_alpha_max), mrad."""
+        v = ctypes.c_double()
+        _native.check(self._L.prism_alpha_max(self._h, int(f), float(alpha_mrad), ctypes.byref(v)))
+        return v.value
+
+    def active_beam_count(self, f, alpha_max_mrad, optics):
+        """B_A: beams of the set inside the probe aperture (prism_active_beam_count)."""
+        v = ctypes.c_int()
+        o = _optics(optics)
+        _native.check(self._L.prism_active_beam_count(self._h, int(f), float(alpha_max_mrad),
+                                                      ctypes.byref(o), ctypes.byref(v)))
+        return v.value
 
     def beam_count(self, f, alpha_max_mrad):
         v = ctypes.c_int()
@@ -188,7 +202,7 @@ class Plan:
         _check_dev(smatrix, torch.complex64, B * (self.n // 2) ** 2, "smatrix")
         _check_dev(workspace, torch.uint8, None, "workspace")
         _native.check(self._L.prism_build_smatrix(self._h, int(f), float(alpha_max_mrad),
-                                                  _ptr(smatrix), _ptr(workspace),
+                                                  _ptr(smatrix), _nbytes(smatrix), _ptr(workspace),
                                                   workspace.numel(), _stream_ptr(stream)))
 
     def probe_outputs(self, f, alpha_max_mrad, smatrix, probe_xy, optics, edges_mrad, out,
@@ -213,8 +227,8 @@ class Plan:
         _check_dev(smatrix, torch.complex64, None, "smatrix")
         _check_dev(workspace, torch.uint8, None, "workspace")
         o = _optics(optics)
-        head = (self._h, int(f), float(alpha_max_mrad), _ptr(smatrix), _ptr(probe_xy), int(P),
-                ctypes.byref(o), ctypes.byref(det.struct))
+        head = (self._h, int(f), float(alpha_max_mrad), _ptr(smatrix), _nbytes(smatrix),
+                _ptr(probe_xy), int(P), ctypes.byref(o), ctypes.byref(det.struct))
         tail = (_ptr(out), _ptr(workspace), workspace.numel(), _stream_ptr(stream))
         if weight is None:
             _native.check(self._L.prism_probe_outputs(*head, *tail))
@@ -241,8 +255,8 @@ class Plan:
         _check_dev(smatrix, torch.complex64, None, "smatrix")
         _check_dev(workspace, torch.uint8, None, "workspace")
         o = _optics(optics)
-        head = (self._h, int(f), float(alpha_max_mrad), _ptr(smatrix), _ptr(probe_xy), int(P),
-                ctypes.byref(o))
+        head = (self._h, int(f), float(alpha_max_mrad), _ptr(smatrix), _nbytes(smatrix),
+                _ptr(probe_xy), int(P), ctypes.byref(o))
         tail = (_ptr(out), _ptr(workspace), workspace.numel(), _stream_ptr(stream))
         if weight is None:
             _native.check(self._L.prism_probe_cbed(*head, *tail))
@@ -283,7 +297,8 @@ def _batch_items(items, with_outputs):
             import torch
             B = plan.beam_count(f, amax)
             _check_dev(S, torch.complex64, B * (plan.n // 2) ** 2, f"smatrix of item {k}")
-        arr[k] = _native.PrismBuildItem(plan._h, f, amax, _ptr(S) if S is not None else None)
+        arr[k] = _native.PrismBuildItem(plan._h, f, amax, _ptr(S) if S is not None else None,
+                                        _nbytes(S) if S is not None else 0)
     return arr
 
 
@@ -360,7 +375,8 @@ class Server:
             _check_dev(build_workspace, torch.uint8, None, "build_workspace")
             wp, wn = _ptr(build_workspace), build_workspace.numel()
         _native.check(self._L.prism_server_admit(self._h, plan._h, int(f), float(alpha_max_mrad),
-                                                 _ptr(smatrix), wp, wn, ctypes.byref(i)))
+                                                 _ptr(smatrix), _nbytes(smatrix), wp, wn,
+                                                 ctypes.byref(i)))
         self._spec[i.value] = (plan, smatrix, build_workspace)
         return i.value
 

@@ -20,8 +20,8 @@ PRISM_PREC_BF16 = 1
 PRISM_PREC_FP16 = 2
 
 EXPORTS = (
-    "prism_plan_create", "prism_plan_destroy", "prism_wavelength", "prism_beam_count",
-    "prism_beams", "prism_smatrix_bytes", "prism_build_workspace_bytes",
+    "prism_plan_create", "prism_plan_destroy", "prism_wavelength", "prism_alpha_max",
+    "prism_beam_count", "prism_beams", "prism_active_beam_count", "prism_smatrix_bytes", "prism_build_workspace_bytes",
     "prism_multislice_workspace_bytes", "prism_probe_workspace_bytes", "prism_probe_group",
     "prism_probe_order",
     "prism_set_probe_precision", "prism_set_potential_slices", "prism_build_smatrix",
@@ -53,7 +53,8 @@ class PrismDetector(ctypes.Structure):
 
 class PrismBuildItem(ctypes.Structure):
     _fields_ = [("plan", ctypes.c_void_p), ("f", ctypes.c_int),
-                ("alpha_max_mrad", ctypes.c_double), ("smatrix_dev", ctypes.c_void_p)]
+                ("alpha_max_mrad", ctypes.c_double), ("smatrix_dev", ctypes.c_void_p),
+                ("smatrix_bytes", ctypes.c_size_t)]
 
 
 class PrismError(RuntimeError):
@@ -86,7 +87,9 @@ def lib():
         "prism_plan_create": (I, [ctypes.POINTER(P), ctypes.POINTER(PrismGeometry)]),
         "prism_plan_destroy": (None, [P]),
         "prism_wavelength": (I, [P, ctypes.POINTER(D)]),
+        "prism_alpha_max": (I, [P, I, D, ctypes.POINTER(D)]),
         "prism_beam_count": (I, [P, I, D, ctypes.POINTER(I)]),
+        "prism_active_beam_count": (I, [P, I, D, ctypes.POINTER(PrismOptics), ctypes.POINTER(I)]),
         "prism_beams": (I, [P, I, D, ctypes.POINTER(ctypes.c_int32), I]),
         "prism_smatrix_bytes": (I, [P, I, D, SZ]),
         "prism_build_workspace_bytes": (I, [P, I, D, SZ, SZ]),
@@ -96,18 +99,21 @@ def lib():
         "prism_probe_order": (I, [P, I, P, I, P]),
         "prism_set_probe_precision": (I, [P, I]),
         "prism_set_potential_slices": (I, [P, P]),
-        "prism_build_smatrix": (I, [P, I, D, P, P, ctypes.c_size_t, P]),
-        "prism_probe_outputs": (I, [P, I, D, P, P, I, ctypes.POINTER(PrismOptics),
-                                    ctypes.POINTER(PrismDetector), P, P, ctypes.c_size_t, P]),
-        "prism_probe_cbed": (I, [P, I, D, P, P, I, ctypes.POINTER(PrismOptics), P, P,
-                                 ctypes.c_size_t, P]),
+        "prism_build_smatrix": (I, [P, I, D, P, ctypes.c_size_t, P, ctypes.c_size_t, P]),
+        "prism_probe_outputs": (I, [P, I, D, P, ctypes.c_size_t, P, I,
+                                    ctypes.POINTER(PrismOptics), ctypes.POINTER(PrismDetector), P,
+                                    P, ctypes.c_size_t, P]),
+        "prism_probe_cbed": (I, [P, I, D, P, ctypes.c_size_t, P, I, ctypes.POINTER(PrismOptics),
+                                 P, P, ctypes.c_size_t, P]),
         "prism_multislice_outputs": (I, [P, P, I, ctypes.POINTER(PrismOptics),
                                          ctypes.POINTER(PrismDetector), P, P, ctypes.c_size_t, P]),
-        "prism_probe_outputs_accumulate": (I, [P, I, D, P, P, I, ctypes.POINTER(PrismOptics),
+        "prism_probe_outputs_accumulate": (I, [P, I, D, P, ctypes.c_size_t, P, I,
+                                               ctypes.POINTER(PrismOptics),
                                                ctypes.POINTER(PrismDetector), D, P, P,
                                                ctypes.c_size_t, P]),
-        "prism_probe_cbed_accumulate": (I, [P, I, D, P, P, I, ctypes.POINTER(PrismOptics), D, P,
-                                            P, ctypes.c_size_t, P]),
+        "prism_probe_cbed_accumulate": (I, [P, I, D, P, ctypes.c_size_t, P, I,
+                                            ctypes.POINTER(PrismOptics), D, P, P,
+                                            ctypes.c_size_t, P]),
         "prism_multislice_outputs_accumulate": (I, [P, P, I, ctypes.POINTER(PrismOptics),
                                                     ctypes.POINTER(PrismDetector), D, P, P,
                                                     ctypes.c_size_t, P]),
@@ -118,7 +124,8 @@ def lib():
         "prism_server_create": (I, [ctypes.POINTER(P), ctypes.c_size_t, I, I, I, P,
                                     ctypes.c_size_t]),
         "prism_server_destroy": (None, [P]),
-        "prism_server_admit": (I, [P, P, I, D, P, P, ctypes.c_size_t, ctypes.POINTER(I)]),
+        "prism_server_admit": (I, [P, P, I, D, P, ctypes.c_size_t, P, ctypes.c_size_t,
+                                   ctypes.POINTER(I)]),
         "prism_server_evict": (I, [P, I]),
         "prism_server_submit": (I, [P, I, P, I, ctypes.POINTER(PrismOptics),
                                     ctypes.POINTER(PrismDetector), P,

@@ -95,14 +95,7 @@ struct ActiveBeam {
   int m, n;   // plane-wave indices
 };
 
-hipError_t launch_alpha(const double* probe_xy, int p0, int np, const ActiveBeam* act, int n_act,
-                        int f, int ns, int w, const ProbeOptics& po, float2* alpha,
-                        int2* origin, hipStream_t st);
-// alpha: c64 [n_act][np] (beam-major). Union-window complex contraction on
-// MFMA: window[p][v][u] = sum_a alpha[a][p] * S[act[a].plane][(oy_p + v) % ns][(ox_p + u) % ns].
-hipError_t launch_contract(const float2* smatrix, const ActiveBeam* act, int n_act,
-                           const float2* alpha, const int2* origin, int np, int ns, int w,
-                           int group, float2* window, hipStream_t st);
+// Probes per group of the packed window sum (they share one union window).
 int contract_group(int w);
 // Workgroups per probe group along the union tiles (each loops over tiles).
 int contract_tile_slots(int w);

@@ -120,9 +120,16 @@ struct prism_plan {
     prism::BinLists lists;
   };
   std::map<std::string, PixLists> pixlists;  // window detector bin lists
-  // multislice aperture rows per (alpha, tilt): kept here because the
-  // asynchronous copy to the device reads them after the call returns
-  std::map<std::tuple<uint64_t, uint64_t, uint64_t>, std::vector<int32_t>> aper_rows;
+  // multislice aperture rows per (alpha, tilt) and their pixel count: kept
+  // here because the asynchronous copy to the device reads them after the
+  // call returns. An entry is filled once, when inserted, and never
+  // rewritten, so a copy still queued by an earlier call reads what it was
+  // given.
+  struct AperRows {
+    std::vector<int32_t> rows;
+    long long count = 0;
+  };
+  std::map<std::tuple<uint64_t, uint64_t, uint64_t>, AperRows> aper_rows;
   // per-wave tables of batched builds led by this plan (same reason: the
   // asynchronous copies read them later); set nodes keep their addresses
   std::set<std::vector<uint64_t>> batch_tables;
@@ -196,6 +203,11 @@ int beams_checked(const prism_plan* cp, int f, double amax_mrad, const std::vect
   *out = get_beams(p, f, amax_mrad);
   if ((*out)->empty()) return fail(PRISM_EINVAL, "empty beam set");
   return PRISM_OK;
+}
+
+// Bytes of the compact S-matrix of a beam set: c64 [B][n/2][n/2].
+size_t smatrix_need(const prism_plan* p, const std::vector<int32_t>& mn) {
+  return (mn.size() / 2) * (size_t)(p->n / 2) * (p->n / 2) * sizeof(float2);
 }
 
 // Per-row kx interval of the (tilted) aperture over full-grid rows
@@ -375,7 +387,6 @@ struct ProbeWs {
   float2* twW;
   uint16_t* pix;
   prism::ActiveBeam* act;
-  float2* alpha;    // FP32: [n_act][chunk]
   float* scale;     // 16-bit: [n_act] power-of-two beam scales
   float* scale_part;  // 16-bit: [n_act][kScaleSplit] per-block maxima
   uint32_t* s16;    // packed S: [ns^2][n_actp] (re, im), one word (16-bit) or two (FP32)
@@ -385,13 +396,7 @@ struct ProbeWs {
   double* partial;  // W = 256: [chunk][tiles][PRISM_MAX_DET] detector partials
 };
 
-#ifndef PRISM_F32_PACKED
-#define PRISM_F32_PACKED 1  // FP32 window sum on the packed layout (else beam-major k_contract)
-#endif
-
-// Operand form of the packed window sum for a plan precision (FP32 packed
-// unless the beam-major kernel is selected at build time).
-bool packed_path(int prec) { return prec != PRISM_PREC_FP32 || PRISM_F32_PACKED; }
+// Operand form of the packed window sum for a plan precision.
 prism::Prec packed_prec(int prec) {
   return prec == PRISM_PREC_BF16 ? prism::Prec::kBF16
                                  : (prec == PRISM_PREC_FP16 ? prism::Prec::kFP16 : prism::Prec::kF32);
@@ -411,21 +416,14 @@ size_t probe_layout(int w, int ns, int n_act, int chunk, int prec, ProbeWs* pw, 
   pw->pix = c.take<uint16_t>(
       w == 256 ? 0 : (size_t)PRISM_MAX_DET * ((size_t)w * w + prism::kWdListChunk));
   pw->act = c.take<prism::ActiveBeam>(n_act);
-  if (!packed_path(prec)) {
-    pw->alpha = c.take<float2>((size_t)chunk * n_act);
-    pw->scale = pw->scale_part = nullptr;
-    pw->s16 = pw->a16 = nullptr;
-  } else {
-    const prism::Prec pk = packed_prec(prec);
-    const int n_actp = padded_beams(n_act, pk);
-    pw->alpha = nullptr;
-    pw->scale = pk == prism::Prec::kF32 ? nullptr : c.take<float>(n_act);
-    pw->scale_part =
-        pk == prism::Prec::kF32 ? nullptr : c.take<float>((size_t)n_act * prism::kScaleSplit);
-    pw->s16 = c.take<uint32_t>((size_t)ns * ns * n_actp * prism::prec_words(pk));
-    // per probe: n_actp / KB blocks x 2 rows x 32 words
-    pw->a16 = c.take<uint32_t>((size_t)chunk * (n_actp / prism::prec_block_beams(pk)) * 64);
-  }
+  const prism::Prec pk = packed_prec(prec);
+  const int n_actp = padded_beams(n_act, pk);
+  pw->scale = pk == prism::Prec::kF32 ? nullptr : c.take<float>(n_act);
+  pw->scale_part =
+      pk == prism::Prec::kF32 ? nullptr : c.take<float>((size_t)n_act * prism::kScaleSplit);
+  pw->s16 = c.take<uint32_t>((size_t)ns * ns * n_actp * prism::prec_words(pk));
+  // per probe: n_actp / KB blocks x 2 rows x 32 words
+  pw->a16 = c.take<uint32_t>((size_t)chunk * (n_actp / prism::prec_block_beams(pk)) * 64);
   pw->origin = c.take<int2>(chunk);
   pw->window = c.take<float2>((size_t)chunk * w * w);
   pw->partial = w == 256 ? c.take<double>((size_t)chunk * prism::window256_tiles() * PRISM_MAX_DET)
@@ -494,7 +492,8 @@ int out_mode(bool accumulate, double weight, prism::OutAcc* oa) {
 // PRISM probe step (Fig. 1d-f). d != nullptr: detector sums into out;
 // d == nullptr: full CBED intensities into cbed. oa selects overwrite or
 // weighted accumulation of the results.
-int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, const double* xy, int P,
+int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, size_t S_bytes,
+               const double* xy, int P,
                const prism_optics* o, const prism_detector* d, double* out, float* cbed,
                prism::OutAcc oa, void* ws, size_t ws_bytes, void* stream) {
   const std::vector<int32_t>* mn;
@@ -515,6 +514,8 @@ int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, const doub
   if (n_act < 1) return fail(PRISM_EINVAL, "no beam of the set lies inside the probe aperture");
   if (P == 0) return PRISM_OK;
   if (!S || !xy || !ws || (want_cbed ? !cbed : !out)) return fail(PRISM_EINVAL, "null device buffer");
+  if (S_bytes < smatrix_need(p, *mn))
+    return fail(PRISM_EINVAL, "S-matrix buffer smaller than prism_smatrix_bytes for this f and alpha_max");
   const int G = prism::contract_group(w);
   void* base = aligned_base(ws);
   const size_t avail = ws_bytes;  // layouts include 256 B of alignment slack
@@ -565,32 +566,22 @@ int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, const doub
     }
     return PRISM_OK;
   };
-  if (packed_path(prec)) {
-    const prism::Prec pr = packed_prec(prec);
-    const int n_actp = padded_beams(n_act, pr);
-    const float out_scale = (float)po.norm;
-    po.norm = 1.0;
-    if (pr != prism::Prec::kF32)
-      LAUNCH(p, st, "s16_scale", prism::launch_s16_scale(Sd, pw.act, n_act, ns, pw.scale_part, pw.scale, st));
-    LAUNCH(p, st, pr == prism::Prec::kF32 ? "s32_pack" : "s16_pack",
-           prism::launch_s16_pack(Sd, pw.act, n_act, n_actp, ns, pw.scale, pw.s16, pr, st));
-    for (int p0 = 0; p0 < P; p0 += chunk) {
-      const int np = std::min(chunk, P - p0);
-      LAUNCH(p, st, pr == prism::Prec::kF32 ? "alpha" : "alpha16",
-             prism::launch_alpha16(xy, p0, np, pw.act, n_act, n_actp, f, ns, w, po, pw.scale, G,
-                                   pw.a16, pw.origin, pr, st));
-      LAUNCH(p, st, pr == prism::Prec::kF32 ? "contract" : "contract16",
-             prism::launch_contract16(pw.s16, n_actp, pw.a16, pw.origin, np, ns, w, G, out_scale,
-                                      pw.window, pr, st));
-      if (int r = window_stage(np, p0)) return r;
-    }
-    return PRISM_OK;
-  }
+  const prism::Prec pr = packed_prec(prec);
+  const int n_actp = padded_beams(n_act, pr);
+  const float out_scale = (float)po.norm;
+  po.norm = 1.0;
+  if (pr != prism::Prec::kF32)
+    LAUNCH(p, st, "s16_scale", prism::launch_s16_scale(Sd, pw.act, n_act, ns, pw.scale_part, pw.scale, st));
+  LAUNCH(p, st, pr == prism::Prec::kF32 ? "s32_pack" : "s16_pack",
+         prism::launch_s16_pack(Sd, pw.act, n_act, n_actp, ns, pw.scale, pw.s16, pr, st));
   for (int p0 = 0; p0 < P; p0 += chunk) {
     const int np = std::min(chunk, P - p0);
-    LAUNCH(p, st, "alpha", prism::launch_alpha(xy, p0, np, pw.act, n_act, f, ns, w, po, pw.alpha, pw.origin, st));
-    LAUNCH(p, st, "contract", prism::launch_contract(Sd, pw.act, n_act, pw.alpha, pw.origin, np, ns, w, G, pw.window,
-                                   st));
+    LAUNCH(p, st, pr == prism::Prec::kF32 ? "alpha" : "alpha16",
+           prism::launch_alpha16(xy, p0, np, pw.act, n_act, n_actp, f, ns, w, po, pw.scale, G,
+                                 pw.a16, pw.origin, pr, st));
+    LAUNCH(p, st, pr == prism::Prec::kF32 ? "contract" : "contract16",
+           prism::launch_contract16(pw.s16, n_actp, pw.a16, pw.origin, np, ns, w, G, out_scale,
+                                    pw.window, pr, st));
     if (int r = window_stage(np, p0)) return r;
   }
   return PRISM_OK;
@@ -616,9 +607,16 @@ int multislice_step(prism_plan* p, const double* xy, int P, const prism_optics* 
   SliceWs w;
   slice_layout(p, chunk, 0, bins.n, &w, base);
   prism::ProbeOptics po = probe_optics(p, o);
-  std::vector<int32_t>& rows = p->aper_rows[std::make_tuple(
-      dbits(o->alpha_mrad), dbits(o->tilt_x_mrad), dbits(o->tilt_y_mrad))];
-  const long long n_ap = aperture_rows(p, o, &rows);
+  const auto akey =
+      std::make_tuple(dbits(o->alpha_mrad), dbits(o->tilt_x_mrad), dbits(o->tilt_y_mrad));
+  auto ait = p->aper_rows.find(akey);
+  if (ait == p->aper_rows.end()) {
+    prism_plan::AperRows ar;
+    ar.count = aperture_rows(p, o, &ar.rows);
+    ait = p->aper_rows.emplace(akey, std::move(ar)).first;
+  }
+  const std::vector<int32_t>& rows = ait->second.rows;
+  const long long n_ap = ait->second.count;
   if (n_ap < 1) return fail(PRISM_EINVAL, "the probe aperture holds no grid frequency");
   po.norm = 1.0 / std::sqrt((double)n_ap);
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -694,6 +692,28 @@ int prism_wavelength(const prism_plan* p, double* lam) {
   return PRISM_OK;
 }
 
+int prism_alpha_max(const prism_plan* p, int f, double alpha_mrad, double* alpha_max_mrad) {
+  if (!p || !alpha_max_mrad) return fail(PRISM_EINVAL, "null argument");
+  if (int r = check_f(p, f)) return r;
+  if (!(alpha_mrad > 0.0) || !std::isfinite(alpha_mrad))
+    return fail(PRISM_EINVAL, "alpha_mrad must be positive and finite");
+  // one beam-spacing margin beyond the largest probe semi-angle: the
+  // interpolated beam pitch is f dq, i.e. f lambda dq in angle
+  *alpha_max_mrad = alpha_mrad + (double)f * (p->lam * p->dq) * 1e3;
+  return PRISM_OK;
+}
+
+int prism_active_beam_count(const prism_plan* cp, int f, double amax_mrad,
+                            const prism_optics* o, int* n_active) {
+  if (!n_active) return fail(PRISM_EINVAL, "null argument");
+  prism_plan* p = const_cast<prism_plan*>(cp);
+  const std::vector<int32_t>* mn;
+  if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
+  if (int r = check_optics(p, o)) return r;
+  *n_active = (int)get_active(p, f, amax_mrad, *mn, o)->size();
+  return PRISM_OK;
+}
+
 int prism_beam_count(const prism_plan* p, int f, double amax_mrad, int* n_beams) {
   if (!n_beams) return fail(PRISM_EINVAL, "null argument");
   const std::vector<int32_t>* mn;
@@ -715,7 +735,7 @@ int prism_smatrix_bytes(const prism_plan* p, int f, double amax_mrad, size_t* by
   if (!bytes) return fail(PRISM_EINVAL, "null argument");
   const std::vector<int32_t>* mn;
   if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
-  *bytes = (mn->size() / 2) * (size_t)(p->n / 2) * (p->n / 2) * sizeof(float2);
+  *bytes = smatrix_need(p, *mn);
   return PRISM_OK;
 }
 
@@ -854,11 +874,13 @@ int prism_set_potential_slices(prism_plan* p, const float* phase_dev) {
 #define PRISM_BUILD_STREAMS 2
 #endif
 
-int prism_build_smatrix(prism_plan* p, int f, double amax_mrad, void* S, void* ws, size_t ws_bytes,
-                        void* stream) {
+int prism_build_smatrix(prism_plan* p, int f, double amax_mrad, void* S, size_t S_bytes, void* ws,
+                        size_t ws_bytes, void* stream) {
   const std::vector<int32_t>* mn;
   if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
   if (!S || !ws) return fail(PRISM_EINVAL, "null device buffer");
+  if (S_bytes < smatrix_need(p, *mn))
+    return fail(PRISM_EINVAL, "S-matrix buffer smaller than prism_smatrix_bytes for this f and alpha_max");
   if (!p->phase) return fail(PRISM_ENOTREADY, "potential slices not set");
   const int n = p->n, B = (int)(mn->size() / 2);
   void* base = aligned_base(ws);
@@ -924,38 +946,40 @@ int prism_multislice_outputs_accumulate(prism_plan* p, const double* xy, int P,
   return multislice_step(p, xy, P, o, d, out, oa, ws, ws_bytes, stream);
 }
 
-int prism_probe_outputs(prism_plan* p, int f, double amax_mrad, const void* S, const double* xy,
-                        int P, const prism_optics* o, const prism_detector* d, double* out,
-                        void* ws, size_t ws_bytes, void* stream) {
+int prism_probe_outputs(prism_plan* p, int f, double amax_mrad, const void* S, size_t S_bytes,
+                        const double* xy, int P, const prism_optics* o, const prism_detector* d,
+                        double* out, void* ws, size_t ws_bytes, void* stream) {
   if (!d) return fail(PRISM_EINVAL, "null detector");
-  return probe_step(p, f, amax_mrad, S, xy, P, o, d, out, nullptr, prism::OutAcc{0, 1.0}, ws,
-                    ws_bytes, stream);
+  return probe_step(p, f, amax_mrad, S, S_bytes, xy, P, o, d, out, nullptr,
+                    prism::OutAcc{0, 1.0}, ws, ws_bytes, stream);
 }
 
 int prism_probe_outputs_accumulate(prism_plan* p, int f, double amax_mrad, const void* S,
-                                   const double* xy, int P, const prism_optics* o,
+                                   size_t S_bytes, const double* xy, int P, const prism_optics* o,
                                    const prism_detector* d, double weight, double* out, void* ws,
                                    size_t ws_bytes, void* stream) {
   if (!d) return fail(PRISM_EINVAL, "null detector");
   prism::OutAcc oa;
   if (int r = out_mode(true, weight, &oa)) return r;
-  return probe_step(p, f, amax_mrad, S, xy, P, o, d, out, nullptr, oa, ws, ws_bytes, stream);
+  return probe_step(p, f, amax_mrad, S, S_bytes, xy, P, o, d, out, nullptr, oa, ws, ws_bytes,
+                    stream);
 }
 
-int prism_probe_cbed(prism_plan* p, int f, double amax_mrad, const void* S, const double* xy,
-                     int P, const prism_optics* o, float* cbed, void* ws, size_t ws_bytes,
-                     void* stream) {
-  return probe_step(p, f, amax_mrad, S, xy, P, o, nullptr, nullptr, cbed, prism::OutAcc{0, 1.0},
-                    ws, ws_bytes, stream);
+int prism_probe_cbed(prism_plan* p, int f, double amax_mrad, const void* S, size_t S_bytes,
+                     const double* xy, int P, const prism_optics* o, float* cbed, void* ws,
+                     size_t ws_bytes, void* stream) {
+  return probe_step(p, f, amax_mrad, S, S_bytes, xy, P, o, nullptr, nullptr, cbed,
+                    prism::OutAcc{0, 1.0}, ws, ws_bytes, stream);
 }
 
 int prism_probe_cbed_accumulate(prism_plan* p, int f, double amax_mrad, const void* S,
-                                const double* xy, int P, const prism_optics* o, double weight,
+                                size_t S_bytes, const double* xy, int P, const prism_optics* o,
+                                double weight,
                                 float* cbed, void* ws, size_t ws_bytes, void* stream) {
   prism::OutAcc oa;
   if (int r = out_mode(true, weight, &oa)) return r;
-  return probe_step(p, f, amax_mrad, S, xy, P, o, nullptr, nullptr, cbed, oa, ws, ws_bytes,
-                    stream);
+  return probe_step(p, f, amax_mrad, S, S_bytes, xy, P, o, nullptr, nullptr, cbed, oa, ws,
+                    ws_bytes, stream);
 }
 
 }  // extern "C"
@@ -1189,6 +1213,11 @@ int prism_build_smatrix_batch(const prism_build_item* items, int count, void* ws
   if (int r = batch_groups(items, count, &groups)) return r;
   for (int i = 0; i < count; ++i) {
     if (!items[i].smatrix_dev) return fail(PRISM_EINVAL, "batch item " + std::to_string(i) + ": null S-matrix");
+    const std::vector<int32_t>& mn =
+        items[i].plan->beams.at({items[i].f, dbits(items[i].alpha_max_mrad)});
+    if (items[i].smatrix_bytes < smatrix_need(items[i].plan, mn))
+      return fail(PRISM_EINVAL, "batch item " + std::to_string(i) +
+                                    ": S-matrix buffer smaller than prism_smatrix_bytes");
     if (!items[i].plan->phase)
       return fail(PRISM_ENOTREADY, "batch item " + std::to_string(i) + ": potential slices not set");
   }

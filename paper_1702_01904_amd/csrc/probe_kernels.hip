@@ -1,18 +1,11 @@
-// PRISM probe step (Fig. 1d-f): coefficients, window sum, FFT, detectors.
+// PRISM probe step (Fig. 1d-f), second half: the window FFT, |Psi|^2 and
+// the detector sums.
 //
 //   alpha_{m,n}(r0) = A(q) e^{-i chi(q)} e^{-2 pi i q.r0} / (W sqrt(B_A))
 //   psi(r, r0)      = sum_{m,n} S_{m,n}(r) alpha_{m,n}(r0)      (Eq. PRISMfinal)
-// inside the W x W window of Eq. RegionBounds, then |FFT_W psi|^2 / W^2
-// integrated per detector bin.
-//
-// The window sum is a complex GEMM when neighbouring probes share their
-// windows: for a group of G probes the union of their windows U is one
-// M = 2G (real/imag rows) x N = |U| pixels x K = 2 B_A product with
-//   A'[2g  ][2b] =  Re a_gb, A'[2g  ][2b+1] = -Im a_gb,
-//   A'[2g+1][2b] =  Im a_gb, A'[2g+1][2b+1] =  Re a_gb,
-//   B'[2b][x] = Re S_b(x),   B'[2b+1][x]   = Im S_b(x),
-// run on v_mfma_f32_16x16x4f32 with FP32 accumulation. Each output pixel
-// of the union is kept for the probes whose own window contains it.
+// inside the W x W window of Eq. RegionBounds (coefficients and window sum:
+// probe16_kernels.hip), then |FFT_W psi|^2 / W^2 integrated per detector
+// bin here, or stored whole (CBED).
 #include <algorithm>
 
 #include "fft_lds.hpp"
@@ -23,292 +16,12 @@ namespace prism {
 
 namespace {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ int wrap_mod(long long v, int m) {
-  long long r = v % m;
-  return (int)(r < 0 ? r + m : r);
-}
-
-// One thread per (active beam, probe); alpha is stored beam-major
-// [n_act][np] so that a probe group's coefficients for one beam are
-// contiguous. Also writes each probe's window origin (first S pixel of the
-// cut-out, periodic).
-__global__ void k_alpha(const double* __restrict__ probe_xy, int p0, int np,
-                        const ActiveBeam* __restrict__ act, int n_act, int f, int ns, int w,
-                        ProbeOptics po, float2* __restrict__ alpha, int2* __restrict__ origin) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)np * n_act) return;
-  const int a = (int)(i / np), p = (int)(i % np);
-  const double x0 = probe_xy[2 * (size_t)(p0 + p)], y0 = probe_xy[2 * (size_t)(p0 + p) + 1];
-  if (a == 0) {
-    const double dxs = po.cell / (double)ns;
-    const int cx = wrap_mod((long long)floor(x0 / dxs + 0.5), ns);
-    const int cy = wrap_mod((long long)floor(y0 / dxs + 0.5), ns);
-    origin[p] = make_int2(wrap_mod((long long)cx - w / 2, ns), wrap_mod((long long)cy - w / 2, ns));
-  }
-  const double kx = (double)act[a].m * f, ky = (double)act[a].n * f;
-  const double dx = kx - po.ktx, dy = ky - po.kty;
-  const double q2 = (dx * dx + dy * dy) * (po.dq * po.dq);
-  double t = -(0.5 * po.lam * q2 * po.C1 + 0.25 * po.lam * po.lam * po.lam * q2 * q2 * po.C3) -
-             (kx * (x0 - po.sx) + ky * (y0 - po.sy)) * po.dq;
-  t -= floor(t);
-  double s, c;
-  sincospi(2.0 * t, &s, &c);
-  alpha[i] = make_float2((float)(c * po.norm), (float)(s * po.norm));
-}
-
-// Contraction tile shape (tuned on MI355X; overridable at build time).
-#ifndef PRISM_CKB
-#define PRISM_CKB 16   // beams per K block
-#endif
-#ifndef PRISM_CCT
-#define PRISM_CCT 2    // 16-pixel MFMA column tiles per wave
-#endif
-#ifndef PRISM_CG128
-#define PRISM_CG128 64 // probes per group for W >= 128
-#endif
-#ifndef PRISM_CTILES_PER_WG
-#define PRISM_CTILES_PER_WG 4  // union tiles per workgroup for a single window
-#endif
-constexpr int kCNT = 256;                 // threads per contraction workgroup (4 waves)
-constexpr int kCCT = PRISM_CCT;
-constexpr int kCTile = 4 * 16 * kCCT;     // union pixels per workgroup
-constexpr int kCKB = PRISM_CKB;
-
-struct UnionGeom {
-  int y0, x0;  // first S pixel of the union (periodic)
-  int uy, ux;  // union extent
-};
-
-// Contract one 128-pixel tile of the union for all G probes of the group.
-// only < 0: write every probe whose window holds a pixel; only >= 0: write
-// that probe alone (scattered groups). The K loop is double buffered: the
-// next 16-beam block of alpha and S is fetched into registers while the
-// MFMAs consume the current block from LDS.
-template <int G>
-struct ContractLds {
-  static constexpr int AROW = 2 * G + 16;        // A'[k'][m'] row pitch (floats)
-  static constexpr int BROW = kCTile + 16;       // B'[k'][n] row pitch (floats)
-  static constexpr int ABUF = 2 * kCKB * AROW;   // floats per A' buffer
-  static constexpr int BBUF = 2 * kCKB * BROW;   // floats per B' buffer
-  static constexpr int FLOATS = 2 * (ABUF + BBUF);
-};
-
-template <int G>
-__device__ __forceinline__ void contract_tile(const float2* __restrict__ S,
-                                              const ActiveBeam* __restrict__ act, int n_act,
-                                              const float2* __restrict__ alpha, int np,
-                                              int p_base, int gcount, int ns, int w,
-                                              const UnionGeom& U,
-                                              int tile, const int* offx, const int* offy, int only,
-                                              float* __restrict__ smem,
-                                              float2* __restrict__ window) {
-  using CL = ContractLds<G>;
-  constexpr int RT = G / 8;                 // 16-row MFMA tiles covering 2G real rows
-  constexpr int NA = G * kCKB / kCNT;       // alpha values staged per thread
-  constexpr int NSV = kCKB * kCTile / kCNT; // S values staged per thread
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int npix = U.uy * U.ux;
-
-  // pixel this thread stages for the S block (fixed across K blocks)
-  const int n_ld = tid & (kCTile - 1);
-  // beam row of the S block this wave stages: uniform per wave, so the
-  // plane lookups below become scalar loads
-  const int bl0 = __builtin_amdgcn_readfirstlane(tid / kCTile);
-  const int up_ld = tile * kCTile + n_ld;
-  long long soff = -1;
-  if (up_ld < npix) {
-    const int a = up_ld / U.ux, b = up_ld - a * U.ux;
-    soff = (long long)((U.y0 + a) % ns) * ns + ((U.x0 + b) % ns);
-  }
-  const size_t plane = (size_t)ns * ns;
-
-  // Two register sets: the block after next is in flight while a block is
-  // computed. Loads are issued unconditionally from clamped (in-bounds)
-  // indices and out-of-range entries are zeroed when staged, so the number
-  // of loads in flight is the same on every path and each wait covers only
-  // the older set.
-  float2 ra[2][NA], rs[2][NSV];
-  const long long soff_c = soff < 0 ? 0 : soff;
-  auto fetch = [&](int set, int kb) {
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int e = tid + i * kCNT;
-      const int g = e % G, bl = e / G;
-      const int b = min(kb + bl, n_act - 1), pidx = min(p_base + g, np - 1);
-      ra[set][i] = alpha[(size_t)b * np + pidx];
-    }
-#pragma unroll
-    for (int i = 0; i < NSV; ++i) {
-      const int bl = bl0 + i * (kCNT / kCTile);
-      rs[set][i] = S[(size_t)act[min(kb + bl, n_act - 1)].plane * plane + soff_c];
-    }
-  };
-  // Stage one K block in the real MFMA operand layout:
-  //   A'[2b][2g] = Re a, A'[2b+1][2g] = -Im a, A'[2b][2g+1] = Im a, A'[2b+1][2g+1] = Re a
-  //   B'[2b][n]  = Re S, B'[2b+1][n] = Im S
-  auto stash = [&](int set, int kb) {  // register set s goes to LDS buffer s
-    float* A = smem + set * CL::ABUF;
-    float* Bm = smem + 2 * CL::ABUF + set * CL::BBUF;
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int e = tid + i * kCNT;
-      const int g = e % G, bl = e / G;
-      const bool ok = g < gcount && kb + bl < n_act;
-      const float2 a = ok ? ra[set][i] : make_float2(0.f, 0.f);
-      *reinterpret_cast<float2*>(A + (2 * bl) * CL::AROW + 2 * g) = a;
-      *reinterpret_cast<float2*>(A + (2 * bl + 1) * CL::AROW + 2 * g) = make_float2(-a.y, a.x);
-    }
-#pragma unroll
-    for (int i = 0; i < NSV; ++i) {
-      const int bl = bl0 + i * (kCNT / kCTile);
-      const bool ok = soff >= 0 && kb + bl < n_act;
-      Bm[(2 * bl) * CL::BROW + n_ld] = ok ? rs[set][i].x : 0.f;
-      Bm[(2 * bl + 1) * CL::BROW + n_ld] = ok ? rs[set][i].y : 0.f;
-    }
-  };
-
-  floatx4 acc[RT][kCCT];
-#pragma unroll
-  for (int r = 0; r < RT; ++r)
-#pragma unroll
-    for (int c = 0; c < kCCT; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-  const int krow = lane >> 4, mcol = lane & 15;
-  auto compute = [&](int buf) {
-    const float* A = smem + buf * CL::ABUF + krow * CL::AROW + mcol;
-    const float* Bm =
-        smem + 2 * CL::ABUF + buf * CL::BBUF + krow * CL::BROW + 16 * kCCT * wv + mcol;
-    // operands of K step ks+1 are read while the MFMAs of step ks run
-    float av[2][RT], bv[2][kCCT];
-#pragma unroll
-    for (int r = 0; r < RT; ++r) av[0][r] = A[16 * r];
-#pragma unroll
-    for (int c = 0; c < kCCT; ++c) bv[0][c] = Bm[16 * c];
-#pragma unroll
-    for (int ks = 0; ks < kCKB / 2; ++ks) {
-      const int cur = ks & 1, nxt = cur ^ 1;
-      if (ks + 1 < kCKB / 2) {
-#pragma unroll
-        for (int r = 0; r < RT; ++r) av[nxt][r] = A[4 * (ks + 1) * CL::AROW + 16 * r];
-#pragma unroll
-        for (int c = 0; c < kCCT; ++c) bv[nxt][c] = Bm[4 * (ks + 1) * CL::BROW + 16 * c];
-      }
-      __builtin_amdgcn_sched_barrier(0);  // keep those reads ahead of this step's MFMAs
-#pragma unroll
-      for (int r = 0; r < RT; ++r)
-#pragma unroll
-        for (int c = 0; c < kCCT; ++c)
-          acc[r][c] =
-              __builtin_amdgcn_mfma_f32_16x16x4f32(av[cur][r], bv[cur][c], acc[r][c], 0, 0, 0);
-    }
-  };
-  // K blocks alternate between register set / LDS buffer 0 and 1, in pairs;
-  // an odd last block is paired with a zero-weight block.
-  const int npair = (n_act + 2 * kCKB - 1) / (2 * kCKB);
-  fetch(0, 0);
-  fetch(1, kCKB);
-  for (int pr = 0; pr < npair; ++pr) {
-    const int kb = 2 * kCKB * pr;
-    stash(0, kb);
-    __syncthreads();
-    fetch(0, kb + 2 * kCKB);
-    compute(0);
-    stash(1, kb + kCKB);
-    __syncthreads();
-    fetch(1, kb + 3 * kCKB);
-    compute(1);
-  }
-  __syncthreads();  // LDS buffers free for a following tile
-
-  // epilogue: lane holds rows 4*(lane/16)+i of each 16x16 tile, column lane%16
-  const size_t w2 = (size_t)w * w;
-#pragma unroll
-  for (int c = 0; c < kCCT; ++c) {
-    const int up = tile * kCTile + 16 * kCCT * wv + 16 * c + (lane & 15);
-    if (up >= npix) continue;
-    const int a = up / U.ux, b = up - a * U.ux;
-#pragma unroll
-    for (int r = 0; r < RT; ++r) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int g = 8 * r + 2 * (lane >> 4) + h;
-        if (g >= gcount || (only >= 0 && g != only)) continue;
-        const int v = a - offy[g], u = b - offx[g];
-        if (v < 0 || v >= w || u < 0 || u >= w) continue;
-        window[(size_t)(p_base + g) * w2 + (size_t)v * w + u] =
-            make_float2(acc[r][c][2 * h], acc[r][c][2 * h + 1]);
-      }
-    }
-  }
-}
-
-template <int G>
-__global__ __launch_bounds__(kCNT) __attribute__((amdgpu_waves_per_eu(2))) void k_contract(const float2* __restrict__ S,
-                                                   const ActiveBeam* __restrict__ act, int n_act,
-                                                   const float2* __restrict__ alpha,
-                                                   const int2* __restrict__ origin, int np, int ns,
-                                                   int w, float2* __restrict__ window) {
-  __shared__ float smem[ContractLds<G>::FLOATS];  // two A' and two B' buffers
-  __shared__ int offx[G], offy[G];
-  __shared__ int ginfo[6];
-  const int tid = threadIdx.x;
-  const int p_base = blockIdx.y * G;
-  const int gcount = min(G, np - p_base);
-  if (tid < 64) {
-    // group geometry in wave 0, one lane per probe (G <= 64): offsets of
-    // each window from the first, their extent, and the union origin
-    const int2 o0 = origin[p_base];
-    int rx = 0, ry = 0;
-    if (tid < gcount) {
-      const int2 o = origin[p_base + tid];
-      rx = wrap_mod((long long)o.x - o0.x + ns / 2, ns) - ns / 2;
-      ry = wrap_mod((long long)o.y - o0.y + ns / 2, ns) - ns / 2;
-    }
-    int minx = rx, maxx = rx, miny = ry, maxy = ry;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      minx = min(minx, __shfl_xor(minx, off, 64));
-      maxx = max(maxx, __shfl_xor(maxx, off, 64));
-      miny = min(miny, __shfl_xor(miny, off, 64));
-      maxy = max(maxy, __shfl_xor(maxy, off, 64));
-    }
-    if (tid < G) {
-      offx[tid] = rx - minx;
-      offy[tid] = ry - miny;
-    }
-    if (tid == 0) {
-      const int smax = w / 2;
-      ginfo[0] = (maxx - minx <= smax && maxy - miny <= smax) ? 0 : 1;
-      ginfo[1] = wrap_mod((long long)o0.y + miny, ns);
-      ginfo[2] = wrap_mod((long long)o0.x + minx, ns);
-      ginfo[3] = w + (maxy - miny);
-      ginfo[4] = w + (maxx - minx);
-    }
-  }
-  __syncthreads();
-  // the workgroups of a group share its tiles round-robin
-  if (ginfo[0] == 0) {
-    UnionGeom U{ginfo[1], ginfo[2], ginfo[3], ginfo[4]};
-    for (int tile = blockIdx.x; tile * kCTile < U.uy * U.ux; tile += gridDim.x)
-      contract_tile<G>(S, act, n_act, alpha, np, p_base, gcount, ns, w, U, tile, offx, offy, -1,
-                       smem, window);
-  } else {
-    // windows too far apart to share: one probe at a time, its window alone
-    __shared__ int zero[G];
-    for (int g = tid; g < G; g += kCNT) zero[g] = 0;
-    __syncthreads();
-    for (int tile = blockIdx.x; tile * kCTile < w * w; tile += gridDim.x) {
-      for (int g = 0; g < gcount; ++g) {
-        const int2 o = origin[p_base + g];
-        UnionGeom U{o.y, o.x, w, w};
-        contract_tile<G>(S, act, n_act, alpha, np, p_base, gcount, ns, w, U, tile, zero, zero, g,
-                         smem, window);
-      }
-    }
-  }
-}
+// Probe grouping of the window sum (shared with probe16_kernels.hip): probes
+// per group for W >= 128, and the union tiles of 128 pixels that one
+// workgroup walks for a single window.
+constexpr int kCG128 = 64;
+constexpr int kCTile = 128;
+constexpr int kCTilesPerWg = 4;
 
 // ---------------------------------------------------------------------------
 // W = 256 windows (too large for one workgroup's LDS): the 2D FFT runs as
@@ -555,43 +268,11 @@ inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 
 
 }  // namespace
 
-int contract_group(int w) { return w >= 128 ? PRISM_CG128 : (w >= 64 ? 32 : 16); }
-
-hipError_t launch_alpha(const double* probe_xy, int p0, int np, const ActiveBeam* act, int n_act,
-                        int f, int ns, int w, const ProbeOptics& po, float2* alpha,
-                        int2* origin, hipStream_t st) {
-  hipLaunchKernelGGL(k_alpha, dim3(blocks_for((size_t)np * n_act, 256)), dim3(256), 0, st,
-                     probe_xy, p0, np, act, n_act, f, ns, w, po, alpha, origin);
-  return hipGetLastError();
-}
+int contract_group(int w) { return w >= 128 ? kCG128 : (w >= 64 ? 32 : 16); }
 
 int contract_tile_slots(int w) {
   const int own = (w * w + kCTile - 1) / kCTile;  // tiles of one window
-  return std::max(1, own / PRISM_CTILES_PER_WG);
-}
-
-hipError_t launch_contract(const float2* smatrix, const ActiveBeam* act, int n_act,
-                           const float2* alpha, const int2* origin, int np, int ns, int w,
-                           int group, float2* window, hipStream_t st) {
-  const unsigned groups = (unsigned)((np + group - 1) / group);
-  const dim3 grid((unsigned)contract_tile_slots(w), groups);
-  switch (group) {
-    case 16:
-      hipLaunchKernelGGL(k_contract<16>, grid, dim3(kCNT), 0, st, smatrix, act, n_act, alpha,
-                         origin, np, ns, w, window);
-      break;
-    case 32:
-      hipLaunchKernelGGL(k_contract<32>, grid, dim3(kCNT), 0, st, smatrix, act, n_act, alpha,
-                         origin, np, ns, w, window);
-      break;
-    case 64:
-      hipLaunchKernelGGL(k_contract<64>, grid, dim3(kCNT), 0, st, smatrix, act, n_act, alpha,
-                         origin, np, ns, w, window);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return std::max(1, own / kCTilesPerWg);
 }
 
 int window256_tiles() { return kW4 / 16; }

@@ -32,7 +32,8 @@ struct Specimen {
   int f;
   double amax;
   const void* S;
-  size_t bytes;
+  size_t bytes;     // prism_smatrix_bytes: what the budget counts
+  size_t S_bytes;   // the caller's buffer
   hipEvent_t ready;
   bool live;
 };
@@ -193,8 +194,9 @@ int flush_groups(prism_server* s, std::vector<char>* sent) {
       }
       prism_detector det{n_det, q0.edges.data()};
       if (total > 0)
-        if (int r = prism_probe_outputs(sp.plan, sp.f, sp.amax, sp.S, rg.xy, total, &q0.optics, &det,
-                                        rg.out, rg.probe_ws, rg.probe_ws_bytes, st))
+        if (int r = prism_probe_outputs(sp.plan, sp.f, sp.amax, sp.S, sp.S_bytes, rg.xy, total,
+                                        &q0.optics, &det, rg.out, rg.probe_ws, rg.probe_ws_bytes,
+                                        st))
           return r;
       off = 0;
       for (size_t i = a; i < b; ++i) {
@@ -267,22 +269,28 @@ int prism_server_create(prism_server** out, size_t smatrix_budget_bytes, int n_s
 void prism_server_destroy(prism_server* s) { delete s; }
 
 int prism_server_admit(prism_server* s, prism_plan* plan, int f, double alpha_max_mrad,
-                       void* smatrix_dev, void* build_ws, size_t build_ws_bytes, int* id) {
+                       void* smatrix_dev, size_t smatrix_bytes, void* build_ws,
+                       size_t build_ws_bytes, int* id) {
   if (!s || !plan || !smatrix_dev || !id) return set_error(PRISM_EINVAL, "null argument");
   size_t bytes;
   if (int r = prism_smatrix_bytes(plan, f, alpha_max_mrad, &bytes)) return r;
+  if (smatrix_bytes < bytes)
+    return set_error(PRISM_EINVAL, "S-matrix buffer smaller than prism_smatrix_bytes");
   if (s->used + bytes > s->budget)
     return set_error(PRISM_ENOSPACE, "S-matrix does not fit in the server's budget");
-  hipStream_t st = s->streams[s->specs.size() % s->streams.size()];
+  // every build runs on the server's first stream, so builds are ordered
+  // among themselves (two builds may share one build workspace)
+  hipStream_t st = s->streams[0];
   if (build_ws) {
-    if (int r = prism_build_smatrix(plan, f, alpha_max_mrad, smatrix_dev, build_ws,
-                                    build_ws_bytes, st))
+    if (int r = prism_build_smatrix(plan, f, alpha_max_mrad, smatrix_dev, smatrix_bytes,
+                                    build_ws, build_ws_bytes, st))
       return r;
   }
   hipEvent_t ready = s->event();
   if (!ready) return set_error(PRISM_EHIP, "create event");
   if (hipError_t e = hipEventRecord(ready, st); e != hipSuccess) return hip_err(e, "record event");
-  s->specs.push_back(Specimen{plan, f, alpha_max_mrad, smatrix_dev, bytes, ready, true});
+  s->specs.push_back(Specimen{plan, f, alpha_max_mrad, smatrix_dev, bytes, smatrix_bytes, ready,
+                              true});
   s->used += bytes;
   *id = (int)s->specs.size() - 1;
   return PRISM_OK;

@@ -78,7 +78,7 @@ def test_beam_set_identical_to_oracle(n, cell, E, alpha, f):
     p = Plan(n, cell, E, [2.0])
     lam = O.wavelength(E)
     amax = O.default_alpha_max(alpha * 1e-3, f, lam, 1 / cell) * 1e3
-    assert abs(p.alpha_max_default(alpha, f) - amax) < 1e-12
+    assert abs(p.alpha_max_default(alpha, f) - amax) <= 1e-12 * amax
     got = p.beams(f, amax)
     ref = O.beam_set(n, cell, lam, f, amax * 1e-3)
     assert got.shape == ref.shape
@@ -156,23 +156,26 @@ def _raw(p):
     return p._L, p._h
 
 
+SBIG = 1 << 40   # S-matrix byte size passed with a dummy pointer: large enough for any case
+
+
 def test_errors_before_any_launch():
     p = _plan()
     L, h = _raw(p)
     amax = p.alpha_max_default(20.0, 2)
     dummy = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails validation first
     # potential not set
-    r = L.prism_build_smatrix(h, 2, amax, dummy, dummy, 1 << 30, None)
+    r = L.prism_build_smatrix(h, 2, amax, dummy, SBIG, dummy, 1 << 30, None)
     assert r == _native.PRISM_ENOTREADY
     assert b"potential" in L.prism_last_error()
     # null buffers
-    assert L.prism_build_smatrix(h, 2, amax, None, dummy, 1 << 30, None) == _native.PRISM_EINVAL
+    assert L.prism_build_smatrix(h, 2, amax, None, SBIG, dummy, 1 << 30, None) == _native.PRISM_EINVAL
     L.prism_set_potential_slices(h, dummy)
     # workspace too small
-    r = L.prism_build_smatrix(h, 2, amax, dummy, dummy, 1024, None)
+    r = L.prism_build_smatrix(h, 2, amax, dummy, SBIG, dummy, 1024, None)
     assert r == _native.PRISM_ENOSPACE
     # bad f
-    assert L.prism_build_smatrix(h, 3, amax, dummy, dummy, 1 << 30, None) == _native.PRISM_EINVAL
+    assert L.prism_build_smatrix(h, 3, amax, dummy, SBIG, dummy, 1 << 30, None) == _native.PRISM_EINVAL
 
     optics = _native.PrismOptics(20.0, 0.0, 0.0)
     edges = (ctypes.c_double * 2)(40.0, 150.0)
@@ -198,7 +201,7 @@ def test_errors_before_any_launch():
     big = Plan(1024, 102.4, 80.0, [2.0])
     Lb, hb = _raw(big)
     amax1 = big.alpha_max_default(20.0, 1)
-    r = Lb.prism_probe_outputs(hb, 1, amax1, dummy, dummy, 4, ctypes.byref(optics),
+    r = Lb.prism_probe_outputs(hb, 1, amax1, dummy, SBIG, dummy, 4, ctypes.byref(optics),
                                ctypes.byref(det), dummy, dummy, 1 << 30, None)
     assert r == _native.PRISM_EINVAL and b"window" in Lb.prism_last_error()
     # tilt: aperture pushed across the half-band limit (104 mrad at 80 keV)
@@ -208,7 +211,7 @@ def test_errors_before_any_launch():
     assert b"half-band" in L.prism_last_error()
     # tilt: semi-angle + tilt beyond the beam set's alpha_max
     t5 = _native.PrismOptics(20.0, 0.0, 0.0, 3.0, 4.0)
-    r = L.prism_probe_outputs(h, 2, 24.0, dummy, dummy, 4, ctypes.byref(t5), ctypes.byref(det),
+    r = L.prism_probe_outputs(h, 2, 24.0, dummy, SBIG, dummy, 4, ctypes.byref(t5), ctypes.byref(det),
                               dummy, dummy, 1 << 30, None)
     assert r == _native.PRISM_EINVAL and b"tilt" in L.prism_last_error()
     nan_tilt = _native.PrismOptics(20.0, 0.0, 0.0, float("nan"), 0.0)
@@ -216,45 +219,45 @@ def test_errors_before_any_launch():
                                       dummy, dummy, 1 << 30, None) == _native.PRISM_EINVAL
     # probe step: semi-angle beyond the beam set's alpha_max
     wider = _native.PrismOptics(amax + 1.0, 0.0, 0.0)
-    r = L.prism_probe_outputs(h, 2, amax, dummy, dummy, 4, ctypes.byref(wider), ctypes.byref(det),
+    r = L.prism_probe_outputs(h, 2, amax, dummy, SBIG, dummy, 4, ctypes.byref(wider), ctypes.byref(det),
                               dummy, dummy, 1 << 30, None)
     assert r == _native.PRISM_EINVAL and b"alpha_max" in L.prism_last_error()
     # CBED output: null output buffer, and the same checks as the detector path
-    r = L.prism_probe_cbed(h, 2, amax, dummy, dummy, 4, ctypes.byref(optics), None, dummy,
+    r = L.prism_probe_cbed(h, 2, amax, dummy, SBIG, dummy, 4, ctypes.byref(optics), None, dummy,
                            1 << 30, None)
     assert r == _native.PRISM_EINVAL
-    r = L.prism_probe_cbed(h, 2, amax, dummy, dummy, 4, ctypes.byref(wider), dummy, dummy,
+    r = L.prism_probe_cbed(h, 2, amax, dummy, SBIG, dummy, 4, ctypes.byref(wider), dummy, dummy,
                            1 << 30, None)
     assert r == _native.PRISM_EINVAL
-    assert L.prism_probe_cbed(h, 2, amax, None, None, 0, ctypes.byref(optics), None, None, 0,
+    assert L.prism_probe_cbed(h, 2, amax, None, 0, None, 0, ctypes.byref(optics), None, None, 0,
                               None) == _native.PRISM_OK
     # probe step: too small workspace
-    r = L.prism_probe_outputs(h, 2, amax, dummy, dummy, 4, ctypes.byref(optics), ctypes.byref(det),
+    r = L.prism_probe_outputs(h, 2, amax, dummy, SBIG, dummy, 4, ctypes.byref(optics), ctypes.byref(det),
                               dummy, dummy, 128, None)
     assert r == _native.PRISM_ENOSPACE
     # accumulating forms: weight must be finite; otherwise the checks of the
     # call they extend, and zero probes is a no-op
     for wgt in (float("nan"), float("inf")):
-        r = L.prism_probe_outputs_accumulate(h, 2, amax, dummy, dummy, 4, ctypes.byref(optics),
+        r = L.prism_probe_outputs_accumulate(h, 2, amax, dummy, SBIG, dummy, 4, ctypes.byref(optics),
                                              ctypes.byref(det), wgt, dummy, dummy, 1 << 30, None)
         assert r == _native.PRISM_EINVAL and b"weight" in L.prism_last_error()
-        r = L.prism_probe_cbed_accumulate(h, 2, amax, dummy, dummy, 4, ctypes.byref(optics), wgt,
+        r = L.prism_probe_cbed_accumulate(h, 2, amax, dummy, SBIG, dummy, 4, ctypes.byref(optics), wgt,
                                           dummy, dummy, 1 << 30, None)
         assert r == _native.PRISM_EINVAL and b"weight" in L.prism_last_error()
         r = L.prism_multislice_outputs_accumulate(h, dummy, 4, ctypes.byref(optics),
                                                   ctypes.byref(det), wgt, dummy, dummy, 1 << 30,
                                                   None)
         assert r == _native.PRISM_EINVAL and b"weight" in L.prism_last_error()
-    r = L.prism_probe_outputs_accumulate(h, 2, amax, dummy, dummy, 4, ctypes.byref(optics),
+    r = L.prism_probe_outputs_accumulate(h, 2, amax, dummy, SBIG, dummy, 4, ctypes.byref(optics),
                                          None, 0.5, dummy, dummy, 1 << 30, None)
     assert r == _native.PRISM_EINVAL
-    r = L.prism_probe_cbed_accumulate(h, 2, amax, dummy, dummy, 4, ctypes.byref(wider), 0.5,
+    r = L.prism_probe_cbed_accumulate(h, 2, amax, dummy, SBIG, dummy, 4, ctypes.byref(wider), 0.5,
                                       dummy, dummy, 1 << 30, None)
     assert r == _native.PRISM_EINVAL and b"alpha_max" in L.prism_last_error()
     r = L.prism_multislice_outputs_accumulate(h, dummy, 4, ctypes.byref(optics), ctypes.byref(det),
                                               0.5, dummy, dummy, 64, None)
     assert r == _native.PRISM_ENOSPACE
-    assert L.prism_probe_outputs_accumulate(h, 2, amax, None, None, 0, ctypes.byref(optics),
+    assert L.prism_probe_outputs_accumulate(h, 2, amax, None, 0, None, 0, ctypes.byref(optics),
                                             ctypes.byref(det), 0.5, None, None, 0,
                                             None) == _native.PRISM_OK
 
@@ -297,7 +300,7 @@ def test_batch_build_validation():
     arr = (_native.PrismBuildItem * 3)()
     dummy = ctypes.c_void_p(0x1000)
     for k, (p, f, am) in enumerate(items):
-        arr[k] = _native.PrismBuildItem(p._h, f, am, dummy)
+        arr[k] = _native.PrismBuildItem(p._h, f, am, dummy, SBIG)
     # potential slices not set (checked per item, before any launch)
     r = L.prism_build_smatrix_batch(arr, 3, dummy, 1 << 30, None)
     assert r == _native.PRISM_ENOTREADY and b"item 0" in L.prism_last_error()
@@ -307,10 +310,10 @@ def test_batch_build_validation():
     assert L.prism_build_smatrix_batch(arr, 0, None, 0, None) == _native.PRISM_OK
     bad = (_native.PrismBuildItem * 2)()
     bad[0] = arr[0]
-    bad[1] = _native.PrismBuildItem(b._h, 3, 30.0, dummy)        # 128 % 6 != 0
+    bad[1] = _native.PrismBuildItem(b._h, 3, 30.0, dummy, SBIG)  # 128 % 6 != 0
     r = L.prism_build_smatrix_batch(bad, 2, dummy, 1 << 30, None)
     assert r == _native.PRISM_EINVAL and b"item 1" in L.prism_last_error()
-    bad[1] = _native.PrismBuildItem(None, 1, 30.0, dummy)
+    bad[1] = _native.PrismBuildItem(None, 1, 30.0, dummy, SBIG)
     assert L.prism_build_smatrix_batch(bad, 2, dummy, 1 << 30, None) == _native.PRISM_EINVAL
     pref_q, min_q = ctypes.c_size_t(), ctypes.c_size_t()
     assert L.prism_build_batch_workspace_bytes(bad, 2, ctypes.byref(pref_q),
@@ -318,7 +321,7 @@ def test_batch_build_validation():
     for p in (a, b, c):
         L.prism_set_potential_slices(p._h, dummy)
     nulls = (_native.PrismBuildItem * 1)()
-    nulls[0] = _native.PrismBuildItem(a._h, fa, items[0][2], None)
+    nulls[0] = _native.PrismBuildItem(a._h, fa, items[0][2], None, 0)
     r = L.prism_build_smatrix_batch(nulls, 1, dummy, 1 << 30, None)
     assert r == _native.PRISM_EINVAL and b"S-matrix" in L.prism_last_error()
     assert L.prism_build_smatrix_batch(arr, 3, None, 1 << 30, None) == _native.PRISM_EINVAL
@@ -398,3 +401,65 @@ def test_traffic_hash_ignores_comments_only():
     assert bench._code_only(a) != bench._code_only(c)
     assert '"//kept /* too */"' in bench._code_only(a)
     assert len(bench.kernel_source_sha()) == 16
+
+
+def test_undersized_smatrix_rejected_before_any_launch():
+    # an S-matrix built for another f / alpha_max (fewer beams) must not
+    # reach the kernels: every call that takes S checks its byte size against
+    # prism_smatrix_bytes of its own f and alpha_max
+    p = _plan()
+    L, h = _raw(p)
+    dummy = ctypes.c_void_p(0x1000)
+    L.prism_set_potential_slices(h, dummy)
+    amax1 = p.alpha_max_default(20.0, 1)
+    need = p.smatrix_bytes(1, amax1)
+    small = p.smatrix_bytes(2, p.alpha_max_default(20.0, 2))    # the f = 2 set: 49 beams
+    assert small < need
+    optics = _native.PrismOptics(20.0, 0.0, 0.0)
+    edges = (ctypes.c_double * 2)(40.0, 150.0)
+    det = _native.PrismDetector(1, edges)
+    for nbytes, ok in ((small, False), (need - 1, False), (need, True)):
+        calls = [
+            L.prism_build_smatrix(h, 1, amax1, dummy, nbytes, dummy, 64, None),
+            L.prism_probe_outputs(h, 1, amax1, dummy, nbytes, dummy, 4, ctypes.byref(optics),
+                                  ctypes.byref(det), dummy, dummy, 64, None),
+            L.prism_probe_outputs_accumulate(h, 1, amax1, dummy, nbytes, dummy, 4,
+                                             ctypes.byref(optics), ctypes.byref(det), 0.5, dummy,
+                                             dummy, 64, None),
+            L.prism_probe_cbed(h, 1, amax1, dummy, nbytes, dummy, 4, ctypes.byref(optics), dummy,
+                               dummy, 64, None),
+            L.prism_probe_cbed_accumulate(h, 1, amax1, dummy, nbytes, dummy, 4,
+                                          ctypes.byref(optics), 0.5, dummy, dummy, 64, None),
+        ]
+        for r in calls:
+            if ok:   # the size passes; the 64-byte workspace is what fails
+                assert r == _native.PRISM_ENOSPACE
+            else:
+                assert r == _native.PRISM_EINVAL
+                assert b"prism_smatrix_bytes" in L.prism_last_error()
+    item = (_native.PrismBuildItem * 1)()
+    item[0] = _native.PrismBuildItem(h, 1, amax1, dummy, small)
+    r = L.prism_build_smatrix_batch(item, 1, dummy, 1 << 30, None)
+    assert r == _native.PRISM_EINVAL and b"prism_smatrix_bytes" in L.prism_last_error()
+
+
+@pytest.mark.parametrize("n,cell,E,alpha", [(128, 12.8, 80.0, 20.0), (1024, 40.0, 200.0, 25.0),
+                                            (2048, 80.0, 80.0, 20.0), (384, 38.4, 80.0, 11.5)])
+def test_alpha_max_and_active_beams_match_the_oracle(n, cell, E, alpha):
+    p = Plan(n, cell, E, [2.0])
+    lam = O.wavelength(E)
+    for f in (1, 2, 4, 8):
+        if n % (2 * f):
+            continue
+        amax = p.alpha_max_default(alpha, f)
+        ref = O.default_alpha_max(alpha * 1e-3, f, lam, 1.0 / cell) * 1e3
+        assert abs(amax - ref) <= 1e-12 * ref
+        beams = O.beam_set(n, cell, lam, f, amax * 1e-3)
+        optics = dict(alpha_mrad=alpha)
+        _, A = O.prism_coefficients(beams, f, cell, lam, optics, 0.0, 0.0)
+        assert p.active_beam_count(f, amax, optics) == int(A.sum())
+    L, h = _raw(p)
+    v = ctypes.c_double()
+    assert L.prism_alpha_max(h, 0, alpha, ctypes.byref(v)) == _native.PRISM_EINVAL
+    assert L.prism_alpha_max(h, 1, -1.0, ctypes.byref(v)) == _native.PRISM_EINVAL
+    assert L.prism_alpha_max(None, 1, alpha, ctypes.byref(v)) == _native.PRISM_EINVAL
