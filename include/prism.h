@@ -230,6 +230,28 @@ int prism_probe_outputs(prism_plan* plan, int f, double alpha_max_mrad, const vo
                         const prism_optics* optics, const prism_detector* detector,
                         double* out_dev, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * prism_probe_outputs with no workspace argument. Its scratch is a
+ * library-held device array of PRISM_NOALLOC_SCRATCH_BYTES per GPU, part of
+ * the library's code object (each GPU the library runs on holds one until
+ * the process ends). Results equal prism_probe_outputs'.
+ * Limit: PRISM_ENOSPACE, before anything is enqueued, when the probe step's
+ * minimum workspace (prism_probe_workspace_bytes) exceeds the array, e.g.
+ * 305 active beams on a 512^2 S-matrix (649 MiB in FP32, 329 MiB in BF16);
+ * 69 active beams at 512^2 need 193 MiB. Other errors as
+ * prism_probe_outputs.
+ * Every call on one GPU shares that GPU's array, and it keeps the last
+ * call's contents: calls that overlap on one GPU (other streams, other host
+ * threads) race and must be ordered by the caller. Nothing in the array has
+ * to start at zero: each call writes every scratch value it reads. */
+#define PRISM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int prism_probe_outputs_noalloc(prism_plan* plan, int f, double alpha_max_mrad,
+                                const void* smatrix_dev, size_t smatrix_bytes,
+                                const double* probe_xy_dev, int n_probes,
+                                const prism_optics* optics, const prism_detector* detector,
+                                double* out_dev, void* stream);
+
 /* The same probe step with the full diffraction pattern as output (Fig. 1f:
  * the CBED alternative to virtual detectors): cbed_dev float32 [P][W][W],
  * I(kw) = |FFT_W psi|^2 / W^2 with both axes in W-point fftfreq order (window

@@ -211,6 +211,22 @@ class Plan:
         self._probe_outputs(None, f, alpha_max_mrad, smatrix, probe_xy, optics, edges_mrad, out,
                             workspace, stream)
 
+    def probe_outputs_noalloc(self, f, alpha_max_mrad, smatrix, probe_xy, optics, edges_mrad,
+                              out, stream=None):
+        """probe_outputs without a workspace: the library-held scratch of
+        prism_probe_outputs_noalloc (calls overlapping on one GPU race)."""
+        import torch
+        det = _Det(edges_mrad)
+        P = probe_xy.shape[0]
+        _check_dev(probe_xy, torch.float64, 2 * P, "probe_xy")
+        _check_dev(out, torch.float64, P * det.edges.shape[0], "out")
+        _check_dev(smatrix, torch.complex64, None, "smatrix")
+        o = _optics(optics)
+        _native.check(self._L.prism_probe_outputs_noalloc(
+            self._h, int(f), float(alpha_max_mrad), _ptr(smatrix), _nbytes(smatrix),
+            _ptr(probe_xy), int(P), ctypes.byref(o), ctypes.byref(det.struct), _ptr(out),
+            _stream_ptr(stream)))
+
     def probe_outputs_accumulate(self, f, alpha_max_mrad, smatrix, probe_xy, optics, edges_mrad,
                                  weight, out, workspace, stream=None):
         """As probe_outputs, but out += weight * result (frozen-phonon averaging)."""

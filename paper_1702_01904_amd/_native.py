@@ -18,6 +18,7 @@ PRISM_MAX_DET = 32
 PRISM_PREC_FP32 = 0
 PRISM_PREC_BF16 = 1
 PRISM_PREC_FP16 = 2
+PRISM_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 EXPORTS = (
     "prism_plan_create", "prism_plan_destroy", "prism_wavelength", "prism_alpha_max",
@@ -25,7 +26,8 @@ EXPORTS = (
     "prism_multislice_workspace_bytes", "prism_probe_workspace_bytes", "prism_probe_group",
     "prism_probe_order",
     "prism_set_probe_precision", "prism_set_potential_slices", "prism_build_smatrix",
-    "prism_probe_outputs", "prism_probe_cbed", "prism_multislice_outputs",
+    "prism_probe_outputs", "prism_probe_outputs_noalloc", "prism_probe_cbed",
+    "prism_multislice_outputs",
     "prism_probe_outputs_accumulate", "prism_probe_cbed_accumulate",
     "prism_multislice_outputs_accumulate", "prism_build_batch_workspace_bytes",
     "prism_build_smatrix_batch", "prism_server_workspace_bytes", "prism_server_create",
@@ -103,6 +105,9 @@ def lib():
         "prism_probe_outputs": (I, [P, I, D, P, ctypes.c_size_t, P, I,
                                     ctypes.POINTER(PrismOptics), ctypes.POINTER(PrismDetector), P,
                                     P, ctypes.c_size_t, P]),
+        "prism_probe_outputs_noalloc": (I, [P, I, D, P, ctypes.c_size_t, P, I,
+                                            ctypes.POINTER(PrismOptics),
+                                            ctypes.POINTER(PrismDetector), P, P]),
         "prism_probe_cbed": (I, [P, I, D, P, ctypes.c_size_t, P, I, ctypes.POINTER(PrismOptics),
                                  P, P, ctypes.c_size_t, P]),
         "prism_multislice_outputs": (I, [P, P, I, ctypes.POINTER(PrismOptics),

@@ -23,8 +23,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INC}", f"-I{SRC}", "-Wall", "-Wno-u
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-fno-signed-zeros"]
 
-SOURCES = ["slice_kernels.hip", "probe_kernels.hip", "probe16_kernels.hip", "plan.cpp",
-           "server.cpp"]
+SOURCES = ["slice_kernels.hip", "probe_kernels.hip", "probe16_kernels.hip", "scratch.hip",
+           "plan.cpp", "server.cpp"]
 
 
 def _cmd(src, obj):

@@ -463,3 +463,24 @@ def test_alpha_max_and_active_beams_match_the_oracle(n, cell, E, alpha):
     assert L.prism_alpha_max(h, 0, alpha, ctypes.byref(v)) == _native.PRISM_EINVAL
     assert L.prism_alpha_max(h, 1, -1.0, ctypes.byref(v)) == _native.PRISM_EINVAL
     assert L.prism_alpha_max(None, 1, alpha, ctypes.byref(v)) == _native.PRISM_EINVAL
+
+
+def test_noalloc_rejects_probe_steps_beyond_its_scratch():
+    # fcc1024 at f = 4: 305 active beams, a 649 MiB minimum FP32 workspace,
+    # more than the 256 MiB library-held scratch; refused before any device call
+    p = Plan(1024, 40.0, 200.0, [2.0] * 50)
+    L, h = _raw(p)
+    amax = p.alpha_max_default(25.0, 4)
+    _, mn = p.probe_workspace_bytes(4, amax, dict(alpha_mrad=25.0))
+    assert mn > _native.PRISM_NOALLOC_SCRATCH_BYTES
+    dummy = ctypes.c_void_p(0x1000)
+    optics = _native.PrismOptics(25.0, 0.0, 0.0)
+    edges = (ctypes.c_double * 2)(0.0, 200.0)
+    det = _native.PrismDetector(1, edges)
+    r = L.prism_probe_outputs_noalloc(h, 4, amax, dummy, SBIG, dummy, 16, ctypes.byref(optics),
+                                      ctypes.byref(det), dummy, None)
+    assert r == _native.PRISM_ENOSPACE and b"library-held" in L.prism_last_error()
+    # the probe step's own checks come first
+    r = L.prism_probe_outputs_noalloc(h, 3, amax, dummy, SBIG, dummy, 16, ctypes.byref(optics),
+                                      ctypes.byref(det), dummy, None)
+    assert r == _native.PRISM_EINVAL
