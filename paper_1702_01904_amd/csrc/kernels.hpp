@@ -52,6 +52,18 @@ struct ProbeOptics {
   double norm;     // incident-wave normalisation factor
 };
 
+// Launch shapes that do not change any result (work distribution only):
+// the four-step slice passes' iteration caps and smallest grids, and the
+// window sum's workgroups per probe group (union tiles of one window /
+// window_tile_div). Set per plan (prism_set_tuning); defaults below.
+struct LaunchTuning {
+  int row_iters = 16;      // most row groups per workgroup (power of two)
+  int row_min_wg = 512;    // fewest workgroups per row-pass launch
+  int col_iters = 8;       // most column tiles per workgroup (power of two)
+  int col_min_wg = 256;    // fewest workgroups per column-pass launch
+  int window_tile_div = 4;
+};
+
 hipError_t launch_twiddles(float2* tw, int L, hipStream_t st);
 hipError_t launch_transmission(const float* phase, float2* trans, size_t count, float scale,
                                hipStream_t st);
@@ -74,10 +86,12 @@ hipError_t launch_twiddles2(float2* tw2, int n, hipStream_t st);
 // (device table of per-wave transmission bases: waves of several specimens
 // in one launch).
 hipError_t launch_row_pass(float2* state, int nwaves, int n, const float2* trans_p,
-                           const float2* twN, const float2* tw2, hipStream_t st,
-                           const float2* const* wtrans = nullptr, size_t soff = 0);
+                           const float2* twN, const float2* tw2, const LaunchTuning& tune,
+                           hipStream_t st, const float2* const* wtrans = nullptr,
+                           size_t soff = 0);
 hipError_t launch_col_pass(float2* state, int nwaves, int n, const float2* prop_p,
-                           const float2* twN, const float2* tw2, hipStream_t st);
+                           const float2* twN, const float2* tw2, const LaunchTuning& tune,
+                           hipStream_t st);
 // Last slice of multislice STEM: FFT_y, propagator, band limit, |Psi|^2/n^2
 // and per-column-tile detector partial sums (double [wave][tiles][n_det]).
 hipError_t launch_col_detect(const float2* state, int nwaves, int n, const float2* prop_p,
@@ -95,10 +109,11 @@ struct ActiveBeam {
   int m, n;   // plane-wave indices
 };
 
-// Probes per group of the packed window sum (they share one union window).
+// Probes per group of the packed window sum (they share one union window):
+// the default for window side w.
 int contract_group(int w);
 // Workgroups per probe group along the union tiles (each loops over tiles).
-int contract_tile_slots(int w);
+int contract_tile_slots(int w, int window_tile_div);
 
 // Low-precision probe step (BF16 or FP16 operands, FP32 accumulation).
 // Operand forms of the packed window sum: 16-bit (BF16, FP16; one 32-bit
@@ -127,7 +142,7 @@ hipError_t launch_alpha16(const double* probe_xy, int p0, int np, const ActiveBe
                           hipStream_t st);
 hipError_t launch_contract16(const void* s16, int n_actp, const void* a16, const int2* origin,
                              int np, int ns, int w, int group, float out_scale, float2* window,
-                             Prec prec, hipStream_t st);
+                             Prec prec, int window_tile_div, hipStream_t st);
 // Detector bins as lists of window pixels (v * W + u of the W x W window),
 // cut into chunks of kWdListChunk entries: bin j owns the chunks
 // off[j] .. off[j+1]), i.e. pix[off[j] 64 .. off[j+1] 64), its last chunk
@@ -138,24 +153,28 @@ struct BinLists {
 };
 constexpr int kWdListChunk = 64;  // one entry per lane of a wave
 constexpr uint16_t kNoPix = 0xFFFF;
-// W = 256: window FFT in two passes (rows in place, then columns fused with
-// |Psi|^2 / W^2 and bin sums) into partial[probe][tile][n_det], tiles =
-// window256_tiles(); reduce with launch_reduce_partials.
-int window256_tiles();
-hipError_t launch_window256(float2* window, int np, const float2* twW, int f,
-                            const DetBins& bins, double* partial, hipStream_t st);
-// W = 256 CBED: cbed[p][ky][kx] = |Psi|^2 / W^2 (float32, fftfreq order).
-hipError_t launch_window256_cbed(float2* window, int np, const float2* twW, float* cbed,
-                                 OutAcc acc, hipStream_t st);
-// Window sides of the LDS window kernels: powers of two 8..128 and the
-// 3 * 2^k / 9 * 2^k sides 24, 48, 72, 96 (multiples of 8 for the first
-// radix-8 stage, at most 96^2 values in LDS); W = 256 has its own passes.
+// Windows larger than 128 (W = 144, 192, 256): window FFT in two passes over
+// the window buffer (rows in place, then tiles of 16 columns fused with
+// |Psi|^2 / W^2 and per-element bin sums) into partial[probe][tile][n_det],
+// tiles = window_big_tiles(w), reduced with launch_reduce_partials; or,
+// with cbed != nullptr, cbed[p][ky][kx] = |Psi|^2 / W^2 (float32, fftfreq
+// order) stored or accumulated by acc. W = 256 runs four-step 16 x 16
+// passes, W = 144 and 192 LDS Stockham passes.
+__host__ __device__ constexpr bool window_big(int w) { return w > 128; }
+int window_big_tiles(int w);
+hipError_t launch_window_big(float2* window, int np, int w, const float2* twW, int f,
+                             const DetBins& bins, double* partial, float* cbed, OutAcc acc,
+                             hipStream_t st);
+// Window sides: in one workgroup's LDS the powers of two 8..128 and the
+// 3 * 2^k / 9 * 2^k sides 12, 18, 24, 36, 48, 72, 96; over HBM (two passes)
+// 144, 192 and 256.
 __host__ __device__ constexpr bool window_side_ok(int w) {
-  return w == 8 || w == 16 || w == 32 || w == 64 || w == 128 || w == 256 || w == 24 ||
-         w == 48 || w == 72 || w == 96;
+  return w == 8 || w == 16 || w == 32 || w == 64 || w == 128 || w == 12 || w == 18 ||
+         w == 24 || w == 36 || w == 48 || w == 72 || w == 96 || w == 144 || w == 192 ||
+         w == 256;
 }
 // Full CBED output: cbed[p][ky][kx] = |FFT_W window_p|^2 / W^2 (float32,
-// window fftfreq order), W <= 128.
+// window fftfreq order), W <= 128 (larger windows: launch_window_big).
 hipError_t launch_window_cbed(const float2* window, int np, int w, const float2* twW,
                               float* cbed, OutAcc acc, hipStream_t st);
 hipError_t launch_window_detect(const float2* window, int np, int w, const float2* twW,

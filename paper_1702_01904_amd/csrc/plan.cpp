@@ -107,6 +107,10 @@ struct prism_plan {
 
   int n = 0;
   int prec = PRISM_PREC_FP32;  // operand precision of the probe-step window sum
+  // launch shapes (prism_set_tuning): none of them changes a result
+  prism::LaunchTuning tune;
+  size_t wave_chunk_bytes = size_t(256) << 20;  // wave state per slice-pass launch
+  int probe_group = 0;                           // probes per window-sum group (0: by W)
   double cell = 0, energy = 0, lam = 0, dq = 0;
   double height = 0;           // total slice thickness (A)
   int H = 0;
@@ -335,16 +339,18 @@ const prism_plan::PixLists* get_pixlists(prism_plan* p, int w, int f, const pris
 // ---------------------------------------------------------------- layouts
 
 constexpr size_t kChunkBytes = size_t(1) << 28;  // preferred probe-window bytes per chunk
-#ifndef PRISM_WAVE_CHUNK_SHIFT
-#define PRISM_WAVE_CHUNK_SHIFT 28
-#endif
-constexpr size_t kWaveChunkBytes = size_t(1) << PRISM_WAVE_CHUNK_SHIFT;  // wave states per chunk
 
 size_t state_bytes(int n) { return (size_t)n * (n / 2) * sizeof(float2); }
 
-int pref_wave_chunk(int n, int count) {
-  const int c = (int)std::max<size_t>(1, kWaveChunkBytes / state_bytes(n));
+// waves per slice-pass launch: the plan's wave-state bytes per launch
+int pref_wave_chunk(const prism_plan* p, int count) {
+  const int c = (int)std::max<size_t>(1, p->wave_chunk_bytes / state_bytes(p->n));
   return std::max(1, std::min(c, count));
+}
+
+// probes per window-sum group for window side w
+int group_of(const prism_plan* p, int w) {
+  return p->probe_group > 0 ? p->probe_group : prism::contract_group(w);
 }
 
 struct SliceWs {
@@ -393,7 +399,7 @@ struct ProbeWs {
   uint32_t* a16;    // packed alpha: [chunk / G][K blocks][2G][32 words]
   int2* origin;
   float2* window;
-  double* partial;  // W = 256: [chunk][tiles][PRISM_MAX_DET] detector partials
+  double* partial;  // W > 128: [chunk][tiles][PRISM_MAX_DET] detector partials
 };
 
 // Operand form of the packed window sum for a plan precision.
@@ -414,7 +420,7 @@ size_t probe_layout(int w, int ns, int n_act, int chunk, int prec, ProbeWs* pw, 
   // per-bin pixel lists (W <= 128), worst case: every bin holds every pixel
   // and a padded last chunk
   pw->pix = c.take<uint16_t>(
-      w == 256 ? 0 : (size_t)PRISM_MAX_DET * ((size_t)w * w + prism::kWdListChunk));
+      prism::window_big(w) ? 0 : (size_t)PRISM_MAX_DET * ((size_t)w * w + prism::kWdListChunk));
   pw->act = c.take<prism::ActiveBeam>(n_act);
   const prism::Prec pk = packed_prec(prec);
   const int n_actp = padded_beams(n_act, pk);
@@ -426,7 +432,8 @@ size_t probe_layout(int w, int ns, int n_act, int chunk, int prec, ProbeWs* pw, 
   pw->a16 = c.take<uint32_t>((size_t)chunk * (n_actp / prism::prec_block_beams(pk)) * 64);
   pw->origin = c.take<int2>(chunk);
   pw->window = c.take<float2>((size_t)chunk * w * w);
-  pw->partial = w == 256 ? c.take<double>((size_t)chunk * prism::window256_tiles() * PRISM_MAX_DET)
+  pw->partial = prism::window_big(w)
+                    ? c.take<double>((size_t)chunk * prism::window_big_tiles(w) * PRISM_MAX_DET)
                          : nullptr;
   return c.used + 256;
 }
@@ -508,7 +515,9 @@ int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, size_t S_b
     if (int r = make_bins(p, d, &bins)) return r;
   const int n = p->n, ns = n / 2, w = n / (2 * f);
   if (!prism::window_side_ok(w))
-    return fail(PRISM_EINVAL, "window side n/(2f) must be 8..256, a power of two or 24, 48, 72, 96");
+    return fail(PRISM_EINVAL,
+                "window side n/(2f) must be a power of two in 8..256 or one of 12, 18, 24, 36, "
+                "48, 72, 96, 144, 192");
   const auto* act = get_active(p, f, amax_mrad, *mn, o);
   const int n_act = (int)act->size();
   if (n_act < 1) return fail(PRISM_EINVAL, "no beam of the set lies inside the probe aperture");
@@ -516,7 +525,7 @@ int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, size_t S_b
   if (!S || !xy || !ws || (want_cbed ? !cbed : !out)) return fail(PRISM_EINVAL, "null device buffer");
   if (S_bytes < smatrix_need(p, *mn))
     return fail(PRISM_EINVAL, "S-matrix buffer smaller than prism_smatrix_bytes for this f and alpha_max");
-  const int G = prism::contract_group(w);
+  const int G = group_of(p, w);
   void* base = aligned_base(ws);
   const size_t avail = ws_bytes;  // layouts include 256 B of alignment slack
   ProbeWs pw;
@@ -528,9 +537,9 @@ int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, size_t S_b
   probe_layout(w, ns, n_act, chunk, prec, &pw, base);
   hipStream_t st = static_cast<hipStream_t>(stream);
   LAUNCH(p, st, "twiddles", prism::launch_twiddles(pw.twW, w, st));
-  // per-bin pixel lists drive the W <= 128 detector; W = 256 bins per element
+  // per-bin pixel lists drive the W <= 128 detector; larger windows bin per element
   const prism_plan::PixLists* pl =
-      (w == 256 || want_cbed) ? nullptr : get_pixlists(p, w, f, bins);
+      (prism::window_big(w) || want_cbed) ? nullptr : get_pixlists(p, w, f, bins);
   if (pl && !pl->pix.empty())
     HIP_TRY(hipMemcpyAsync(pw.pix, pl->pix.data(), pl->pix.size() * sizeof(uint16_t),
                            hipMemcpyHostToDevice, st),
@@ -545,21 +554,22 @@ int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, size_t S_b
   auto window_stage = [&](int np, int p0) -> int {
     if (want_cbed) {
       float* dst = cbed + (size_t)p0 * w * w;
-      if (w == 256) {
-        LAUNCH(p, st, "window256_cbed",
-               prism::launch_window256_cbed(pw.window, np, pw.twW, dst, oa, st));
+      if (prism::window_big(w)) {
+        LAUNCH(p, st, "window_big_cbed",
+               prism::launch_window_big(pw.window, np, w, pw.twW, f, bins, nullptr, dst, oa, st));
       } else {
         LAUNCH(p, st, "window_cbed", prism::launch_window_cbed(pw.window, np, w, pw.twW, dst, oa, st));
       }
       return PRISM_OK;
     }
     double* dst = out + (size_t)p0 * bins.n;
-    if (w == 256) {
-      LAUNCH(p, st, "window256",
-             prism::launch_window256(pw.window, np, pw.twW, f, bins, pw.partial, st));
+    if (prism::window_big(w)) {
+      LAUNCH(p, st, "window_big",
+             prism::launch_window_big(pw.window, np, w, pw.twW, f, bins, pw.partial, nullptr,
+                                      prism::OutAcc{0, 1.0}, st));
       LAUNCH(p, st, "reduce_partials",
-             prism::launch_reduce_partials(pw.partial, np, prism::window256_tiles(), bins.n, dst,
-                                           oa, st));
+             prism::launch_reduce_partials(pw.partial, np, prism::window_big_tiles(w), bins.n,
+                                           dst, oa, st));
     } else {
       LAUNCH(p, st, "window_detect",
              prism::launch_window_detect(pw.window, np, w, pw.twW, pw.pix, pl->lists, dst, oa, st));
@@ -581,7 +591,7 @@ int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, size_t S_b
                                  pw.a16, pw.origin, pr, st));
     LAUNCH(p, st, pr == prism::Prec::kF32 ? "contract" : "contract16",
            prism::launch_contract16(pw.s16, n_actp, pw.a16, pw.origin, np, ns, w, G, out_scale,
-                                    pw.window, pr, st));
+                                    pw.window, pr, p->tune.window_tile_div, st));
     if (int r = window_stage(np, p0)) return r;
   }
   return PRISM_OK;
@@ -602,7 +612,7 @@ int multislice_step(prism_plan* p, const double* xy, int P, const prism_optics* 
   if (!p->phase) return fail(PRISM_ENOTREADY, "potential slices not set");
   const int n = p->n;
   void* base = aligned_base(ws);
-  const int chunk = choose_chunk(p, pref_wave_chunk(n, P), 0, bins.n, ws_bytes);
+  const int chunk = choose_chunk(p, pref_wave_chunk(p, P), 0, bins.n, ws_bytes);
   if (chunk < 1) return fail(PRISM_ENOSPACE, "workspace smaller than the multislice minimum");
   SliceWs w;
   slice_layout(p, chunk, 0, bins.n, &w, base);
@@ -629,9 +639,9 @@ int multislice_step(prism_plan* p, const double* xy, int P, const prism_optics* 
     const int np = std::min(chunk, P - p0);
     LAUNCH(p, st, "probe_init", prism::launch_probe_init(w.state, xy, p0, np, n, po, w.aper, w.twN, st));
     for (int s = 0; s < p->H; ++s) {
-      LAUNCH(p, st, "row_pass", prism::launch_row_pass(w.state, np, n, w.trans + (size_t)s * n * n, w.twN, w.tw2, st));
+      LAUNCH(p, st, "row_pass", prism::launch_row_pass(w.state, np, n, w.trans + (size_t)s * n * n, w.twN, w.tw2, p->tune, st));
       if (s + 1 < p->H) {
-        LAUNCH(p, st, "col_pass", prism::launch_col_pass(w.state, np, n, w.prop + (size_t)s * n, w.twN, w.tw2, st));
+        LAUNCH(p, st, "col_pass", prism::launch_col_pass(w.state, np, n, w.prop + (size_t)s * n, w.twN, w.tw2, p->tune, st));
       } else {
         LAUNCH(p, st, "col_detect", prism::launch_col_detect(w.state, np, n, w.prop + (size_t)s * n, w.twN, bins,
                                          w.partial, st));
@@ -746,7 +756,7 @@ int prism_build_workspace_bytes(const prism_plan* p, int f, double amax_mrad, si
   if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
   const int B = (int)(mn->size() / 2);
   SliceWs w;
-  *pref = slice_layout(p, pref_wave_chunk(p->n, B), B, 0, &w, nullptr);
+  *pref = slice_layout(p, pref_wave_chunk(p, B), B, 0, &w, nullptr);
   *minimum = slice_layout(p, 1, B, 0, &w, nullptr);
   return PRISM_OK;
 }
@@ -756,7 +766,7 @@ int prism_multislice_workspace_bytes(const prism_plan* p, int n_det, size_t* pre
   if (!p || !pref || !minimum) return fail(PRISM_EINVAL, "null argument");
   if (n_det < 1 || n_det > PRISM_MAX_DET) return fail(PRISM_EINVAL, "n_det out of range");
   SliceWs w;
-  *pref = slice_layout(p, pref_wave_chunk(p->n, 1 << 20), 0, n_det, &w, nullptr);
+  *pref = slice_layout(p, pref_wave_chunk(p, 1 << 20), 0, n_det, &w, nullptr);
   *minimum = slice_layout(p, 1, 0, n_det, &w, nullptr);
   return PRISM_OK;
 }
@@ -765,7 +775,7 @@ int prism_probe_group(const prism_plan* p, int f, int* group, int* tx, int* ty) 
   if (!p || !group || !tx || !ty) return fail(PRISM_EINVAL, "null argument");
   if (int r = check_f(p, f)) return r;
   const int w = p->n / (2 * f);
-  *group = prism::contract_group(w);
+  *group = group_of(p, w);
   *tx = 8;
   *ty = *group / 8;
   if (*group == 16) *tx = *ty = 4;
@@ -806,13 +816,52 @@ int prism_probe_workspace_bytes(const prism_plan* cp, int f, double amax_mrad,
   if (int r = check_optics(p, o)) return r;
   const int w = p->n / (2 * f);
   if (!prism::window_side_ok(w))
-    return fail(PRISM_EINVAL, "window side n/(2f) must be 8..256, a power of two or 24, 48, 72, 96");
+    return fail(PRISM_EINVAL,
+                "window side n/(2f) must be a power of two in 8..256 or one of 12, 18, 24, 36, "
+                "48, 72, 96, 144, 192");
   const auto* act = get_active(p, f, amax_mrad, *mn, o);
-  const int G = prism::contract_group(w);
+  const int G = group_of(p, w);
   ProbeWs pw;
   const int ns = p->n / 2;
   *pref = probe_layout(w, ns, (int)act->size(), pref_probe_chunk(w, G), p->prec, &pw, nullptr);
   *minimum = probe_layout(w, ns, (int)act->size(), G, p->prec, &pw, nullptr);
+  return PRISM_OK;
+}
+
+int prism_set_tuning(prism_plan* p, const prism_tuning* t) {
+  if (!p || !t) return fail(PRISM_EINVAL, "null argument");
+  auto pow2_in = [](int v, int hi) { return v == 0 || (v >= 1 && v <= hi && (v & (v - 1)) == 0); };
+  if (!pow2_in(t->row_iters, 64) || !pow2_in(t->col_iters, 64))
+    return fail(PRISM_EINVAL, "row_iters and col_iters must be 0 or powers of two up to 64");
+  if (t->row_min_groups < 0 || t->row_min_groups > (1 << 20) || t->col_min_groups < 0 ||
+      t->col_min_groups > (1 << 20))
+    return fail(PRISM_EINVAL, "row_min_groups and col_min_groups must be in [0, 2^20]");
+  if (t->wave_chunk_mib != 0 && (t->wave_chunk_mib < 16 || t->wave_chunk_mib > 65536))
+    return fail(PRISM_EINVAL, "wave_chunk_mib must be 0 or in [16, 65536]");
+  if (t->probe_group != 0 && t->probe_group != 16 && t->probe_group != 32 && t->probe_group != 64)
+    return fail(PRISM_EINVAL, "probe_group must be 0, 16, 32 or 64");
+  if (t->window_tile_div < 0 || t->window_tile_div > 64)
+    return fail(PRISM_EINVAL, "window_tile_div must be in [0, 64]");
+  const prism::LaunchTuning def;
+  p->tune.row_iters = t->row_iters ? t->row_iters : def.row_iters;
+  p->tune.row_min_wg = t->row_min_groups ? t->row_min_groups : def.row_min_wg;
+  p->tune.col_iters = t->col_iters ? t->col_iters : def.col_iters;
+  p->tune.col_min_wg = t->col_min_groups ? t->col_min_groups : def.col_min_wg;
+  p->tune.window_tile_div = t->window_tile_div ? t->window_tile_div : def.window_tile_div;
+  p->wave_chunk_bytes = (size_t)(t->wave_chunk_mib ? t->wave_chunk_mib : 256) << 20;
+  p->probe_group = t->probe_group;
+  return PRISM_OK;
+}
+
+int prism_get_tuning(const prism_plan* p, prism_tuning* t) {
+  if (!p || !t) return fail(PRISM_EINVAL, "null argument");
+  t->row_iters = p->tune.row_iters;
+  t->row_min_groups = p->tune.row_min_wg;
+  t->col_iters = p->tune.col_iters;
+  t->col_min_groups = p->tune.col_min_wg;
+  t->wave_chunk_mib = (int)(p->wave_chunk_bytes >> 20);
+  t->probe_group = p->probe_group;
+  t->window_tile_div = p->tune.window_tile_div;
   return PRISM_OK;
 }
 
@@ -884,7 +933,7 @@ int prism_build_smatrix(prism_plan* p, int f, double amax_mrad, void* S, size_t 
   if (!p->phase) return fail(PRISM_ENOTREADY, "potential slices not set");
   const int n = p->n, B = (int)(mn->size() / 2);
   void* base = aligned_base(ws);
-  const int chunk = choose_chunk(p, pref_wave_chunk(n, B), B, 0, ws_bytes);
+  const int chunk = choose_chunk(p, pref_wave_chunk(p, B), B, 0, ws_bytes);
   if (chunk < 1) return fail(PRISM_ENOSPACE, "workspace smaller than the build minimum");
   SliceWs w;
   slice_layout(p, chunk, B, 0, &w, base);
@@ -919,8 +968,8 @@ int prism_build_smatrix(prism_plan* p, int f, double amax_mrad, void* S, size_t 
     float2* state = w.state + (size_t)(g % lanes) * sub * n * (n / 2);
     LAUNCH(p, sg, "beam_init", prism::launch_beam_init(state, w.mn, b0, nb, n, f, w.twN, sg));
     for (int s = 0; s < p->H; ++s) {
-      LAUNCH(p, sg, "row_pass", prism::launch_row_pass(state, nb, n, w.trans + (size_t)s * n * n, w.twN, w.tw2, sg));
-      LAUNCH(p, sg, "col_pass", prism::launch_col_pass(state, nb, n, w.prop + (size_t)s * n, w.twN, w.tw2, sg));
+      LAUNCH(p, sg, "row_pass", prism::launch_row_pass(state, nb, n, w.trans + (size_t)s * n * n, w.twN, w.tw2, p->tune, sg));
+      LAUNCH(p, sg, "col_pass", prism::launch_col_pass(state, nb, n, w.prop + (size_t)s * n, w.twN, w.tw2, p->tune, sg));
     }
     LAUNCH(p, sg, "extract", prism::launch_extract(state, nb, n, Sout + (size_t)b0 * splane, w.twH, sg));
   }
@@ -1169,10 +1218,11 @@ int batch_build_group(const prism_build_item* items, const BatchGroup& g, void* 
       for (const Part& pt : parts)
         if (pt.s->H > s) active = pt.w0 + pt.nb;
       LAUNCH(p, st, "row_pass",
-             prism::launch_row_pass(w.state, active, n, nullptr, w.twN, w.tw2, st,
+             prism::launch_row_pass(w.state, active, n, nullptr, w.twN, w.tw2, p->tune, st,
                                     w.wtab, (size_t)s * n * n));
       LAUNCH(p, st, "col_pass",
-             prism::launch_col_pass(w.state, active, n, w.prop + (size_t)s * n, w.twN, w.tw2, st));
+             prism::launch_col_pass(w.state, active, n, w.prop + (size_t)s * n, w.twN, w.tw2,
+                                    p->tune, st));
     }
     for (const Part& pt : parts) {
       const prism_build_item& it = items[pt.s->item];

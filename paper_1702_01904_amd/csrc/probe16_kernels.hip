@@ -474,8 +474,9 @@ hipError_t launch_alpha16(const double* probe_xy, int p0, int np, const ActiveBe
 
 hipError_t launch_contract16(const void* s16, int n_actp, const void* a16, const int2* origin,
                              int np, int ns, int w, int group, float out_scale, float2* window,
-                             Prec prec, hipStream_t st) {
-  const dim3 grid((unsigned)contract_tile_slots(w), (unsigned)((np + group - 1) / group));
+                             Prec prec, int window_tile_div, hipStream_t st) {
+  const dim3 grid((unsigned)contract_tile_slots(w, window_tile_div),
+                  (unsigned)((np + group - 1) / group));
   const uint32_t* s = static_cast<const uint32_t*>(s16);
   const uint32_t* a = static_cast<const uint32_t*>(a16);
   const int rowlen = n_actp * prec_words(prec);  // 32-bit words per packed pixel row

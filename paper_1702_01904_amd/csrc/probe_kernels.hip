@@ -17,11 +17,9 @@ namespace prism {
 namespace {
 
 // Probe grouping of the window sum (shared with probe16_kernels.hip): probes
-// per group for W >= 128, and the union tiles of 128 pixels that one
-// workgroup walks for a single window.
+// per group for W >= 128, and the union tiles of 128 pixels.
 constexpr int kCG128 = 64;
 constexpr int kCTile = 128;
-constexpr int kCTilesPerWg = 4;
 
 // ---------------------------------------------------------------------------
 // W = 256 windows (too large for one workgroup's LDS): the 2D FFT runs as
@@ -129,6 +127,86 @@ __global__ __launch_bounds__(256) void k_window_cols256_detect(const float2* __r
 }
 
 // ---------------------------------------------------------------------------
+// W = 144 and 192 (more than one workgroup's LDS, not a square of a register
+// DFT length): the same two passes over the window buffer with the LDS
+// Stockham transforms: rows (kBigRows per workgroup) in place, then tiles of
+// 16 columns with |Psi|^2 / W^2 and per-element binning (or CBED) as for
+// W = 256.
+constexpr int kBigRows = 8, kBigTC = 16, kBigNT = 256;
+
+template <int W>
+__global__ __launch_bounds__(kBigNT) void k_window_rows_lds(float2* __restrict__ window,
+                                                            const float2* __restrict__ twW) {
+  using B = RowBatch<W, kBigRows>;
+  __shared__ float2 lds[lds_padded(W * kBigRows)];
+  __shared__ float2 tw[W];
+  const int tid = threadIdx.x;
+  load_twiddles<W, kBigNT>(tw, twW, tid);
+  float2* rows = window + (size_t)blockIdx.x * kBigRows * W;
+  for (int e = tid; e < kBigRows * W; e += kBigNT) lds[lpad(e)] = rows[e];
+  __syncthreads();
+  fft_lds<B, kBigNT, false>(lds, tw, tid);
+  for (int e = tid; e < kBigRows * W; e += kBigNT) rows[e] = lds[lpad(e)];
+}
+
+template <int W, bool CBED>
+__global__ __launch_bounds__(kBigNT) void k_window_cols_lds(const float2* __restrict__ window,
+                                                            const float2* __restrict__ twW, int f,
+                                                            DetBins bins,
+                                                            double* __restrict__ partial,
+                                                            float* __restrict__ cbed, OutAcc oa) {
+  constexpr int TILES = W / kBigTC;
+  using B = Batch<W, kBigTC, kBigTC, 0, 1, kBigTC, true>;  // [y][c], column c is sequence c
+  __shared__ float2 lds[lds_padded(W * kBigTC)];
+  __shared__ float2 tw[W];
+  __shared__ double red[CBED ? 1 : kMaxDet][kBigNT / 64];
+  const int tid = threadIdx.x;
+  load_twiddles<W, kBigNT>(tw, twW, tid);
+  const size_t p = blockIdx.x / TILES;
+  const int tile = blockIdx.x % TILES;
+  const float2* src = window + p * W * W + tile * kBigTC;
+  for (int e = tid; e < W * kBigTC; e += kBigNT) lds[lpad(e)] = src[(e / kBigTC) * W + e % kBigTC];
+  __syncthreads();
+  fft_lds<B, kBigNT, false>(lds, tw, tid);
+  const double inv_w2 = 1.0 / ((double)W * (double)W);
+  if constexpr (CBED) {
+    float* dst = cbed + p * W * W + tile * kBigTC;
+    for (int e = tid; e < W * kBigTC; e += kBigNT) {
+      const float2 z = lds[lpad(e)];
+      put_out(dst + (e / kBigTC) * W + e % kBigTC, ((double)z.x * z.x + (double)z.y * z.y) * inv_w2,
+              oa);
+    }
+    return;
+  }
+  double acc[kMaxDet];
+#pragma unroll
+  for (int q = 0; q < kMaxDet; ++q) acc[q] = 0.0;
+  for (int e = tid; e < W * kBigTC; e += kBigNT) {
+    const int kyi = e / kBigTC, col = tile * kBigTC + e % kBigTC;
+    const long long kx = col < W / 2 ? col : col - W, ky = kyi < W / 2 ? kyi : kyi - W;
+    const long long kk = (long long)f * f * (kx * kx + ky * ky);
+    const float2 z = lds[lpad(e)];
+    const double I = ((double)z.x * z.x + (double)z.y * z.y) * inv_w2;
+#pragma unroll
+    for (int q = 0; q < kMaxDet; ++q)
+      if (q < bins.n && kk >= bins.lo[q] && kk < bins.hi[q]) acc[q] += I;
+  }
+#pragma unroll
+  for (int q = 0; q < kMaxDet; ++q) {
+    if (q < bins.n) {  // uniform
+      const double sum = wave_sum(acc[q]);
+      if ((tid & 63) == 0) red[q][tid >> 6] = sum;
+    }
+  }
+  __syncthreads();
+  if (tid < bins.n) {
+    double sm = 0.0;
+    for (int w = 0; w < kBigNT / 64; ++w) sm += red[tid][w];
+    partial[((size_t)p * TILES + tile) * bins.n + tid] = sm;
+  }
+}
+
+// ---------------------------------------------------------------------------
 #ifndef PRISM_WD_PREFETCH
 #define PRISM_WD_PREFETCH 0  // window kernel: load the next probe during the current one
 #endif
@@ -174,15 +252,18 @@ __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __rest
                                                             OutAcc oa) {
   constexpr int NT = wd_nt(W);
   constexpr int NW = NT / 64;
+  // first row stage, applied from registers: radix 8 where W allows, else
+  // 4, 2 or 3 (W = 12, 36: 4; W = 18: 2)
+  constexpr int R0 = W % 8 == 0 ? 8 : (W % 4 == 0 ? 4 : (W % 2 == 0 ? 2 : 3));
   using Rows = RowBatch<W, W>;
   using Cols = Batch<W, W, W, 0, 1, W, true>;
-  using S8 = StageShape<Rows, 8, NT>;
+  using S8 = StageShape<Rows, R0, NT>;
   __shared__ float2 lds[lds_padded(W * W)];
   __shared__ float2 tw[W];
   __shared__ double red[CBED ? 1 : kMaxDet][NW];
   const int tid = threadIdx.x;
   load_twiddles<W, NT>(tw, twW, tid);
-  float2 nxt[S8::PER][8];
+  float2 nxt[S8::PER][R0];
   auto load = [&](int p) {  // first row stage of window p
     const float2* src = window + (size_t)p * W * W;
 #pragma unroll
@@ -192,7 +273,7 @@ __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __rest
         int row, j;
         stage_coords<Rows, S8::NB>(b, row, j);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) nxt[q][r] = src[row * W + j + r * (W / 8)];
+        for (int r = 0; r < R0; ++r) nxt[q][r] = src[row * W + j + r * (W / R0)];
       }
     }
   };
@@ -200,17 +281,17 @@ __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __rest
   const double inv_w2 = 1.0 / ((double)W * (double)W);
 #pragma unroll 1
   for (int p = blockIdx.x; p < np; p += gridDim.x) {
-    float2 v[S8::PER][8];
+    float2 v[S8::PER][R0];
     if (!PRISM_WD_PREFETCH) load(p);
 #pragma unroll
     for (int q = 0; q < S8::PER; ++q)
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[q][r] = nxt[q][r];
+      for (int r = 0; r < R0; ++r) v[q][r] = nxt[q][r];
     if (PRISM_WD_PREFETCH)
       load(min(p + (int)gridDim.x, np - 1));  // the last round re-reads its own window
-    stage_out<Rows, 8, 1, NT, false>(lds, tid, v);
+    stage_out<Rows, R0, 1, NT, false>(lds, tid, v);
     __syncthreads();
-    fft_from<Rows, NT, false, 8>(lds, tw, tid);
+    fft_from<Rows, NT, false, R0>(lds, tw, tid);
     fft_lds<Cols, NT, false>(lds, tw, tid);
     if constexpr (CBED) {
       float* dst = cbed + (size_t)p * W * W;
@@ -270,33 +351,39 @@ inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 
 
 int contract_group(int w) { return w >= 128 ? kCG128 : (w >= 64 ? 32 : 16); }
 
-int contract_tile_slots(int w) {
+int contract_tile_slots(int w, int window_tile_div) {
   const int own = (w * w + kCTile - 1) / kCTile;  // tiles of one window
-  return std::max(1, own / kCTilesPerWg);
+  return std::max(1, own / std::max(1, window_tile_div));
 }
 
-int window256_tiles() { return kW4 / 16; }
+int window_big_tiles(int w) { return w / 16; }
 
-hipError_t launch_window256(float2* window, int np, const float2* twW, int f,
-                            const DetBins& bins, double* partial, hipStream_t st) {
-  hipLaunchKernelGGL(k_window_rows256, dim3((unsigned)((size_t)np * kW4 / kR4)), dim3(256), 0, st,
-                     window, twW);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_window_cols256_detect<false>, dim3((unsigned)((size_t)np * window256_tiles())),
-                     dim3(256), 0, st, window, twW, f, bins, partial, (float*)nullptr, OutAcc{});
-  return hipGetLastError();
-}
-
-hipError_t launch_window256_cbed(float2* window, int np, const float2* twW, float* cbed,
-                                 OutAcc acc, hipStream_t st) {
-  hipLaunchKernelGGL(k_window_rows256, dim3((unsigned)((size_t)np * kW4 / kR4)), dim3(256), 0, st,
-                     window, twW);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  DetBins none{};
-  hipLaunchKernelGGL(k_window_cols256_detect<true>, dim3((unsigned)((size_t)np * window256_tiles())),
-                     dim3(256), 0, st, window, twW, 1, none, (double*)nullptr, cbed, acc);
+hipError_t launch_window_big(float2* window, int np, int w, const float2* twW, int f,
+                             const DetBins& bins, double* partial, float* cbed, OutAcc acc,
+                             hipStream_t st) {
+  const bool want_cbed = cbed != nullptr;
+  if (w == kW4) {
+    hipLaunchKernelGGL(k_window_rows256, dim3((unsigned)((size_t)np * kW4 / kR4)), dim3(256), 0,
+                       st, window, twW);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 grid((unsigned)((size_t)np * window_big_tiles(w)));
+    if (want_cbed)
+      hipLaunchKernelGGL(k_window_cols256_detect<true>, grid, dim3(256), 0, st, window, twW, f,
+                         bins, (double*)nullptr, cbed, acc);
+    else
+      hipLaunchKernelGGL(k_window_cols256_detect<false>, grid, dim3(256), 0, st, window, twW, f,
+                         bins, partial, (float*)nullptr, OutAcc{});
+    return hipGetLastError();
+  }
+#define WBIG(WW)                                                                                 case WW: {                                                                                       hipLaunchKernelGGL(k_window_rows_lds<WW>, dim3((unsigned)((size_t)np * WW / kBigRows)),                           dim3(kBigNT), 0, st, window, twW);                                          hipError_t e = hipGetLastError();                                                              if (e != hipSuccess) return e;                                                                 const dim3 grid((unsigned)((size_t)np * (WW / kBigTC)));                                       if (want_cbed)                                                                                   hipLaunchKernelGGL((k_window_cols_lds<WW, true>), grid, dim3(kBigNT), 0, st, window, twW,                          f, bins, (double*)nullptr, cbed, acc);                                    else                                                                                             hipLaunchKernelGGL((k_window_cols_lds<WW, false>), grid, dim3(kBigNT), 0, st, window,                             twW, f, bins, partial, (float*)nullptr, OutAcc{});                        break;                                                                                       }
+  switch (w) {
+    WBIG(144)
+    WBIG(192)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef WBIG
   return hipGetLastError();
 }
 
@@ -323,6 +410,9 @@ hipError_t launch_window_detect(const float2* window, int np, int w, const float
     WD(48)
     WD(72)
     WD(96)
+    WD(12)
+    WD(18)
+    WD(36)
     default:
       return hipErrorInvalidValue;
   }
@@ -350,6 +440,9 @@ hipError_t launch_window_cbed(const float2* window, int np, int w, const float2*
     WC(48)
     WC(72)
     WC(96)
+    WC(12)
+    WC(18)
+    WC(36)
     default:
       return hipErrorInvalidValue;
   }

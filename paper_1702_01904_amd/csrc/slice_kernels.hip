@@ -218,12 +218,10 @@ __global__ __launch_bounds__(kRowNT) void k_row_pass(float2* __restrict__ state,
 //            w_n^{ce}, one LDS transpose, lane e transforms over c and
 //            stores the outputs e + R g with |kx| < n/4.
 // Each wave owns its LDS rows, so the transposes need only wave-level
-// ordering. A workgroup walks `iters` row groups; each wave loads the next
-// row's inputs and the current row's t_p while it computes.
-#ifndef PRISM_ROW4_ITER
-#define PRISM_ROW4_ITER 16   // most row groups per workgroup
-#endif
-constexpr int kRow4Iter = PRISM_ROW4_ITER;
+// ordering. Each lane keeps its R - 1 twiddles w_n^{jc} in registers for the
+// whole kernel (no table reads between the transforms). A workgroup walks
+// `iters` row groups; each wave loads the next row's inputs and the current
+// row's t_p while it computes.
 
 // Raw buffer resource over count complex values at p (gfx9 word 3), and
 // 8-byte loads / stores at vector offset voff + scalar offset soff (bytes).
@@ -258,14 +256,10 @@ __global__ __launch_bounds__(256) void k_row_pass4(float2* __restrict__ state,
   constexpr int RPW = 64 / R;             // rows per wave
   constexpr int RS = R * LS + 8;          // LDS row stride (float2)
   constexpr int GROUP = 4 * RPW;          // rows per workgroup iteration
-  __shared__ float2 twl[R * R];
   __shared__ float2 lds[4 * RPW * RS];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int j = lane % R, rw = lane / R;
-  for (int i = tid; i < R * R; i += 256) twl[i] = tw2[i];
-  __syncthreads();
   float2* L = lds + (wv * RPW + rw) * RS;
-  const float2* twj = twl + j;
   const size_t row_base = (size_t)blockIdx.x * (GROUP * iters) + wv * RPW + rw;
 
   float2 s[2 * Q];  // compact inputs of the next row: a < Q, then a >= R - Q
@@ -282,7 +276,14 @@ __global__ __launch_bounds__(256) void k_row_pass4(float2* __restrict__ state,
     for (int a = 0; a < Q; ++a) s[Q + a] = buf_load(rs, lane_off, soff + (R * (R - Q + a) - H2) * 8);
   };
   load_src(0, true);
-  // wait here for the first row (s_waitcnt vmcnt(0)) so that the loop head
+  // this lane's four-step twiddles w_n^{jc}, c = 1 .. R-1 (the same values
+  // serve the inverse, conjugated, and the forward transform), held in
+  // registers for the whole loop
+  float2 tw[R - 1];
+#pragma unroll
+  for (int c = 1; c < R; ++c) tw[c - 1] = tw2[c * R + j];
+  // wait here for the first row and the twiddles (s_waitcnt vmcnt(0)) so
+  // that the loop head
   // carries no pending load and never waits for the previous row's stores
   __builtin_amdgcn_s_waitcnt(0x0F70);
 #pragma unroll 1
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(256) void k_row_pass4(float2* __restrict__ state,
     }
     dft_reg<R, true>(v);
 #pragma unroll
-    for (int c = 0; c < R; ++c) L[c * LS + j] = c ? cmulc(v[c], twj[c * R]) : v[c];
+    for (int c = 0; c < R; ++c) L[c * LS + j] = c ? cmulc(v[c], tw[c - 1]) : v[c];
     wave_sync();
 #pragma unroll
     for (int b = 0; b < R; ++b) v[b] = L[j * LS + b];
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(256) void k_row_pass4(float2* __restrict__ state,
     dft_reg<R, false>(v);
     wave_sync();
 #pragma unroll
-    for (int e = 0; e < R; ++e) L[e * LS + j] = e ? cmul(v[e], twj[e * R]) : v[e];
+    for (int e = 0; e < R; ++e) L[e * LS + j] = e ? cmul(v[e], tw[e - 1]) : v[e];
     wave_sync();
 #pragma unroll
     for (int c = 0; c < R; ++c) v[c] = L[j * LS + c];
@@ -343,13 +344,9 @@ __global__ __launch_bounds__(256) void k_row_pass4(float2* __restrict__ state,
 //             (m1, c) transforms over k1 and stores y = m1 + R m2.
 // A workgroup walks `iters` tiles, loading the next tile while it
 // computes the current one.
-#ifndef PRISM_COL4_ITER
-#define PRISM_COL4_ITER 8    // most tiles per workgroup
-#endif
 #ifndef PRISM_COL4_TC32
 #define PRISM_COL4_TC32 16   // columns per tile at n = 1024
 #endif
-constexpr int kCol4Iter = PRISM_COL4_ITER;
 
 template <int R, int TC>
 __global__ __launch_bounds__(TC * R) __attribute__((amdgpu_waves_per_eu(2))) void k_col_pass4(float2* __restrict__ state,
@@ -402,33 +399,68 @@ __global__ __launch_bounds__(TC * R) __attribute__((amdgpu_waves_per_eu(2))) voi
     load_tile(min(it + 1, iters - 1) * nwg + g, it + 1 < iters);
     dft_reg<R, false>(v);
 #pragma unroll
-    for (int k1 = 0; k1 < R; ++k1) L[k1 * LS + b] = k1 ? cmul(v[k1], twb[k1 * R]) : v[k1];
+    for (int k1 = 0; k1 < R; ++k1) L[k1 * LS + b] = v[k1];
     __syncthreads();
     const int jj = c0 + c;
     const int kx = jj < H2 / 2 ? jj : jj - H2;
-    const float2 px = cscale(prop[kx & (N - 1)], inv_n);
+    // P_p(kx) from the same LDS table as P_p(ky) (compact index jj): a
+    // global load here would be waited for together with the next tile's
+    // loads (vector memory counts complete in order)
+    const float2 px = cscale(pyl[jj], inv_n);
+    // the twiddle w_n^{bb k1} is applied on the reading side (the table is
+    // symmetric, so the reading lane k1 = b indexes it by bb): the element
+    // and twiddle reads go out together instead of one twiddle read waited
+    // for per LDS write
+    {
+      float2 tw[R - 1];
 #pragma unroll
-    for (int bb = 0; bb < R; ++bb) v[bb] = L[b * LS + bb];
+      for (int bb = 0; bb < R; ++bb) v[bb] = L[b * LS + bb];
+#pragma unroll
+      for (int bb = 1; bb < R; ++bb) tw[bb - 1] = twb[bb * R];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int bb = 1; bb < R; ++bb) v[bb] = cmul(v[bb], tw[bb - 1]);
+    }
     dft_reg<R, false>(v);  // lane (k1 = b, c): ky index b + R k2
+    {
+      // P_p(ky) of the kept rows, read together; the band limit is a select
+      // on the computed product (no branch per element)
+      float2 p2[2 * Q];
 #pragma unroll
-    for (int k2 = 0; k2 < R; ++k2) {
-      if (k2 < Q || k2 >= R - Q) {
-        const int kyi = b + R * k2;
-        const int ky = kyi < H2 ? kyi : kyi - N;
-        const float2 p2 = pyl[k2 < Q ? kyi : kyi - H2];
-        v[k2] = 16 * (kx * kx + ky * ky) < N * N ? cmul(cmul(v[k2], px), p2)
-                                                  : make_float2(0.f, 0.f);
-      } else {
-        v[k2] = make_float2(0.f, 0.f);
+      for (int k2 = 0; k2 < 2 * Q; ++k2) {
+        const int kyi = b + R * (k2 < Q ? k2 : k2 + R - 2 * Q);
+        p2[k2] = pyl[k2 < Q ? kyi : kyi - H2];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k2 = 0; k2 < R; ++k2) {
+        if (k2 < Q || k2 >= R - Q) {
+          const int kyi = b + R * k2;
+          const int ky = kyi < H2 ? kyi : kyi - N;
+          float2 m = cmul(cmul(v[k2], px), p2[k2 < Q ? k2 : k2 - (R - 2 * Q)]);
+          asm volatile("" : "+v"(m.x), "+v"(m.y));
+          const bool keep = 16 * (kx * kx + ky * ky) < N * N;
+          v[k2] = make_float2(keep ? m.x : 0.f, keep ? m.y : 0.f);
+        } else {
+          v[k2] = make_float2(0.f, 0.f);
+        }
       }
     }
     dft_reg<R, true>(v);  // over k2 -> m1
     __syncthreads();
 #pragma unroll
-    for (int m1 = 0; m1 < R; ++m1) L[m1 * LS + b] = m1 ? cmulc(v[m1], twb[m1 * R]) : v[m1];
+    for (int m1 = 0; m1 < R; ++m1) L[m1 * LS + b] = v[m1];
     __syncthreads();
+    {
+      float2 tw[R - 1];
 #pragma unroll
-    for (int k1 = 0; k1 < R; ++k1) v[k1] = L[b * LS + k1];
+      for (int k1 = 0; k1 < R; ++k1) v[k1] = L[b * LS + k1];
+#pragma unroll
+      for (int k1 = 1; k1 < R; ++k1) tw[k1 - 1] = twb[k1 * R];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k1 = 1; k1 < R; ++k1) v[k1] = cmulc(v[k1], tw[k1 - 1]);
+    }
     dft_reg<R, true>(v);  // lane (m1 = b, c): y = b + R m2
     const __amdgpu_buffer_rsrc_t rd = wave_rsrc(state + (size_t)w * N * H2, N * H2);
 #pragma unroll
@@ -730,16 +762,16 @@ static int pick_iters(int units, int maxit, int min_wgs) {
 }
 
 hipError_t launch_row_pass(float2* state, int nwaves, int n, const float2* trans_p,
-                           const float2* twN, const float2* tw2, hipStream_t st,
-                           const float2* const* wtrans, size_t soff) {
+                           const float2* twN, const float2* tw2, const LaunchTuning& tune,
+                           hipStream_t st, const float2* const* wtrans, size_t soff) {
   // row groups of 4 waves x 64/R rows; the iteration count is the largest
-  // power of two (up to kRow4Iter) that divides them and still leaves two
-  // workgroups per compute unit
+  // power of two (up to tune.row_iters) that divides them and still leaves
+  // tune.row_min_wg workgroups
   const bool wt = wtrans != nullptr;
   if (n == 1024 || n == 256) {
     const int R = n == 1024 ? 32 : 16;
     const int groups = nwaves * n / (4 * 64 / R);
-    const int it = pick_iters(groups, kRow4Iter, 512);
+    const int it = pick_iters(groups, tune.row_iters, tune.row_min_wg);
     const dim3 grid((unsigned)(groups / it));
 #define ROW4(RR, WW)                                                                            \
   hipLaunchKernelGGL((k_row_pass4<RR, WW>), grid, dim3(256), 0, st, state, trans_p, wtrans, soff, \
@@ -769,18 +801,20 @@ hipError_t launch_row_pass(float2* state, int nwaves, int n, const float2* trans
 int col_tiles(int n) { return (n / 2) / col_tc(n); }
 
 hipError_t launch_col_pass(float2* state, int nwaves, int n, const float2* prop_p,
-                           const float2* twN, const float2* tw2, hipStream_t st) {
-  // tiles per launch: nwaves x (n/2) / (256/R), walked kCol4Iter at a time
+                           const float2* twN, const float2* tw2, const LaunchTuning& tune,
+                           hipStream_t st) {
+  // tiles per launch: nwaves x (n/2) / TC, walked up to tune.col_iters at a
+  // time while tune.col_min_wg workgroups remain
   if (n == 1024) {
     constexpr int TC = PRISM_COL4_TC32, TPW = 512 / TC;
     const int tiles = nwaves * TPW;
-    const int it = pick_iters(tiles, kCol4Iter, TC == 16 ? 256 : 512);
+    const int it = pick_iters(tiles, tune.col_iters, tune.col_min_wg);
     hipLaunchKernelGGL((k_col_pass4<32, TC>), dim3((unsigned)(tiles / it)), dim3(TC * 32), 0, st,
                        state, prop_p, tw2, it);
     return hipGetLastError();
   }
   if (n == 256) {
-    const int tiles = nwaves * 8, it = pick_iters(tiles, kCol4Iter, 512);
+    const int tiles = nwaves * 8, it = pick_iters(tiles, tune.col_iters, tune.col_min_wg);
     hipLaunchKernelGGL((k_col_pass4<16, 16>), dim3((unsigned)(tiles / it)), dim3(256), 0, st,
                        state, prop_p, tw2, it);
     return hipGetLastError();

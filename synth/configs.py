@@ -95,9 +95,8 @@ CONFIGS = {
 # Mixed batches of specimens (many small and large specimens built
 # together). Each entry is a recipe for ``batch_workload``: grid sizes with
 # 0.1 A pixels, slice counts drawn uniformly, interpolation factors drawn
-# among those the grid admits (windows of 8..256 pixels that the window
-# kernels take: powers of two and 24, 48, 72, 96), random atoms at
-# 0.015 A^-3.
+# among those the grid admits (n divisible by 2 f, windows of at least 8
+# pixels), random atoms at 0.015 A^-3.
 BATCHES = {
     # 32 specimens on 2^k, 3 * 2^k and 9 * 2^k grids, 20-120 slices, f in
     # {4, 6, 8, 12, 16}.

@@ -265,8 +265,7 @@ def _batch_shape(rec, rng):
     n = int(rng.choice(np.asarray(rec["sizes"])))
     H = int(rng.integers(rec["h_range"][0], rec["h_range"][1] + 1))
     def window_ok(f):
-        w = n // (2 * f)
-        return n % (2 * f) == 0 and w in (8, 16, 24, 32, 48, 64, 72, 96, 128, 256)
+        return n % (2 * f) == 0 and n // (2 * f) >= 8
     fs = [f for f in rec["f_choices"] if window_ok(f)]
     return n, H, int(rng.choice(np.asarray(fs)))
 
@@ -284,11 +283,10 @@ def batch_workload(name_or_recipe, seed=0, count=None, indices=None):
 
     Per specimen, from ``default_rng([seed, i])``: grid side n from the
     recipe's sizes, slice count H uniform in h_range, f among the recipe's
-    factors with n % (2 f) == 0 and 8 <= n / (2 f) <= 256, then the atoms
+    factors with n % (2 f) == 0 and n / (2 f) >= 8, then the atoms
     (random, density atoms per A^3 in an n * pixel square cell of
     thickness H * slice). The scan is the (n/4) x (n/4) raster at two
-    S-matrix pixels. Factors are kept only where the window n / (2 f) is
-    one the window kernels take (8, 16, 24, 32, 48, 64, 72, 96, 128, 256). ``indices`` builds only those specimens of the batch
+    S-matrix pixels. ``indices`` builds only those specimens of the batch
     (the others are not generated); ``batch_shapes`` lists (n, H, f) of all.
     """
     rec = BATCHES[name_or_recipe] if isinstance(name_or_recipe, str) else name_or_recipe

@@ -1,6 +1,7 @@
 """Grids with a factor 3 or 9 (n = 3 * 2^k, 9 * 2^k: radix-3/9 LDS FFT
 stages in the slice passes, the exit extraction and the multislice probe)
-and windows of 24, 48, 72 and 96 pixels, against the FP64 oracle.
+and windows of 12, 18, 24, 36, 48, 72, 96, 144 and 192 pixels, against the
+FP64 oracle.
 
 Gate: eps_rel <= 1e-4 (FP32), <= 1e-2 (BF16), per S-matrix beam and over the
 outputs.
@@ -85,7 +86,7 @@ def test_multislice_384_sampled(m384):
     assert e <= TOL
 
 
-@pytest.mark.parametrize("f", [3, 4, 6, 8, 12])
+@pytest.mark.parametrize("f", [3, 4, 6, 8, 12, 16])
 def test_prism_384(m384, f):
     d, plan = m384
     amax = _amax(d, f)
@@ -110,11 +111,13 @@ def test_prism_384(m384, f):
 
 
 @pytest.mark.parametrize("n,f,H", [(768, 6, 5), (768, 4, 3), (1536, 12, 3), (576, 4, 3),
-                                   (576, 12, 3), (1152, 8, 3), (1152, 6, 2)])
+                                   (576, 12, 3), (1152, 8, 3), (1152, 6, 2), (576, 16, 3),
+                                   (576, 8, 3), (1152, 16, 2), (1152, 4, 2), (1536, 4, 2)])
 def test_large_3x2k_grids_sampled(n, f, H):
-    # 576^2 .. 1536^2 (0.1 A pixels, random atoms; windows 24 .. 96): one
+    # 576^2 .. 1536^2 (0.1 A pixels, random atoms; windows 18 .. 192): one
     # multislice probe and PRISM probes (two at 768^2, one elsewhere)
-    # against one-probe oracle runs
+    # against one-probe oracle runs; for W = 144 and 192 (the two-pass
+    # window transform over HBM) the diffraction pattern as well
     cfg = dict(
         specimen=dict(kind="random", cell=(0.1 * n, 0.1 * n, 2.0 * H),
                       n_atoms=int(0.015 * (0.1 * n) ** 2 * 2.0 * H), z_choices=(6, 14, 29, 79)),
@@ -140,3 +143,26 @@ def test_large_3x2k_grids_sampled(n, f, H):
         print(f"n={n} f={f} probe {k} prism eps_rel={e:.3e} (multislice {em:.3e})")
         assert e <= TOL
     assert em <= TOL
+    if n // (2 * f) > 128:
+        x0, y0 = d["probes"][9]
+        C = G.probe_cbed(plan, f, amax, S, d["probes"][[9]], d["optics"])
+        _, Cref = O.prism_probe_direct(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f,
+                                       amax, d["optics"], x0, y0, d["edges"], return_cbed=True)
+        e = eps(C[0], Cref)
+        print(f"n={n} f={f} W={n // (2 * f)} cbed eps_rel={e:.3e}")
+        assert e <= TOL
+
+
+def test_window_12_cbed(m384):
+    # the smallest window (W = 12: a radix-4 first row stage, then radix 3)
+    d, plan = m384
+    f = 16
+    amax = _amax(d, f)
+    S = G.build_smatrix(plan, f, amax)
+    beams, Sref = O.smatrix(d["phase"], d["thickness"], d["cell"], d["energy_keV"], f, amax)
+    C = G.probe_cbed(plan, f, amax, S, d["probes"], d["optics"])
+    _, Cref = O.prism_outputs(Sref, beams, f, d["cell"], d["energy_keV"], d["optics"],
+                              d["probes"], d["edges"], return_cbed=True)
+    e = eps(C, Cref)
+    print(f"n=384 f=16 W=12 cbed eps_rel={e:.3e}")
+    assert e <= TOL
