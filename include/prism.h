@@ -32,7 +32,8 @@
  * Limits of this implementation: n is 2^k, 3 * 2^k or 9 * 2^k in
  * [128, 2048] (128, 192, 256, 384, 512, 576, 768, 1024, 1152, 1536, 2048);
  * the PRISM window side W = n / (2 f) is a power of two in [8, 256] or one
- * of 24, 48, 72, 96; at most PRISM_MAX_DET detector bins.
+ * of 12, 18, 24, 36, 48, 72, 96, 144, 192; at most PRISM_MAX_DET detector
+ * bins.
  */
 #ifndef PRISM_H
 #define PRISM_H
@@ -304,28 +305,42 @@ int prism_multislice_outputs_accumulate(prism_plan* plan, const double* probe_xy
                                         void* stream);
 
 /* ---------------------------------------------------------------------
- * Serving: resident S-matrices and merged probe queries.
+ * Serving: resident S-matrices, builds and probe queries that arrive while
+ * others run (continuous batching).
  *
  * An S-matrix, once built, serves any probe positions and probe settings
  * ("PRISM Simulations with Varying Probe Size": the S-matrix is re-used as
  * long as the specimen and f stay the same). A server keeps admitted
- * S-matrices under a byte budget and queues probe queries; a flush merges
- * every queued query of one (specimen, optics, detector) into probe-step
- * calls of up to max_probes positions and spreads them over n_streams HIP
- * streams (created by the server, default priority). A query's result is
- * the prism_probe_outputs result for its own positions.
+ * S-matrices under a byte budget and queues S-matrix builds and probe
+ * queries. Each flush dispatches what arrived since the previous one:
+ *   - queued builds in arrival order on the server's build stream, each
+ *     once prism_smatrix_bytes of it fits the budget (memory-based
+ *     admission); with LRU eviction on, idle S-matrices (no queued query,
+ *     nothing in flight) are released least recently used first to make
+ *     room, and reported by prism_server_evictions;
+ *   - every queued query of one (specimen, optics, detector) merged into
+ *     probe-step calls of up to max_probes positions, each call sent to the
+ *     first query slot (one of n_streams HIP streams, default priority)
+ *     whose earlier calls have all finished, else to the slot with the
+ *     fewest calls in flight. A query's slot waits on the device for its
+ *     S-matrix's build, so builds and other specimens' queries overlap.
+ * A query's result is the prism_probe_outputs result for its own positions.
  *
- * Workspace: the caller's device buffer, split into one region per stream;
- * a region holds the staged positions (max_probes x 2 doubles) and outputs
- * (max_probes x max_det doubles) of one merged call plus the probe-step
- * workspace (probe_ws_bytes, at least the probe step's minimum for every
- * admitted specimen and optics; prism_server_submit checks it).
- * Buffers named in admit and submit (S-matrix, positions, outputs) must stay
- * valid until the query is reported done by poll or wait (S-matrix: until
- * evicted). The server's streams are non-blocking and wait for no other
- * stream: a query's positions must be written (their stream synchronised)
- * before the flush that dispatches it, and its outputs are complete only once
- * poll or wait reports it. A server is used by one host thread at a time.
+ * Workspace: the caller's device buffer, split into one region per query
+ * slot; a region holds the staged positions (max_probes x 2 doubles) and
+ * outputs (max_probes x max_det doubles) of one merged call plus the
+ * probe-step workspace (probe_ws_bytes, at least the probe step's minimum
+ * for every admitted specimen and optics; prism_server_submit checks it).
+ * Buffers named in admit, submit_build and submit (S-matrix, build
+ * workspace, positions, outputs) must stay valid until the server is done
+ * with them: positions and outputs until the query is reported done by poll
+ * or wait, a build workspace until its build is reported done, an S-matrix
+ * until it is evicted (explicitly, or reported by prism_server_evictions).
+ * The server's streams are non-blocking and wait for no other stream: a
+ * query's positions and a plan's potential slices must be written (their
+ * streams synchronised) before the flush that dispatches them, and outputs
+ * are complete only once poll or wait reports them. A server is used by one
+ * host thread at a time.
  * --------------------------------------------------------------------- */
 typedef struct prism_server prism_server;
 
@@ -338,20 +353,41 @@ int prism_server_create(prism_server** server, size_t smatrix_budget_bytes, int 
 /* Waits for the server's streams, then frees the host state (never the
  * caller's device buffers). */
 void prism_server_destroy(prism_server* server);
-/* Admit one specimen's S-matrix (prism_smatrix_bytes of it must fit in the
- * remaining budget, else PRISM_ENOSPACE; smatrix_bytes is the size of the
- * caller's buffer, PRISM_EINVAL if smaller). With build_ws != NULL the
- * server builds it with prism_build_smatrix on its first stream, where
- * every admit's build runs, so builds are ordered among themselves and may
- * share one build workspace; the plan's potential slices must be set and
- * written (their stream synchronised) before the call, since the server's
- * streams wait for no other stream. With build_ws == NULL smatrix_dev must
+/* Admit one specimen's S-matrix now (prism_smatrix_bytes of it must fit in
+ * the remaining budget, after LRU eviction when enabled, else
+ * PRISM_ENOSPACE; smatrix_bytes is the size of the caller's buffer,
+ * PRISM_EINVAL if smaller). With build_ws != NULL the server builds it with
+ * prism_build_smatrix on its build stream, where every build runs, so
+ * builds are ordered among themselves and may share one build workspace;
+ * the plan's potential slices must be set and written (their stream
+ * synchronised) before the call. With build_ws == NULL smatrix_dev must
  * already hold it (built by the caller and synchronised). *id names it. */
 int prism_server_admit(prism_server* server, prism_plan* plan, int f, double alpha_max_mrad,
                        void* smatrix_dev, size_t smatrix_bytes, void* build_ws,
                        size_t build_ws_bytes, int* id);
-/* Release a specimen's budget after its dispatched queries have finished
- * (waits for the server's streams). PRISM_EINVAL if queries are queued. */
+/* Queue the build of one specimen's S-matrix (Fig. 1c), dispatched by a
+ * later flush once its bytes fit the budget. smatrix_dev/smatrix_bytes and
+ * build_ws/build_ws_bytes as in prism_build_smatrix; the build workspace
+ * may be shared by every queued build (builds run one after another on the
+ * build stream). *id names the specimen at once: queries may be submitted
+ * against it before its build runs (they wait for it). *ticket is reported
+ * by poll / wait when the S-matrix is complete.
+ * Errors: PRISM_EINVAL (null argument, the checks of prism_build_smatrix's
+ * sizes), PRISM_ENOSPACE (S-matrix larger than the whole budget, build
+ * workspace below the build minimum). */
+int prism_server_submit_build(prism_server* server, prism_plan* plan, int f,
+                              double alpha_max_mrad, void* smatrix_dev, size_t smatrix_bytes,
+                              void* build_ws, size_t build_ws_bytes, int* id, long long* ticket);
+/* LRU eviction (enable != 0): admission may release idle S-matrices, least
+ * recently used first (off by default: admission then fails or waits). */
+int prism_server_set_lru_eviction(prism_server* server, int enable);
+/* Specimens released by LRU eviction since the previous call: up to
+ * capacity ids into ids, *count of them. Their S-matrix buffers are the
+ * caller's again. */
+int prism_server_evictions(prism_server* server, int* ids, int capacity, int* count);
+/* Release a specimen's budget after its dispatched calls have finished
+ * (waits for the server's streams). PRISM_EINVAL if queries are queued or
+ * its build has not been dispatched. */
 int prism_server_evict(prism_server* server, int id);
 /* Queue one query: n_probes in [0, max_probes] positions (device float64
  * [P][2], A), optics and detector as in prism_probe_outputs (copied), out_dev
@@ -361,18 +397,49 @@ int prism_server_evict(prism_server* server, int id);
 int prism_server_submit(prism_server* server, int id, const double* probe_xy_dev, int n_probes,
                         const prism_optics* optics, const prism_detector* detector,
                         double* out_dev, long long* ticket);
-/* Dispatch every queued query (merged as above). */
+/* Dispatch the queued builds that fit and the queued queries whose
+ * specimen's build has been dispatched (as above). */
 int prism_server_flush(prism_server* server);
-/* Report finished queries: up to capacity tickets into done, *count of them.
- * A ticket is reported once (by poll or by wait). */
+/* Report finished queries and builds: up to capacity tickets into done,
+ * *count of them. A ticket is reported once (by poll or by wait). */
 int prism_server_poll(prism_server* server, long long* done, int capacity, int* count);
-/* Block until one flushed query is done (PRISM_EINVAL if it is still queued
- * or unknown). */
+/* Block until one dispatched query or build is done (PRISM_EINVAL if it is
+ * still queued or unknown). */
 int prism_server_wait(prism_server* server, long long ticket);
-/* Admitted S-matrix bytes, queued queries and dispatched-but-unreported
- * queries (any pointer may be NULL). */
+/* Admitted S-matrix bytes (dispatched builds included), queued queries and
+ * builds, and dispatched-but-unreported tickets (any pointer may be NULL). */
 int prism_server_stats(const prism_server* server, size_t* smatrix_bytes_used, int* queued,
                        int* in_flight);
+
+/* Launch shapes of a plan, none of which changes any result (the same
+ * operations run in the same order; only their distribution over
+ * workgroups and launches changes), chosen per grid by a tuning sweep on
+ * the target GPU. A zero field means the library default (shown).
+ *   row_iters, col_iters: most row groups / column tiles one workgroup of
+ *     the four-step slice passes walks (powers of two up to 64; 16, 8);
+ *   row_min_groups, col_min_groups: fewest workgroups a slice-pass launch
+ *     keeps when choosing those counts (512, 256);
+ *   wave_chunk_mib: wave state per slice-pass launch, which sets the
+ *     preferred build and multislice workspaces (16 .. 65536; 256);
+ *   probe_group: probes per window-sum group (16, 32, 64; 0: 64 for
+ *     W >= 128, 32 for W >= 64, else 16), which also sets the tile shape
+ *     prism_probe_group reports;
+ *   window_tile_div: window-sum workgroups per probe group are the 128-pixel
+ *     tiles of one window divided by this (1 .. 64; 4).
+ * Query workspace sizes after setting it. PRISM_EINVAL for values outside
+ * these ranges (nothing is changed then). */
+typedef struct {
+  int row_iters;
+  int row_min_groups;
+  int col_iters;
+  int col_min_groups;
+  int wave_chunk_mib;
+  int probe_group;
+  int window_tile_div;
+} prism_tuning;
+int prism_set_tuning(prism_plan* plan, const prism_tuning* tuning);
+/* The plan's effective launch shapes (probe_group 0: chosen by W). */
+int prism_get_tuning(const prism_plan* plan, prism_tuning* tuning);
 
 /* Per-kernel timing: while enabled, every kernel launch of this plan is
  * bracketed by HIP events recorded on its stream. prism_profile_report

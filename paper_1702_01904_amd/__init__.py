@@ -59,8 +59,28 @@ def _check_dev(t, dtype, numel=None, name="tensor"):
         raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
 
 
+_TUNING_FIELDS = ("row_iters", "row_min_groups", "col_iters", "col_min_groups",
+                  "wave_chunk_mib", "probe_group", "window_tile_div")
+_TUNING = None
+
+
+def _tuning_table():
+    """Per-grid launch shapes from the committed sweep (tuning_gfx950.json), or {}."""
+    global _TUNING
+    if _TUNING is None:
+        import json
+        import os
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
+        _TUNING = {}
+        if os.path.exists(path):
+            with open(path) as fh:
+                _TUNING = {k: v["tuning"] for k, v in json.load(fh).get("grids", {}).items()}
+    return _TUNING
+
+
 class Plan:
-    """One grid / cell / energy / slicing (prism_plan)."""
+    """One grid / cell / energy / slicing (prism_plan). A plan for a grid in
+    the committed tuning table gets that grid's launch shapes."""
 
     def __init__(self, n, cell_A, energy_keV, slice_thickness_A):
         self._L = _native.lib()
@@ -75,6 +95,9 @@ class Plan:
         self.energy_keV = float(energy_keV)
         self.n_slices = int(th.size)
         self._phase = None
+        tuned = _tuning_table().get(str(self.n))
+        if tuned:
+            self.set_tuning(tuned)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -146,6 +169,17 @@ class Plan:
                                                           ctypes.byref(o), ctypes.byref(a),
                                                           ctypes.byref(b)))
         return a.value, b.value
+
+    def set_tuning(self, tuning):
+        """Launch shapes (prism_set_tuning): dict of prism_tuning fields, absent or 0 = default."""
+        t = _native.PrismTuning(*[int(tuning.get(k, 0)) for k in _TUNING_FIELDS])
+        _native.check(self._L.prism_set_tuning(self._h, ctypes.byref(t)))
+
+    def tuning(self):
+        """The plan's effective launch shapes as a dict (prism_get_tuning)."""
+        t = _native.PrismTuning()
+        _native.check(self._L.prism_get_tuning(self._h, ctypes.byref(t)))
+        return {k: getattr(t, k) for k in _TUNING_FIELDS}
 
     def probe_group(self, f):
         g, tx, ty = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
@@ -395,6 +429,35 @@ class Server:
                                                  ctypes.byref(i)))
         self._spec[i.value] = (plan, smatrix, build_workspace)
         return i.value
+
+    def submit_build(self, plan, f, alpha_max_mrad, smatrix, build_workspace):
+        """Queue one specimen's S-matrix build (dispatched by a flush once it
+        fits the budget); returns (specimen id, ticket)."""
+        import torch
+        B = plan.beam_count(f, alpha_max_mrad)
+        _check_dev(smatrix, torch.complex64, B * (plan.n // 2) ** 2, "smatrix")
+        _check_dev(build_workspace, torch.uint8, None, "build_workspace")
+        i, t = ctypes.c_int(), ctypes.c_longlong()
+        _native.check(self._L.prism_server_submit_build(
+            self._h, plan._h, int(f), float(alpha_max_mrad), _ptr(smatrix), _nbytes(smatrix),
+            _ptr(build_workspace), build_workspace.numel(), ctypes.byref(i), ctypes.byref(t)))
+        self._spec[i.value] = (plan, smatrix, build_workspace)
+        return i.value, t.value
+
+    def set_lru_eviction(self, enable=True):
+        """Let admission release idle S-matrices, least recently used first."""
+        _native.check(self._L.prism_server_set_lru_eviction(self._h, 1 if enable else 0))
+
+    def evictions(self, capacity=1024):
+        """Ids released by LRU eviction since the last call (their buffers are dropped here)."""
+        buf = (ctypes.c_int * int(capacity))()
+        n = ctypes.c_int()
+        _native.check(self._L.prism_server_evictions(self._h, buf, int(capacity),
+                                                     ctypes.byref(n)))
+        ids = [buf[k] for k in range(n.value)]
+        for sid in ids:
+            self._spec.pop(sid, None)
+        return ids
 
     def evict(self, sid):
         _native.check(self._L.prism_server_evict(self._h, int(sid)))

@@ -31,9 +31,11 @@ EXPORTS = (
     "prism_probe_outputs_accumulate", "prism_probe_cbed_accumulate",
     "prism_multislice_outputs_accumulate", "prism_build_batch_workspace_bytes",
     "prism_build_smatrix_batch", "prism_server_workspace_bytes", "prism_server_create",
-    "prism_server_destroy", "prism_server_admit", "prism_server_evict", "prism_server_submit",
+    "prism_server_destroy", "prism_server_admit", "prism_server_submit_build",
+    "prism_server_set_lru_eviction", "prism_server_evictions", "prism_server_evict",
+    "prism_server_submit",
     "prism_server_flush", "prism_server_poll", "prism_server_wait", "prism_server_stats",
-    "prism_profile_enable", "prism_profile_report",
+    "prism_set_tuning", "prism_get_tuning", "prism_profile_enable", "prism_profile_report",
     "prism_last_error",
 )
 
@@ -57,6 +59,13 @@ class PrismBuildItem(ctypes.Structure):
     _fields_ = [("plan", ctypes.c_void_p), ("f", ctypes.c_int),
                 ("alpha_max_mrad", ctypes.c_double), ("smatrix_dev", ctypes.c_void_p),
                 ("smatrix_bytes", ctypes.c_size_t)]
+
+
+class PrismTuning(ctypes.Structure):
+    _fields_ = [("row_iters", ctypes.c_int), ("row_min_groups", ctypes.c_int),
+                ("col_iters", ctypes.c_int), ("col_min_groups", ctypes.c_int),
+                ("wave_chunk_mib", ctypes.c_int), ("probe_group", ctypes.c_int),
+                ("window_tile_div", ctypes.c_int)]
 
 
 class PrismError(RuntimeError):
@@ -131,6 +140,10 @@ def lib():
         "prism_server_destroy": (None, [P]),
         "prism_server_admit": (I, [P, P, I, D, P, ctypes.c_size_t, P, ctypes.c_size_t,
                                    ctypes.POINTER(I)]),
+        "prism_server_submit_build": (I, [P, P, I, D, P, ctypes.c_size_t, P, ctypes.c_size_t,
+                                          ctypes.POINTER(I), ctypes.POINTER(ctypes.c_longlong)]),
+        "prism_server_set_lru_eviction": (I, [P, I]),
+        "prism_server_evictions": (I, [P, ctypes.POINTER(I), I, ctypes.POINTER(I)]),
         "prism_server_evict": (I, [P, I]),
         "prism_server_submit": (I, [P, I, P, I, ctypes.POINTER(PrismOptics),
                                     ctypes.POINTER(PrismDetector), P,
@@ -139,6 +152,8 @@ def lib():
         "prism_server_poll": (I, [P, ctypes.POINTER(ctypes.c_longlong), I, ctypes.POINTER(I)]),
         "prism_server_wait": (I, [P, ctypes.c_longlong]),
         "prism_server_stats": (I, [P, SZ, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "prism_set_tuning": (I, [P, ctypes.POINTER(PrismTuning)]),
+        "prism_get_tuning": (I, [P, ctypes.POINTER(PrismTuning)]),
         "prism_profile_enable": (I, [P, I]),
         "prism_profile_report": (I, [P, ctypes.c_char_p, ctypes.c_size_t]),
         "prism_last_error": (ctypes.c_char_p, []),

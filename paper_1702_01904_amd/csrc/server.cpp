@@ -1,20 +1,29 @@
-// Serving layer: resident S-matrices under a byte budget and a queue of
-// probe queries that are merged into shared probe-step calls.
+// Serving layer: resident S-matrices under a byte budget, S-matrix builds
+// and probe queries that arrive while others run, merged probe-step calls.
 //
 // The S-matrix of a specimen is built once (Fig. 1c) and then serves any
 // number of probe positions and probe settings (the re-use of the S-matrix
 // discussed in "PRISM Simulations with Varying Probe Size"). The server
-// keeps a set of admitted S-matrices whose bytes stay under a budget and a
-// host-side queue of queries. prism_server_flush merges every pending query
-// of one (specimen, optics, detector) into as few probe-step calls as the
-// staging space allows (continuous batching: what arrived since the last
-// flush rides in the same launches) and spreads the merged calls over the
-// server's streams. The server is a client of the public entry points only.
+// keeps the admitted S-matrices under a byte budget and host-side queues of
+// builds and queries. Each flush dispatches what has arrived since the last
+// one (continuous batching):
+//   * builds in arrival order on the server's build stream, each admitted
+//     once its bytes fit the budget; with LRU eviction on, the least
+//     recently used idle S-matrices are released to make room;
+//   * every queued query of one (specimen, optics, detector) merged into as
+//     few probe-step calls as the staging space allows, each call sent to
+//     the first query slot (stream) that has finished its earlier work, or
+//     else to the slot with the fewest calls in flight; a query of a
+//     specimen whose build is still queued waits for that build, and a
+//     query's stream waits for its S-matrix's build event on the device, so
+//     builds and queries of other specimens overlap on the GPU.
+// The server is a client of the public entry points only.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <string>
 #include <tuple>
@@ -27,15 +36,20 @@ namespace {
 
 using prism::set_error;
 
+enum class SpecState { kBuildQueued, kResident, kReleased };
+
 struct Specimen {
   prism_plan* plan;
   int f;
   double amax;
   const void* S;
-  size_t bytes;     // prism_smatrix_bytes: what the budget counts
-  size_t S_bytes;   // the caller's buffer
-  hipEvent_t ready;
-  bool live;
+  size_t bytes;      // prism_smatrix_bytes: what the budget counts
+  size_t S_bytes;    // the caller's buffer
+  hipEvent_t ready;  // recorded after the S-matrix is complete (build stream)
+  SpecState state;
+  long long last_use;  // dispatch sequence of the last call that read it (LRU)
+  int queued;          // queued queries
+  int inflight;        // dispatched calls (builds, probe steps) not yet seen finished
 };
 
 struct Query {
@@ -48,9 +62,19 @@ struct Query {
   double* out;
 };
 
+struct Build {
+  long long ticket;
+  int spec;
+  void* ws;
+  size_t ws_bytes;
+};
+
 struct Batch {
   hipEvent_t done;
-  int pending;  // tickets of this batch not yet reported
+  int pending;    // tickets of this batch not yet reported
+  int spec;       // specimen it reads (or builds)
+  int slot;       // query slot, or -1 for the build stream
+  bool finished;  // done event seen complete (specimen and slot counts released)
 };
 
 uint64_t bits(double x) {
@@ -64,26 +88,33 @@ uint64_t bits(double x) {
 struct prism_server {
   size_t budget = 0, used = 0;
   int max_probes = 0, max_det = 0;
-  std::vector<hipStream_t> streams;
+  bool lru = false;
+  std::vector<hipStream_t> streams;  // query slots
+  std::vector<int> slot_inflight;    // calls in flight per slot
+  hipStream_t build_stream = nullptr;
   char* ws = nullptr;
-  size_t region = 0;  // bytes of the workspace per stream
-  int next_stream = 0;
+  size_t region = 0;  // bytes of the workspace per query slot
+  long long seq = 0;  // dispatch sequence (LRU clock)
   std::vector<Specimen> specs;
   std::vector<Query> pending;
+  std::deque<Build> builds;
   long long next_ticket = 1;
-  std::map<long long, int> ticket_batch;  // in flight: ticket -> batch index
+  std::map<long long, int> ticket_batch;  // dispatched: ticket -> batch index
   std::vector<Batch> batches;
   std::vector<int> free_batches;  // retired batch slots
   std::vector<hipEvent_t> event_pool;
+  std::vector<int> evicted;  // released by LRU eviction, not yet reported
 
   ~prism_server() {
     for (auto s : streams) (void)hipStreamSynchronize(s);
+    if (build_stream) (void)hipStreamSynchronize(build_stream);
     for (auto& b : batches)
       if (b.done) (void)hipEventDestroy(b.done);
     for (auto e : event_pool) (void)hipEventDestroy(e);
     for (auto& s : specs)
       if (s.ready) (void)hipEventDestroy(s.ready);
     for (auto s : streams) (void)hipStreamDestroy(s);
+    if (build_stream) (void)hipStreamDestroy(build_stream);
   }
   hipEvent_t event() {
     if (!event_pool.empty()) {
@@ -99,7 +130,7 @@ struct prism_server {
 
 namespace {
 
-// Per-stream region of the server workspace: probe positions and outputs of
+// Per-slot region of the server workspace: probe positions and outputs of
 // one merged call, then the probe-step workspace.
 struct Region {
   double* xy;
@@ -127,33 +158,125 @@ int hip_err(hipError_t e, const char* where) {
   return set_error(PRISM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-// Retire finished batches: their tickets are reported done by poll/wait.
+// A dispatched call has finished: release what it held.
+void finish(prism_server* s, Batch& bt) {
+  if (bt.finished) return;
+  bt.finished = true;
+  s->specs[bt.spec].inflight--;
+  if (bt.slot >= 0) s->slot_inflight[bt.slot]--;
+}
+
+// Look at every dispatched call not yet seen finished.
+int refresh(prism_server* s) {
+  for (auto& bt : s->batches) {
+    if (!bt.done || bt.finished) continue;
+    const hipError_t e = hipEventQuery(bt.done);
+    if (e == hipErrorNotReady) continue;
+    if (e != hipSuccess) return hip_err(e, "query event");
+    finish(s, bt);
+  }
+  return PRISM_OK;
+}
+
+// Report one ticket of a batch; retire the batch when all are reported.
 void recycle(prism_server* s, int b) {
-  if (--s->batches[b].pending == 0) {
-    if (s->batches[b].done) s->event_pool.push_back(s->batches[b].done);
-    s->batches[b].done = nullptr;
+  Batch& bt = s->batches[b];
+  if (--bt.pending == 0) {
+    finish(s, bt);
+    if (bt.done) s->event_pool.push_back(bt.done);
+    bt.done = nullptr;
     s->free_batches.push_back(b);
   }
 }
 
-int new_batch(prism_server* s, hipEvent_t done, int pending) {
+int new_batch(prism_server* s, hipEvent_t done, int pending, int spec, int slot) {
+  Batch bt{done, pending, spec, slot, false};
+  s->specs[spec].inflight++;
+  if (slot >= 0) s->slot_inflight[slot]++;
   if (!s->free_batches.empty()) {
     const int b = s->free_batches.back();
     s->free_batches.pop_back();
-    s->batches[b] = Batch{done, pending};
+    s->batches[b] = bt;
     return b;
   }
-  s->batches.push_back(Batch{done, pending});
+  s->batches.push_back(bt);
   return (int)s->batches.size() - 1;
 }
 
-int flush_groups(prism_server* s, std::vector<char>* sent) {
+void release(prism_server* s, int id) {
+  s->specs[id].state = SpecState::kReleased;
+  s->used -= s->specs[id].bytes;
+}
+
+// Make room for `need` bytes: with LRU eviction, release idle S-matrices
+// (resident, no queued query, nothing in flight) least recently used first.
+// Returns whether the bytes fit afterwards.
+bool make_room(prism_server* s, size_t need) {
+  if (s->used + need <= s->budget) return true;
+  if (!s->lru || need > s->budget) return false;
+  std::vector<int> idle;
+  for (int i = 0; i < (int)s->specs.size(); ++i) {
+    const Specimen& sp = s->specs[i];
+    // idle: resident, no queued query, no call in flight, and its build
+    // (an admit's build is not a tracked call) complete
+    if (sp.state == SpecState::kResident && sp.queued == 0 && sp.inflight == 0 &&
+        hipEventQuery(sp.ready) == hipSuccess)
+      idle.push_back(i);
+  }
+  std::sort(idle.begin(), idle.end(),
+            [&](int a, int b) { return s->specs[a].last_use < s->specs[b].last_use; });
+  size_t freeable = 0;
+  for (int i : idle) freeable += s->specs[i].bytes;
+  if (s->used - freeable + need > s->budget) return false;  // evict nothing in vain
+  for (int i : idle) {
+    if (s->used + need <= s->budget) break;
+    release(s, i);
+    s->evicted.push_back(i);
+  }
+  return true;
+}
+
+// Query slot for the next call: the first one whose earlier calls have all
+// finished, else the one with the fewest calls in flight.
+int pick_slot(const prism_server* s) {
+  int best = 0;
+  for (int k = 0; k < (int)s->streams.size(); ++k) {
+    if (s->slot_inflight[k] == 0) return k;
+    if (s->slot_inflight[k] < s->slot_inflight[best]) best = k;
+  }
+  return best;
+}
+
+int dispatch_builds(prism_server* s) {
+  while (!s->builds.empty()) {
+    const Build bd = s->builds.front();
+    Specimen& sp = s->specs[bd.spec];
+    if (!make_room(s, sp.bytes)) break;  // arrival order: later builds wait too
+    s->builds.pop_front();
+    hipStream_t st = s->build_stream;
+    if (int r = prism_build_smatrix(sp.plan, sp.f, sp.amax, const_cast<void*>(sp.S), sp.S_bytes,
+                                    bd.ws, bd.ws_bytes, st))
+      return r;
+    if (hipError_t e = hipEventRecord(sp.ready, st); e != hipSuccess) return hip_err(e, "record event");
+    sp.state = SpecState::kResident;
+    s->used += sp.bytes;
+    sp.last_use = ++s->seq;
+    hipEvent_t done = s->event();
+    if (!done) return set_error(PRISM_EHIP, "create event");
+    if (hipError_t e = hipEventRecord(done, st); e != hipSuccess) return hip_err(e, "record event");
+    s->ticket_batch[bd.ticket] = new_batch(s, done, 1, bd.spec, -1);
+  }
+  return PRISM_OK;
+}
+
+int flush_queries(prism_server* s, std::vector<char>* sent) {
   // merge key: specimen, optics, detector; queries keep their arrival order
   using Key = std::tuple<int, uint64_t, uint64_t, uint64_t, uint64_t, uint64_t, std::vector<uint64_t>>;
   std::map<Key, std::vector<size_t>> groups;
   std::vector<Key> order;
   for (size_t i = 0; i < s->pending.size(); ++i) {
     const Query& q = s->pending[i];
+    if (s->specs[q.spec].state != SpecState::kResident) continue;  // its build is still queued
     std::vector<uint64_t> eb;
     for (double e : q.edges) eb.push_back(bits(e));
     Key k{q.spec, bits(q.optics.alpha_mrad), bits(q.optics.C1_A), bits(q.optics.C3_A),
@@ -175,10 +298,9 @@ int flush_groups(prism_server* s, std::vector<char>* sent) {
       int total = 0;
       while (b < qs.size() && total + s->pending[qs[b]].P <= s->max_probes) total += s->pending[qs[b++]].P;
       const Query& q0 = s->pending[qs[a]];
-      const Specimen& sp = s->specs[q0.spec];
+      Specimen& sp = s->specs[q0.spec];
       const int n_det = (int)(q0.edges.size() / 2);
-      const int k_st = s->next_stream;
-      s->next_stream = (s->next_stream + 1) % (int)s->streams.size();
+      const int k_st = pick_slot(s);
       hipStream_t st = s->streams[k_st];
       const Region rg = region_of(s, k_st);
       if (hipError_t e = hipStreamWaitEvent(st, sp.ready, 0); e != hipSuccess) return hip_err(e, "wait S-matrix");
@@ -212,14 +334,31 @@ int flush_groups(prism_server* s, std::vector<char>* sent) {
       hipEvent_t done = s->event();
       if (!done) return set_error(PRISM_EHIP, "create event");
       if (hipError_t e = hipEventRecord(done, st); e != hipSuccess) return hip_err(e, "record event");
-      const int bi = new_batch(s, done, (int)(b - a));
+      const int bi = new_batch(s, done, (int)(b - a), q0.spec, k_st);
+      sp.last_use = ++s->seq;
       for (size_t i = a; i < b; ++i) {
         s->ticket_batch[s->pending[qs[i]].ticket] = bi;
         (*sent)[qs[i]] = 1;
+        sp.queued--;
       }
       a = b;
     }
   }
+  return PRISM_OK;
+}
+
+bool live_id(const prism_server* s, int id) {
+  return id >= 0 && id < (int)s->specs.size() && s->specs[id].state != SpecState::kReleased;
+}
+
+// Register a specimen (its ready event included); *id names it.
+int add_specimen(prism_server* s, prism_plan* plan, int f, double amax, void* S, size_t bytes,
+                 size_t S_bytes, SpecState state, int* id) {
+  hipEvent_t ready = nullptr;
+  if (hipError_t e = hipEventCreateWithFlags(&ready, hipEventDisableTiming); e != hipSuccess)
+    return hip_err(e, "create event");
+  s->specs.push_back(Specimen{plan, f, amax, S, bytes, S_bytes, ready, state, 0, 0, 0});
+  *id = (int)s->specs.size() - 1;
   return PRISM_OK;
 }
 
@@ -253,20 +392,31 @@ int prism_server_create(prism_server** out, size_t smatrix_budget_bytes, int n_s
   const uintptr_t a = (u + 255) & ~uintptr_t(255);
   s->ws = reinterpret_cast<char*>(a);
   s->region = ((ws_bytes - (a - u)) / n_streams) & ~size_t(255);
-  for (int k = 0; k < n_streams; ++k) {
+  for (int k = 0; k <= n_streams; ++k) {
     hipStream_t st = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
     if (e != hipSuccess) {
       delete s;
       return hip_err(e, "create server stream");
     }
-    s->streams.push_back(st);
+    if (k < n_streams) {
+      s->streams.push_back(st);
+      s->slot_inflight.push_back(0);
+    } else {
+      s->build_stream = st;
+    }
   }
   *out = s;
   return PRISM_OK;
 }
 
 void prism_server_destroy(prism_server* s) { delete s; }
+
+int prism_server_set_lru_eviction(prism_server* s, int enable) {
+  if (!s) return set_error(PRISM_EINVAL, "null server");
+  s->lru = enable != 0;
+  return PRISM_OK;
+}
 
 int prism_server_admit(prism_server* s, prism_plan* plan, int f, double alpha_max_mrad,
                        void* smatrix_dev, size_t smatrix_bytes, void* build_ws,
@@ -276,36 +426,73 @@ int prism_server_admit(prism_server* s, prism_plan* plan, int f, double alpha_ma
   if (int r = prism_smatrix_bytes(plan, f, alpha_max_mrad, &bytes)) return r;
   if (smatrix_bytes < bytes)
     return set_error(PRISM_EINVAL, "S-matrix buffer smaller than prism_smatrix_bytes");
-  if (s->used + bytes > s->budget)
+  if (int r = refresh(s)) return r;
+  if (!make_room(s, bytes))
     return set_error(PRISM_ENOSPACE, "S-matrix does not fit in the server's budget");
-  // every build runs on the server's first stream, so builds are ordered
-  // among themselves (two builds may share one build workspace)
-  hipStream_t st = s->streams[0];
+  // builds run on the server's build stream, in the order they are given
+  hipStream_t st = s->build_stream;
   if (build_ws) {
     if (int r = prism_build_smatrix(plan, f, alpha_max_mrad, smatrix_dev, smatrix_bytes,
                                     build_ws, build_ws_bytes, st))
       return r;
   }
-  hipEvent_t ready = s->event();
-  if (!ready) return set_error(PRISM_EHIP, "create event");
-  if (hipError_t e = hipEventRecord(ready, st); e != hipSuccess) return hip_err(e, "record event");
-  s->specs.push_back(Specimen{plan, f, alpha_max_mrad, smatrix_dev, bytes, smatrix_bytes, ready,
-                              true});
+  int sid;
+  if (int r = add_specimen(s, plan, f, alpha_max_mrad, smatrix_dev, bytes, smatrix_bytes,
+                           SpecState::kResident, &sid))
+    return r;
+  if (hipError_t e = hipEventRecord(s->specs[sid].ready, st); e != hipSuccess)
+    return hip_err(e, "record event");
   s->used += bytes;
-  *id = (int)s->specs.size() - 1;
+  s->specs[sid].last_use = ++s->seq;
+  *id = sid;
+  return PRISM_OK;
+}
+
+int prism_server_submit_build(prism_server* s, prism_plan* plan, int f, double alpha_max_mrad,
+                              void* smatrix_dev, size_t smatrix_bytes, void* build_ws,
+                              size_t build_ws_bytes, int* id, long long* ticket) {
+  if (!s || !plan || !smatrix_dev || !build_ws || !id || !ticket)
+    return set_error(PRISM_EINVAL, "null argument");
+  size_t bytes, pref, minimum;
+  if (int r = prism_smatrix_bytes(plan, f, alpha_max_mrad, &bytes)) return r;
+  if (smatrix_bytes < bytes)
+    return set_error(PRISM_EINVAL, "S-matrix buffer smaller than prism_smatrix_bytes");
+  if (bytes > s->budget)
+    return set_error(PRISM_ENOSPACE, "S-matrix larger than the server's whole budget");
+  if (int r = prism_build_workspace_bytes(plan, f, alpha_max_mrad, &pref, &minimum)) return r;
+  if (build_ws_bytes < minimum)
+    return set_error(PRISM_ENOSPACE, "build workspace smaller than the build minimum");
+  int sid;
+  if (int r = add_specimen(s, plan, f, alpha_max_mrad, smatrix_dev, bytes, smatrix_bytes,
+                           SpecState::kBuildQueued, &sid))
+    return r;
+  const long long t = s->next_ticket++;
+  s->builds.push_back(Build{t, sid, build_ws, build_ws_bytes});
+  *id = sid;
+  *ticket = t;
   return PRISM_OK;
 }
 
 int prism_server_evict(prism_server* s, int id) {
-  if (!s || id < 0 || id >= (int)s->specs.size() || !s->specs[id].live)
-    return set_error(PRISM_EINVAL, "no such specimen");
-  for (const Query& q : s->pending)
-    if (q.spec == id) return set_error(PRISM_EINVAL, "specimen has queued queries");
-  // queries already dispatched must finish before the caller reuses the memory
+  if (!s || !live_id(s, id)) return set_error(PRISM_EINVAL, "no such specimen");
+  if (s->specs[id].state == SpecState::kBuildQueued)
+    return set_error(PRISM_EINVAL, "specimen's build is still queued");
+  if (s->specs[id].queued > 0) return set_error(PRISM_EINVAL, "specimen has queued queries");
+  // calls already dispatched must finish before the caller reuses the memory
   for (auto st : s->streams)
     if (hipError_t e = hipStreamSynchronize(st); e != hipSuccess) return hip_err(e, "drain");
-  s->specs[id].live = false;
-  s->used -= s->specs[id].bytes;
+  if (hipError_t e = hipStreamSynchronize(s->build_stream); e != hipSuccess) return hip_err(e, "drain");
+  if (int r = refresh(s)) return r;
+  release(s, id);
+  return PRISM_OK;
+}
+
+int prism_server_evictions(prism_server* s, int* ids, int capacity, int* count) {
+  if (!s || !count || (capacity > 0 && !ids)) return set_error(PRISM_EINVAL, "null argument");
+  const int n = std::min(capacity, (int)s->evicted.size());
+  for (int i = 0; i < n; ++i) ids[i] = s->evicted[i];
+  s->evicted.erase(s->evicted.begin(), s->evicted.begin() + n);
+  *count = n;
   return PRISM_OK;
 }
 
@@ -313,8 +500,7 @@ int prism_server_submit(prism_server* s, int id, const double* probe_xy_dev, int
                         const prism_optics* optics, const prism_detector* detector,
                         double* out_dev, long long* ticket) {
   if (!s || !optics || !detector || !ticket) return set_error(PRISM_EINVAL, "null argument");
-  if (id < 0 || id >= (int)s->specs.size() || !s->specs[id].live)
-    return set_error(PRISM_EINVAL, "no such specimen");
+  if (!live_id(s, id)) return set_error(PRISM_EINVAL, "no such specimen");
   if (n_probes < 0 || n_probes > s->max_probes)
     return set_error(PRISM_EINVAL, "probe count must be 0..max_probes");
   if (detector->n_det < 1 || detector->n_det > s->max_det || !detector->edges_mrad)
@@ -326,7 +512,7 @@ int prism_server_submit(prism_server* s, int id, const double* probe_xy_dev, int
       return set_error(PRISM_EINVAL, "detector edges must satisfy 0 <= inner <= outer");
   }
   if (n_probes > 0 && (!probe_xy_dev || !out_dev)) return set_error(PRISM_EINVAL, "null device buffer");
-  const Specimen& sp = s->specs[id];
+  Specimen& sp = s->specs[id];
   if (optics->alpha_mrad + std::hypot(optics->tilt_x_mrad, optics->tilt_y_mrad) > sp.amax)
     return set_error(PRISM_EINVAL, "probe semi-angle plus tilt exceeds the beam set's alpha_max");
   // the probe step's own checks, and its workspace minimum against a region
@@ -338,14 +524,17 @@ int prism_server_submit(prism_server* s, int id, const double* probe_xy_dev, int
           std::vector<double>(detector->edges_mrad, detector->edges_mrad + 2 * detector->n_det),
           out_dev};
   *ticket = q.ticket;
+  sp.queued++;
   s->pending.push_back(std::move(q));
   return PRISM_OK;
 }
 
 int prism_server_flush(prism_server* s) {
   if (!s) return set_error(PRISM_EINVAL, "null server");
+  if (int r = refresh(s)) return r;
+  int r = dispatch_builds(s);
   std::vector<char> sent(s->pending.size(), 0);
-  const int r = flush_groups(s, &sent);
+  if (r == PRISM_OK) r = flush_queries(s, &sent);
   // dispatched queries leave the queue even when a later group failed
   std::vector<Query> keep;
   for (size_t i = 0; i < s->pending.size(); ++i)
@@ -357,14 +546,12 @@ int prism_server_flush(prism_server* s) {
 int prism_server_poll(prism_server* s, long long* done, int capacity, int* count) {
   if (!s || !count || (capacity > 0 && !done)) return set_error(PRISM_EINVAL, "null argument");
   *count = 0;
+  if (int r = refresh(s)) return r;
   for (auto it = s->ticket_batch.begin(); it != s->ticket_batch.end() && *count < capacity;) {
-    Batch& bt = s->batches[it->second];
-    const hipError_t e = bt.done ? hipEventQuery(bt.done) : hipSuccess;
-    if (e == hipErrorNotReady) {
+    if (!s->batches[it->second].finished) {
       ++it;
       continue;
     }
-    if (e != hipSuccess) return hip_err(e, "query event");
     done[(*count)++] = it->first;
     const int b = it->second;
     it = s->ticket_batch.erase(it);
@@ -377,11 +564,14 @@ int prism_server_wait(prism_server* s, long long ticket) {
   if (!s) return set_error(PRISM_EINVAL, "null server");
   for (const Query& q : s->pending)
     if (q.ticket == ticket) return set_error(PRISM_EINVAL, "query not flushed yet");
+  for (const Build& b : s->builds)
+    if (b.ticket == ticket) return set_error(PRISM_EINVAL, "build not dispatched yet");
   auto it = s->ticket_batch.find(ticket);
   if (it == s->ticket_batch.end()) return set_error(PRISM_EINVAL, "unknown or already reported ticket");
   Batch& bt = s->batches[it->second];
-  if (bt.done)
+  if (bt.done && !bt.finished)
     if (hipError_t e = hipEventSynchronize(bt.done); e != hipSuccess) return hip_err(e, "wait");
+  finish(s, bt);
   const int b = it->second;
   s->ticket_batch.erase(it);
   recycle(s, b);
@@ -392,7 +582,7 @@ int prism_server_stats(const prism_server* s, size_t* smatrix_bytes_used, int* q
                        int* in_flight) {
   if (!s) return set_error(PRISM_EINVAL, "null server");
   if (smatrix_bytes_used) *smatrix_bytes_used = s->used;
-  if (queued) *queued = (int)s->pending.size();
+  if (queued) *queued = (int)(s->pending.size() + s->builds.size());
   if (in_flight) *in_flight = (int)s->ticket_batch.size();
   return PRISM_OK;
 }

@@ -484,3 +484,26 @@ def test_noalloc_rejects_probe_steps_beyond_its_scratch():
     r = L.prism_probe_outputs_noalloc(h, 3, amax, dummy, SBIG, dummy, 16, ctypes.byref(optics),
                                       ctypes.byref(det), dummy, None)
     assert r == _native.PRISM_EINVAL
+
+
+def test_tuning_roundtrip_and_validation():
+    p = _plan(1024, 40.0, 200.0, 2)
+    p.set_tuning({})
+    d = p.tuning()
+    assert d == dict(row_iters=16, row_min_groups=512, col_iters=8, col_min_groups=256,
+                     wave_chunk_mib=256, probe_group=0, window_tile_div=4)
+    amax = p.alpha_max_default(25.0, 4)
+    pref0, mn0 = p.build_workspace_bytes(4, amax)
+    p.set_tuning(dict(row_iters=4, col_min_groups=128, wave_chunk_mib=128, probe_group=32,
+                      window_tile_div=2))
+    t = p.tuning()
+    assert (t["row_iters"], t["col_min_groups"], t["wave_chunk_mib"], t["probe_group"],
+            t["window_tile_div"]) == (4, 128, 128, 32, 2)
+    pref1, mn1 = p.build_workspace_bytes(4, amax)
+    assert mn1 == mn0 and pref1 < pref0          # half the wave state per launch
+    assert p.probe_group(4) == (32, 8, 4)
+    for bad in (dict(row_iters=3), dict(col_iters=128), dict(wave_chunk_mib=8),
+                dict(probe_group=48), dict(window_tile_div=65), dict(row_min_groups=-1)):
+        with pytest.raises(PrismError):
+            p.set_tuning(bad)
+    assert p.tuning() == t                          # a refused setting changes nothing

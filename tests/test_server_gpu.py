@@ -140,3 +140,92 @@ def test_server_budget_and_evict(served):
     assert np.abs(out.cpu().numpy() - alone).max() <= 1e-6 * np.abs(alone).max()
     with pytest.raises(PrismError):
         srv.wait(t)                                          # already reported
+
+
+def test_server_continuous_batching_build_overlap_and_lru():
+    # Builds queued beside queries: specimen B's build is dispatched by the
+    # same flush as queries of A (running on the query slots while B builds)
+    # and of B (waiting on the device for its build). Every result must equal
+    # the same query run alone. Then, with LRU eviction on and a budget of
+    # B + C, C's queued build releases A (the least recently used idle
+    # S-matrix) and C's query equals its run alone and the oracle.
+    import torch
+    dA, dB, dC = build_inputs("tiny", 0), build_inputs("mid256", 2), build_inputs("tiny", 7)
+    ents = []
+    for d, f in ((dA, 2), (dB, 4), (dC, 1)):
+        plan = G.make_plan(d)
+        amax = _amax(d, f)
+        S = torch.empty((plan.beam_count(f, amax), plan.n // 2, plan.n // 2),
+                        dtype=torch.complex64, device=G.device())
+        ents.append(dict(d=d, f=f, plan=plan, amax=amax, S=S, bytes=S.numel() * 8))
+    eA, eB, eC = ents
+    probe_ws = max(e["plan"].probe_workspace_bytes(e["f"], e["amax"], e["d"]["optics"])[0]
+                   for e in ents)
+    wsb = G.workspace(max(e["plan"].build_workspace_bytes(e["f"], e["amax"])[0] for e in ents))
+    ws = G.workspace(Server.workspace_bytes(3, 4096, 4, probe_ws))
+    srv = Server(eB["bytes"] + eC["bytes"], ws, n_streams=3, max_probes=4096, max_det=4)
+    torch.cuda.synchronize()
+    G.say("server admit A, queue build of B with queries of A and B")
+    eA["id"] = srv.admit(eA["plan"], eA["f"], eA["amax"], eA["S"], wsb)
+    eB["id"], tB = srv.submit_build(eB["plan"], eB["f"], eB["amax"], eB["S"], wsb)
+    rng = np.random.default_rng(5)
+    queries = []
+    for k in range(10):
+        e = eA if k < 6 else eB
+        d = e["d"]
+        P = int(rng.integers(1, min(200, len(d["probes"])) + 1))
+        sel = rng.choice(len(d["probes"]), P, replace=False)
+        xy = G.upload(d["probes"][sel])
+        out = torch.full((P, len(d["edges"])), float("nan"), dtype=torch.float64,
+                         device=G.device())
+        t = srv.submit(e["id"], xy, d["optics"], d["edges"], out)
+        queries.append(dict(e=e, xy=xy, out=out, sel=sel, t=t))
+    assert srv.stats()[1] == 11            # ten queries and one build queued
+    srv.flush()
+    assert srv.stats()[1] == 0
+    srv.wait(tB)
+    done = set()
+    while len(done) < len(queries):
+        done.update(srv.poll())
+    worst = 0.0
+    for q in queries:
+        e = q["e"]
+        alone = G.probe_outputs(e["plan"], e["f"], e["amax"], e["S"], q["xy"].cpu().numpy(),
+                                e["d"]["optics"], e["d"]["edges"])
+        got = q["out"].cpu().numpy()
+        worst = max(worst, float(np.abs(got - alone).max() / np.abs(alone).max()))
+    print(f"server with an overlapping build: worst max rel diff to alone {worst:.3e}")
+    assert worst <= 1e-6
+    # B's S-matrix from the queued build against the oracle, on its queries
+    d = dB
+    beams, Sref = O.smatrix(d["phase"], d["thickness"], d["cell"], d["energy_keV"], eB["f"],
+                            eB["amax"])
+    for q in queries:
+        if q["e"] is eB:
+            ref = O.prism_outputs(Sref, beams, eB["f"], d["cell"], d["energy_keV"], d["optics"],
+                                  d["probes"][q["sel"]], d["edges"])
+            assert eps(q["out"].cpu().numpy(), ref) <= TOL
+    # LRU admission: C needs A's bytes; A was used before B
+    srv.set_lru_eviction(True)
+    G.say("server queue build of C under LRU eviction")
+    eC["id"], tC = srv.submit_build(eC["plan"], eC["f"], eC["amax"], eC["S"], wsb)
+    xyC = G.upload(dC["probes"][:40])
+    outC = torch.full((40, len(dC["edges"])), float("nan"), dtype=torch.float64,
+                      device=G.device())
+    qC = srv.submit(eC["id"], xyC, dC["optics"], dC["edges"], outC)
+    srv.flush()
+    srv.wait(tC)
+    srv.wait(qC)
+    assert srv.evictions() == [eA["id"]]
+    assert srv.stats()[0] == eB["bytes"] + eC["bytes"]
+    with pytest.raises(PrismError):       # A is gone
+        srv.submit(eA["id"], xyC, dA["optics"], dA["edges"], outC)
+    alone = G.probe_outputs(eC["plan"], eC["f"], eC["amax"], eC["S"], dC["probes"][:40],
+                            dC["optics"], dC["edges"])
+    assert np.abs(outC.cpu().numpy() - alone).max() <= 1e-6 * np.abs(alone).max()
+    beams, Sref = O.smatrix(dC["phase"], dC["thickness"], dC["cell"], dC["energy_keV"], eC["f"],
+                            eC["amax"])
+    ref = O.prism_outputs(Sref, beams, eC["f"], dC["cell"], dC["energy_keV"], dC["optics"],
+                          dC["probes"][:40], dC["edges"])
+    assert eps(outC.cpu().numpy(), ref) <= TOL
+    srv.close()
