@@ -147,9 +147,13 @@ def test_probe_precision_setting_and_workspace():
 
 def test_probe_group_shapes():
     p = Plan(1024, 40.0, 200.0, [2.0])
+    p.set_tuning({})                      # the library's own choice, per window size
     assert p.probe_group(4) == (64, 8, 8)
     assert p.probe_group(8) == (32, 8, 4)
     assert p.probe_group(16) == (16, 4, 4)
+    p.set_tuning({"probe_group": 16})     # a fixed group for every factor
+    assert p.probe_group(4) == (16, 4, 4)
+    assert p.probe_group(8) == (16, 4, 4)
 
 
 def _raw(p):
