@@ -263,6 +263,55 @@ int prism_probe_cbed(prism_plan* plan, int f, double alpha_max_mrad, const void*
                      const prism_optics* optics, float* cbed_dev, void* ws, size_t ws_bytes,
                      void* stream);
 
+/* The probe step (Fig. 1d-f, Eqs. RegionBounds and PRISMfinal) for several
+ * requests in one call: each request is the work of one prism_probe_outputs
+ * (detector != NULL) or prism_probe_cbed (detector == NULL) call, or of
+ * their _accumulate forms (accumulate != 0: out += weight * result), with
+ * its own plan, f, alpha_max, S-matrix, positions, optics and outputs; the
+ * optics and detector edges are read during the call. Results equal those
+ * of the separate calls bit for bit. Requests whose plans give the same
+ * window side n/(2f), probe group, window tiles (prism_tuning) and operand
+ * precision, and that ask for the same output kind, share each chunk's
+ * window-sum and window-transform launches (several specimens in one
+ * launch); each distinct (S-matrix, active beam set) is packed once per
+ * workspace fill. Requests of one batch must write disjoint outputs. All
+ * plans must be on the device of the stream; none of them may be used
+ * concurrently on another stream while the batch is in flight.
+ * Workspace: prism_probe_batch_workspace_bytes gives the size that runs
+ * each launch class in one fill (preferred) and the size of the largest
+ * single request's minimum (minimum); with less than preferred the call
+ * runs the requests in several fills, in order.
+ * Errors: PRISM_EINVAL (null or invalid request, negative count; the checks
+ * of the single calls, message prefixed by the request index), then
+ * PRISM_ENOSPACE, PRISM_EHIP. Every request is checked before anything is
+ * enqueued. count == 0 is a no-op. */
+typedef struct {
+  prism_plan* plan;
+  int f;
+  double alpha_max_mrad;
+  const void* smatrix_dev;
+  size_t smatrix_bytes;
+  const double* probe_xy_dev;      /* [n_probes][2], Angstrom            */
+  int n_probes;
+  const prism_optics* optics;
+  const prism_detector* detector;  /* NULL: full CBED output             */
+  double* out_dev;                 /* detector: float64 [n_probes][n_det] */
+  float* cbed_dev;                 /* CBED: float32 [n_probes][W][W]      */
+  int accumulate;                  /* 0: store; 1: add weight * result   */
+  double weight;
+} prism_probe_request;
+
+/* Launch class of the probe step for (plan, f): requests of one
+ * prism_probe_batch call with equal keys and the same output kind share
+ * their window-sum and window launches (the key encodes the window side,
+ * probe group, window tiles and operand precision; its value has no other
+ * meaning). Errors: PRISM_EINVAL for an invalid f or window side. */
+int prism_probe_class(const prism_plan* plan, int f, unsigned long long* key);
+int prism_probe_batch_workspace_bytes(const prism_probe_request* requests, int count,
+                                      size_t* preferred, size_t* minimum);
+int prism_probe_batch(const prism_probe_request* requests, int count, void* ws,
+                      size_t ws_bytes, void* stream);
+
 /* Conventional multislice STEM (Eq. 5 run once per probe): incident probe
  * iFFT[A e^{-i chi} e^{-2 pi i q.r0}] n / sqrt(N_A) (tilt as in prism_optics),
  * H slice steps,
@@ -318,13 +367,18 @@ int prism_multislice_outputs_accumulate(prism_plan* plan, const double* probe_xy
  *     admission); with LRU eviction on, idle S-matrices (no queued query,
  *     nothing in flight) are released least recently used first to make
  *     room, and reported by prism_server_evictions;
- *   - every queued query of one (specimen, optics, detector) merged into
- *     probe-step calls of up to max_probes positions, each call sent to the
- *     first query slot (one of n_streams HIP streams, default priority)
- *     whose earlier calls have all finished, else to the slot with the
- *     fewest calls in flight. A query's slot waits on the device for its
- *     S-matrix's build, so builds and other specimens' queries overlap.
- * A query's result is the prism_probe_outputs result for its own positions.
+ *   - the queued queries whose specimen's build has been dispatched,
+ *     bucketed by launch class (prism_probe_class) in arrival order and
+ *     merged into prism_probe_batch calls of up to max_probes positions:
+ *     queries of different specimens and optics in one bucket share the
+ *     window-sum and window launches, and the queries of one (specimen,
+ *     optics, detector) form one request. Each call goes to the first query
+ *     slot (one of n_streams HIP streams, default priority) whose earlier
+ *     calls have all finished, else to the slot with the fewest calls in
+ *     flight. A call's slot waits on the device for the builds of the
+ *     S-matrices it reads, so builds and other specimens' queries overlap.
+ * A query's result is the prism_probe_outputs result for its own positions
+ * (bit for bit, whatever it was merged with).
  *
  * Workspace: the caller's device buffer, split into one region per query
  * slot; a region holds the staged positions (max_probes x 2 doubles) and
@@ -410,6 +464,12 @@ int prism_server_wait(prism_server* server, long long ticket);
  * builds, and dispatched-but-unreported tickets (any pointer may be NULL). */
 int prism_server_stats(const prism_server* server, size_t* smatrix_bytes_used, int* queued,
                        int* in_flight);
+/* Probe-step calls the server has dispatched (prism_probe_batch calls), and
+ * how many of them read more than one specimen's S-matrix (queries of
+ * several specimens merged into shared launches). Either pointer may be
+ * NULL. */
+int prism_server_call_stats(const prism_server* server, long long* probe_calls,
+                            long long* multi_specimen_calls);
 
 /* Launch shapes of a plan, none of which changes any result (the same
  * operations run in the same order; only their distribution over

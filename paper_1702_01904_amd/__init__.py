@@ -13,7 +13,7 @@ from . import _native
 from ._native import PrismError, PrismOptics, PrismDetector, PrismGeometry  # noqa: F401
 
 __all__ = ["Plan", "PrismError", "Server", "build_batch_workspace_bytes", "build_smatrix_batch",
-           "tile_order", "untile"]
+           "probe_batch", "probe_batch_workspace_bytes", "tile_order", "untile"]
 
 
 def _ptr(t):
@@ -186,6 +186,12 @@ class Plan:
         _native.check(self._L.prism_probe_group(self._h, int(f), ctypes.byref(g), ctypes.byref(tx),
                                                 ctypes.byref(ty)))
         return g.value, tx.value, ty.value
+
+    def probe_class(self, f):
+        """Launch-class key of the probe step (prism_probe_class)."""
+        k = ctypes.c_ulonglong()
+        _native.check(self._L.prism_probe_class(self._h, int(f), ctypes.byref(k)))
+        return k.value
 
     # ------------------------------------------------------------ kernel timing
     def probe_order(self, f, probes):
@@ -376,6 +382,67 @@ def build_smatrix_batch(items, workspace, stream=None):
                                                           workspace.numel(), _stream_ptr(stream)))
 
 
+class _Requests:
+    """prism_probe_request array for probe_batch; keeps the optics and
+    detector structs alive while the C array points at them."""
+
+    def __init__(self, requests, with_buffers):
+        import torch
+        self.keep = []
+        self.arr = (_native.PrismProbeRequest * max(1, len(requests)))()
+        for k, r in enumerate(requests):
+            plan, f, amax = r["plan"], int(r["f"]), float(r["alpha_max_mrad"])
+            o = _optics(r["optics"])
+            edges = r.get("edges_mrad")
+            det = _Det(edges) if edges is not None else None
+            self.keep += [o, det]
+            S = xy = out = None
+            P = int(r["probe_xy"].shape[0]) if r.get("probe_xy") is not None else int(r.get("n_probes", 0))
+            if with_buffers:
+                S, xy, out = r["smatrix"], r["probe_xy"], r["out"]
+                _check_dev(S, torch.complex64, None, f"smatrix of request {k}")
+                _check_dev(xy, torch.float64, 2 * P, f"probe_xy of request {k}")
+                if det is not None:
+                    _check_dev(out, torch.float64, P * det.edges.shape[0], f"out of request {k}")
+                else:
+                    w = plan.n // (2 * f)
+                    _check_dev(out, torch.float32, P * w * w, f"cbed out of request {k}")
+            weight = r.get("weight")
+            self.arr[k] = _native.PrismProbeRequest(
+                plan._h, f, amax, _ptr(S) if S is not None else None,
+                _nbytes(S) if S is not None else 0, _ptr(xy) if xy is not None else None, P,
+                ctypes.pointer(o), ctypes.pointer(det.struct) if det is not None else None,
+                _ptr(out) if (out is not None and det is not None) else None,
+                _ptr(out) if (out is not None and det is None) else None,
+                0 if weight is None else 1, 0.0 if weight is None else float(weight))
+
+
+def probe_batch_workspace_bytes(requests):
+    """(preferred, minimum) workspace bytes of probe_batch for the same
+    requests (device buffers not needed: give n_probes instead of probe_xy)."""
+    rq = _Requests(requests, False)
+    pref, mn = ctypes.c_size_t(), ctypes.c_size_t()
+    _native.check(_native.lib().prism_probe_batch_workspace_bytes(
+        rq.arr, len(requests), ctypes.byref(pref), ctypes.byref(mn)))
+    return pref.value, mn.value
+
+
+def probe_batch(requests, workspace, stream=None):
+    """Probe steps of several requests in shared launches (prism_probe_batch).
+
+    requests: dicts with plan, f, alpha_max_mrad, smatrix (complex64 device
+    [B][n/2][n/2]), probe_xy (float64 device [P][2]), optics (dict as for
+    probe_outputs), edges_mrad ([n_det][2]; None for the full CBED), out
+    (float64 [P][n_det], or float32 [P][W][W] for the CBED) and optionally
+    weight (out += weight * result). workspace: uint8 device tensor.
+    """
+    import torch
+    _check_dev(workspace, torch.uint8, None, "workspace")
+    rq = _Requests(requests, True)
+    _native.check(_native.lib().prism_probe_batch(rq.arr, len(requests), _ptr(workspace),
+                                                  workspace.numel(), _stream_ptr(stream)))
+
+
 class Server:
     """Resident S-matrices and merged probe queries (prism_server_*).
 
@@ -500,6 +567,12 @@ class Server:
         _native.check(self._L.prism_server_stats(self._h, ctypes.byref(b), ctypes.byref(q),
                                                  ctypes.byref(f)))
         return b.value, q.value, f.value
+
+    def call_stats(self):
+        """(probe-step calls dispatched, calls that read several specimens)."""
+        c, m = ctypes.c_longlong(), ctypes.c_longlong()
+        _native.check(self._L.prism_server_call_stats(self._h, ctypes.byref(c), ctypes.byref(m)))
+        return c.value, m.value
 
 
 def tile_order(nx, ny, tx, ty):

@@ -29,12 +29,14 @@ EXPORTS = (
     "prism_probe_outputs", "prism_probe_outputs_noalloc", "prism_probe_cbed",
     "prism_multislice_outputs",
     "prism_probe_outputs_accumulate", "prism_probe_cbed_accumulate",
+    "prism_probe_batch_workspace_bytes", "prism_probe_batch", "prism_probe_class",
     "prism_multislice_outputs_accumulate", "prism_build_batch_workspace_bytes",
     "prism_build_smatrix_batch", "prism_server_workspace_bytes", "prism_server_create",
     "prism_server_destroy", "prism_server_admit", "prism_server_submit_build",
     "prism_server_set_lru_eviction", "prism_server_evictions", "prism_server_evict",
     "prism_server_submit",
     "prism_server_flush", "prism_server_poll", "prism_server_wait", "prism_server_stats",
+    "prism_server_call_stats",
     "prism_set_tuning", "prism_get_tuning", "prism_profile_enable", "prism_profile_report",
     "prism_last_error",
 )
@@ -59,6 +61,16 @@ class PrismBuildItem(ctypes.Structure):
     _fields_ = [("plan", ctypes.c_void_p), ("f", ctypes.c_int),
                 ("alpha_max_mrad", ctypes.c_double), ("smatrix_dev", ctypes.c_void_p),
                 ("smatrix_bytes", ctypes.c_size_t)]
+
+
+class PrismProbeRequest(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("f", ctypes.c_int),
+                ("alpha_max_mrad", ctypes.c_double), ("smatrix_dev", ctypes.c_void_p),
+                ("smatrix_bytes", ctypes.c_size_t), ("probe_xy_dev", ctypes.c_void_p),
+                ("n_probes", ctypes.c_int), ("optics", ctypes.POINTER(PrismOptics)),
+                ("detector", ctypes.POINTER(PrismDetector)), ("out_dev", ctypes.c_void_p),
+                ("cbed_dev", ctypes.c_void_p), ("accumulate", ctypes.c_int),
+                ("weight", ctypes.c_double)]
 
 
 class PrismTuning(ctypes.Structure):
@@ -131,6 +143,9 @@ def lib():
         "prism_multislice_outputs_accumulate": (I, [P, P, I, ctypes.POINTER(PrismOptics),
                                                     ctypes.POINTER(PrismDetector), D, P, P,
                                                     ctypes.c_size_t, P]),
+        "prism_probe_batch_workspace_bytes": (I, [ctypes.POINTER(PrismProbeRequest), I, SZ, SZ]),
+        "prism_probe_batch": (I, [ctypes.POINTER(PrismProbeRequest), I, P, ctypes.c_size_t, P]),
+        "prism_probe_class": (I, [P, I, ctypes.POINTER(ctypes.c_ulonglong)]),
         "prism_build_batch_workspace_bytes": (I, [ctypes.POINTER(PrismBuildItem), I, SZ, SZ]),
         "prism_build_smatrix_batch": (I, [ctypes.POINTER(PrismBuildItem), I, P, ctypes.c_size_t,
                                           P]),
@@ -152,6 +167,8 @@ def lib():
         "prism_server_poll": (I, [P, ctypes.POINTER(ctypes.c_longlong), I, ctypes.POINTER(I)]),
         "prism_server_wait": (I, [P, ctypes.c_longlong]),
         "prism_server_stats": (I, [P, SZ, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "prism_server_call_stats": (I, [P, ctypes.POINTER(ctypes.c_longlong),
+                                        ctypes.POINTER(ctypes.c_longlong)]),
         "prism_set_tuning": (I, [P, ctypes.POINTER(PrismTuning)]),
         "prism_get_tuning": (I, [P, ctypes.POINTER(PrismTuning)]),
         "prism_profile_enable": (I, [P, I]),

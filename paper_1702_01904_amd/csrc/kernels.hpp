@@ -140,9 +140,30 @@ hipError_t launch_alpha16(const double* probe_xy, int p0, int np, const ActiveBe
                           int n_act, int n_actp, int f, int ns, int w, const ProbeOptics& po,
                           const float* scale, int group, void* a16, int2* origin, Prec prec,
                           hipStream_t st);
-hipError_t launch_contract16(const void* s16, int n_actp, const void* a16, const int2* origin,
-                             int np, int ns, int w, int group, float out_scale, float2* window,
-                             Prec prec, int window_tile_div, hipStream_t st);
+// Segments of one window-sum launch: the probe groups of several requests
+// (specimens, optics) that share the window side, operand form and group
+// size. Segment k owns the launch's groups g_begin .. g_begin +
+// ceil(np / G) (its probes' A blocks at a16, group-major) and writes the
+// windows of its np probes from window on (contiguous, probe order).
+constexpr int kMaxSeg = 16;
+struct ContractSeg {
+  const uint32_t* s16;  // packed S of its specimen: [ns^2][rowlen] words
+  const uint32_t* a16;  // [groups][K blocks][2G][32 words]
+  const int2* origin;   // [np] window origins
+  float2* window;       // [np][w][w]
+  int rowlen;           // 32-bit words per packed pixel row
+  int ns;               // S-matrix side (n / 2)
+  int np;               // probes
+  int g_begin;          // first group of the launch's grid
+  float out_scale;      // 1 / (W sqrt(B_A)) of its active beams
+};
+struct ContractSegs {
+  int n;       // segments
+  int groups;  // groups over all segments
+  ContractSeg s[kMaxSeg];
+};
+hipError_t launch_contract16(const ContractSegs& segs, int w, int group, Prec prec,
+                             int window_tile_div, hipStream_t st);
 // Detector bins as lists of window pixels (v * W + u of the W x W window),
 // cut into chunks of kWdListChunk entries: bin j owns the chunks
 // off[j] .. off[j+1]), i.e. pix[off[j] 64 .. off[j+1] 64), its last chunk
@@ -173,12 +194,28 @@ __host__ __device__ constexpr bool window_side_ok(int w) {
          w == 24 || w == 36 || w == 48 || w == 72 || w == 96 || w == 144 || w == 192 ||
          w == 256;
 }
+// Segments of one window launch (W <= 128): windows begin .. next begin
+// (or total) of the window buffer belong to segment k, whose probe q =
+// window - begin stores into out[q][n_det] (detector sums, pixel lists pix
+// with the device copy lists of their offsets) or cbed[q][W][W].
+struct WindowSeg {
+  const uint16_t* pix;
+  const BinLists* lists;
+  double* out;
+  float* cbed;
+  OutAcc oa;
+  int begin;
+};
+struct WindowSegs {
+  int n;      // segments
+  int total;  // windows
+  WindowSeg s[kMaxSeg];
+};
 // Full CBED output: cbed[p][ky][kx] = |FFT_W window_p|^2 / W^2 (float32,
 // window fftfreq order), W <= 128 (larger windows: launch_window_big).
-hipError_t launch_window_cbed(const float2* window, int np, int w, const float2* twW,
-                              float* cbed, OutAcc acc, hipStream_t st);
-hipError_t launch_window_detect(const float2* window, int np, int w, const float2* twW,
-                                const uint16_t* pix, const BinLists& lists, double* out,
-                                OutAcc acc, hipStream_t st);
+hipError_t launch_window_cbed(const float2* window, const WindowSegs& segs, int w,
+                              const float2* twW, hipStream_t st);
+hipError_t launch_window_detect(const float2* window, const WindowSegs& segs, int w,
+                                const float2* twW, hipStream_t st);
 
 }  // namespace prism

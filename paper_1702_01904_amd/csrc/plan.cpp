@@ -389,19 +389,6 @@ int choose_chunk(const prism_plan* p, int want, int n_beams, int n_det, size_t w
   return 0;
 }
 
-struct ProbeWs {
-  float2* twW;
-  uint16_t* pix;
-  prism::ActiveBeam* act;
-  float* scale;     // 16-bit: [n_act] power-of-two beam scales
-  float* scale_part;  // 16-bit: [n_act][kScaleSplit] per-block maxima
-  uint32_t* s16;    // packed S: [ns^2][n_actp] (re, im), one word (16-bit) or two (FP32)
-  uint32_t* a16;    // packed alpha: [chunk / G][K blocks][2G][32 words]
-  int2* origin;
-  float2* window;
-  double* partial;  // W > 128: [chunk][tiles][PRISM_MAX_DET] detector partials
-};
-
 // Operand form of the packed window sum for a plan precision.
 prism::Prec packed_prec(int prec) {
   return prec == PRISM_PREC_BF16 ? prism::Prec::kBF16
@@ -414,27 +401,62 @@ int padded_beams(int n_act, prism::Prec pk) {
   return (n_act + pad - 1) / pad * pad;
 }
 
-size_t probe_layout(int w, int ns, int n_act, int chunk, int prec, ProbeWs* pw, void* base) {
+// Probe-step workspace of one sub-batch: requests of one launch class (same
+// window side w, group G, operand form), their distinct packed S-matrices
+// and detector pixel-list sets, and the per-chunk buffers of `chunk` probes.
+struct PackShape {
+  int n_act, n_actp, ns;
+};
+struct PackWs {
+  prism::ActiveBeam* act;
+  float* scale;       // 16-bit: [n_act] power-of-two beam scales
+  float* scale_part;  // 16-bit: [n_act][kScaleSplit] per-block maxima
+  uint32_t* s16;      // packed S: [ns^2][n_actp] (re, im), one word (16-bit) or two (FP32)
+};
+struct ProbeBatchWs {
+  float2* twW;
+  std::vector<PackWs> packs;
+  std::vector<uint16_t*> pix;  // per pixel-list set: bins as lists of window pixels
+  std::vector<prism::BinLists*> lists;
+  uint32_t* a16;    // packed alpha: [groups][K blocks][2G][32 words]
+  int2* origin;     // [chunk]
+  float2* window;   // [chunk][w][w]
+  double* partial;  // W > 128: [chunk][tiles][PRISM_MAX_DET] detector partials
+};
+
+size_t probe_batch_layout(int w, int G, prism::Prec pk, const std::vector<PackShape>& packs,
+                    int n_lists, int n_reqs, int chunk, ProbeBatchWs* bw, void* base) {
   Carve c(base);
-  pw->twW = c.take<float2>(w);
+  bw->twW = c.take<float2>(w);
+  bw->packs.resize(packs.size());
+  int nblk_max = 1;
+  for (size_t k = 0; k < packs.size(); ++k) {
+    const PackShape& ps = packs[k];
+    PackWs& pw = bw->packs[k];
+    pw.act = c.take<prism::ActiveBeam>(ps.n_act);
+    pw.scale = pk == prism::Prec::kF32 ? nullptr : c.take<float>(ps.n_act);
+    pw.scale_part =
+        pk == prism::Prec::kF32 ? nullptr : c.take<float>((size_t)ps.n_act * prism::kScaleSplit);
+    pw.s16 = c.take<uint32_t>((size_t)ps.ns * ps.ns * ps.n_actp * prism::prec_words(pk));
+    nblk_max = std::max(nblk_max, ps.n_actp / prism::prec_block_beams(pk));
+  }
   // per-bin pixel lists (W <= 128), worst case: every bin holds every pixel
   // and a padded last chunk
-  pw->pix = c.take<uint16_t>(
-      prism::window_big(w) ? 0 : (size_t)PRISM_MAX_DET * ((size_t)w * w + prism::kWdListChunk));
-  pw->act = c.take<prism::ActiveBeam>(n_act);
-  const prism::Prec pk = packed_prec(prec);
-  const int n_actp = padded_beams(n_act, pk);
-  pw->scale = pk == prism::Prec::kF32 ? nullptr : c.take<float>(n_act);
-  pw->scale_part =
-      pk == prism::Prec::kF32 ? nullptr : c.take<float>((size_t)n_act * prism::kScaleSplit);
-  pw->s16 = c.take<uint32_t>((size_t)ns * ns * n_actp * prism::prec_words(pk));
-  // per probe: n_actp / KB blocks x 2 rows x 32 words
-  pw->a16 = c.take<uint32_t>((size_t)chunk * (n_actp / prism::prec_block_beams(pk)) * 64);
-  pw->origin = c.take<int2>(chunk);
-  pw->window = c.take<float2>((size_t)chunk * w * w);
-  pw->partial = prism::window_big(w)
+  bw->pix.resize(n_lists);
+  bw->lists.resize(n_lists);
+  for (int k = 0; k < n_lists; ++k) {
+    bw->pix[k] = c.take<uint16_t>((size_t)PRISM_MAX_DET * ((size_t)w * w + prism::kWdListChunk));
+    bw->lists[k] = c.take<prism::BinLists>(1);
+  }
+  // a chunk's pieces (at most one per request, kMaxSeg at most) each add
+  // at most one partial group to the chunk / G whole ones
+  const int groups = chunk / G + std::min(prism::kMaxSeg, std::max(n_reqs, 1)) - 1;
+  bw->a16 = c.take<uint32_t>((size_t)groups * nblk_max * 2 * G * prism::kC16KB);
+  bw->origin = c.take<int2>(chunk);
+  bw->window = c.take<float2>((size_t)chunk * w * w);
+  bw->partial = prism::window_big(w)
                     ? c.take<double>((size_t)chunk * prism::window_big_tiles(w) * PRISM_MAX_DET)
-                         : nullptr;
+                    : nullptr;
   return c.used + 256;
 }
 
@@ -496,105 +518,318 @@ int out_mode(bool accumulate, double weight, prism::OutAcc* oa) {
   return PRISM_OK;
 }
 
-// PRISM probe step (Fig. 1d-f). d != nullptr: detector sums into out;
-// d == nullptr: full CBED intensities into cbed. oa selects overwrite or
-// weighted accumulation of the results.
-int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, size_t S_bytes,
-               const double* xy, int P,
-               const prism_optics* o, const prism_detector* d, double* out, float* cbed,
-               prism::OutAcc oa, void* ws, size_t ws_bytes, void* stream) {
+// ---------------------------------------------------------------------------
+// PRISM probe step (Fig. 1d-f) over a batch of requests. Each request is
+// the work of one prism_probe_outputs / prism_probe_cbed call (its own
+// specimen, S-matrix, optics, detector and outputs). Requests with the same
+// window side, probe group, window tiles, operand form and output kind form
+// a launch class: per chunk of probes the window sum and the window
+// detector run once over all of the class's requests (one segment each),
+// while the S-matrix packing (once per distinct S-matrix and active beam
+// set) and the coefficients (per piece) run per request. Every probe group
+// lies inside one request and is computed as in a call of its own, so the
+// results do not depend on what else is in the batch.
+
+struct Req {
+  prism_plan* p;
+  int f;
+  double amax;
+  const float2* S;
+  const double* xy;
+  int P;
+  prism_optics o;
+  bool cbed_out;
+  prism::DetBins bins;
+  double* out;
+  float* cbed;
+  prism::OutAcc oa;
+  const std::vector<prism::ActiveBeam>* act;
+  const prism_plan::PixLists* pl;  // detector sums with W <= 128
+  prism::ProbeOptics po;           // norm 1: the scale is applied by the window sum
+  float out_scale;                 // 1 / (W sqrt(B_A))
+  int w, ns, G, tile_div, n_act, n_actp;
+  prism::Prec pr;
+};
+
+bool same_class(const Req& a, const Req& b) {
+  return a.w == b.w && a.G == b.G && a.tile_div == b.tile_div && a.pr == b.pr &&
+         a.cbed_out == b.cbed_out;
+}
+bool same_pack(const Req& a, const Req& b) {
+  return a.S == b.S && a.act == b.act && a.pr == b.pr && a.ns == b.ns;
+}
+
+// Every check of a probe-step call; buffers are checked only when the call
+// is to run (buffers == true) and has probes. d == nullptr: CBED output.
+int check_request(prism_plan* p, int f, double amax_mrad, const void* S, size_t S_bytes,
+                  const double* xy, int P, const prism_optics* o, const prism_detector* d,
+                  double* out, float* cbed, prism::OutAcc oa, bool buffers, Req* r) {
+  if (!p) return fail(PRISM_EINVAL, "null plan");
   const std::vector<int32_t>* mn;
-  if (int r = beams_checked(p, f, amax_mrad, &mn)) return r;
+  if (int e = beams_checked(p, f, amax_mrad, &mn)) return e;
   if (P < 0) return fail(PRISM_EINVAL, "negative probe count");
-  if (int r = check_optics(p, o)) return r;
+  if (int e = check_optics(p, o)) return e;
   if (o->alpha_mrad + std::hypot(o->tilt_x_mrad, o->tilt_y_mrad) > amax_mrad)
     return fail(PRISM_EINVAL, "probe semi-angle plus tilt exceeds the beam set's alpha_max");
-  const bool want_cbed = d == nullptr;
-  prism::DetBins bins{};
-  if (!want_cbed)
-    if (int r = make_bins(p, d, &bins)) return r;
-  const int n = p->n, ns = n / 2, w = n / (2 * f);
+  r->cbed_out = d == nullptr;
+  std::memset(&r->bins, 0, sizeof r->bins);
+  if (!r->cbed_out)
+    if (int e = make_bins(p, d, &r->bins)) return e;
+  const int n = p->n, w = n / (2 * f);
   if (!prism::window_side_ok(w))
     return fail(PRISM_EINVAL,
                 "window side n/(2f) must be a power of two in 8..256 or one of 12, 18, 24, 36, "
                 "48, 72, 96, 144, 192");
   const auto* act = get_active(p, f, amax_mrad, *mn, o);
-  const int n_act = (int)act->size();
-  if (n_act < 1) return fail(PRISM_EINVAL, "no beam of the set lies inside the probe aperture");
-  if (P == 0) return PRISM_OK;
-  if (!S || !xy || !ws || (want_cbed ? !cbed : !out)) return fail(PRISM_EINVAL, "null device buffer");
-  if (S_bytes < smatrix_need(p, *mn))
-    return fail(PRISM_EINVAL, "S-matrix buffer smaller than prism_smatrix_bytes for this f and alpha_max");
-  const int G = group_of(p, w);
-  void* base = aligned_base(ws);
-  const size_t avail = ws_bytes;  // layouts include 256 B of alignment slack
-  ProbeWs pw;
-  int chunk = std::min(pref_probe_chunk(w, G), (P + G - 1) / G * G);
-  const int prec = p->prec;
-  while (chunk >= G && probe_layout(w, ns, n_act, chunk, prec, &pw, nullptr) > avail)
-    chunk = chunk > 8 * G ? (chunk * 3 / 4) / G * G : chunk - G;
-  if (chunk < G) return fail(PRISM_ENOSPACE, "workspace smaller than the probe-step minimum");
-  probe_layout(w, ns, n_act, chunk, prec, &pw, base);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  LAUNCH(p, st, "twiddles", prism::launch_twiddles(pw.twW, w, st));
+  if (act->empty()) return fail(PRISM_EINVAL, "no beam of the set lies inside the probe aperture");
+  if (buffers && P > 0) {
+    if (!S || !xy || (r->cbed_out ? !cbed : !out)) return fail(PRISM_EINVAL, "null device buffer");
+    if (S_bytes < smatrix_need(p, *mn))
+      return fail(PRISM_EINVAL,
+                  "S-matrix buffer smaller than prism_smatrix_bytes for this f and alpha_max");
+  }
+  r->p = p;
+  r->f = f;
+  r->amax = amax_mrad;
+  r->S = static_cast<const float2*>(S);
+  r->xy = xy;
+  r->P = P;
+  r->o = *o;
+  r->out = out;
+  r->cbed = cbed;
+  r->oa = oa;
+  r->act = act;
+  r->w = w;
+  r->ns = n / 2;
+  r->G = group_of(p, w);
+  r->tile_div = p->tune.window_tile_div;
+  r->pr = packed_prec(p->prec);
+  r->n_act = (int)act->size();
+  r->n_actp = padded_beams(r->n_act, r->pr);
+  r->po = probe_optics(p, o);
+  r->out_scale = (float)(1.0 / ((double)w * std::sqrt((double)r->n_act)));
   // per-bin pixel lists drive the W <= 128 detector; larger windows bin per element
-  const prism_plan::PixLists* pl =
-      (prism::window_big(w) || want_cbed) ? nullptr : get_pixlists(p, w, f, bins);
-  if (pl && !pl->pix.empty())
-    HIP_TRY(hipMemcpyAsync(pw.pix, pl->pix.data(), pl->pix.size() * sizeof(uint16_t),
+  r->pl = (prism::window_big(w) || r->cbed_out) ? nullptr : get_pixlists(p, w, f, r->bins);
+  return PRISM_OK;
+}
+
+// Requests (indices) that run on one workspace fill: their distinct packed
+// S-matrices and pixel-list sets.
+struct Sub {
+  std::vector<int> reqs, pack_of, lists_of;  // per request
+  std::vector<int> packs, lists;             // first request of each
+  long long probes = 0;
+  void add(const std::vector<Req>& rq, int i) {
+    const Req& r = rq[i];
+    int k = 0;
+    while (k < (int)packs.size() && !same_pack(rq[packs[k]], r)) ++k;
+    if (k == (int)packs.size()) packs.push_back(i);
+    int l = -1;
+    if (r.pl) {
+      l = 0;
+      while (l < (int)lists.size() && rq[lists[l]].pl != r.pl) ++l;
+      if (l == (int)lists.size()) lists.push_back(i);
+    }
+    reqs.push_back(i);
+    pack_of.push_back(k);
+    lists_of.push_back(l);
+    probes += r.P;
+  }
+  size_t layout(const std::vector<Req>& rq, int chunk, ProbeBatchWs* bw, void* base) const {
+    const Req& r0 = rq[reqs[0]];
+    std::vector<PackShape> shapes;
+    for (int i : packs) shapes.push_back(PackShape{rq[i].n_act, rq[i].n_actp, rq[i].ns});
+    return probe_batch_layout(r0.w, r0.G, r0.pr, shapes, (int)lists.size(), (int)reqs.size(),
+                              chunk, bw, base);
+  }
+};
+
+// Probes of one request that one chunk holds: request probes q0 .. q0 + np
+// at windows begin .. begin + np of the chunk.
+struct Piece {
+  int req, sub_idx, q0, np, begin;
+};
+
+int run_sub(std::vector<Req>& rq, const Sub& sb, int chunk, void* base, hipStream_t st) {
+  ProbeBatchWs bw;
+  sb.layout(rq, chunk, &bw, base);
+  const Req& r0 = rq[sb.reqs[0]];
+  prism_plan* lp = r0.p;  // launches shared by the requests are timed on the first one's plan
+  const int w = r0.w, G = r0.G;
+  const prism::Prec pr = r0.pr;
+  const bool f32 = pr == prism::Prec::kF32, big = prism::window_big(w);
+  const size_t w2 = (size_t)w * w;
+  LAUNCH(lp, st, "twiddles", prism::launch_twiddles(bw.twW, w, st));
+  // host tables come from the plans' caches, whose entries are never
+  // rewritten, so the asynchronous copies may read them after the return
+  for (size_t l = 0; l < sb.lists.size(); ++l) {
+    const prism_plan::PixLists* pl = rq[sb.lists[l]].pl;
+    if (!pl->pix.empty())
+      HIP_TRY(hipMemcpyAsync(bw.pix[l], pl->pix.data(), pl->pix.size() * sizeof(uint16_t),
+                             hipMemcpyHostToDevice, st),
+              "copy detector pixel lists");
+    HIP_TRY(hipMemcpyAsync(bw.lists[l], &pl->lists, sizeof(prism::BinLists), hipMemcpyHostToDevice,
+                           st),
+            "copy detector bin offsets");
+  }
+  for (size_t k = 0; k < sb.packs.size(); ++k) {
+    const Req& r = rq[sb.packs[k]];
+    const PackWs& pw = bw.packs[k];
+    HIP_TRY(hipMemcpyAsync(pw.act, r.act->data(), r.act->size() * sizeof(prism::ActiveBeam),
                            hipMemcpyHostToDevice, st),
-            "copy detector pixel lists");
-  HIP_TRY(hipMemcpyAsync(pw.act, act->data(), act->size() * sizeof(prism::ActiveBeam),
-                         hipMemcpyHostToDevice, st),
-          "copy active beams");
-  prism::ProbeOptics po = probe_optics(p, o);
-  po.norm = 1.0 / ((double)w * std::sqrt((double)n_act));
-  const float2* Sd = static_cast<const float2*>(S);
-  // window FFT, |Psi|^2 and detector sums of one chunk of probes
-  auto window_stage = [&](int np, int p0) -> int {
-    if (want_cbed) {
-      float* dst = cbed + (size_t)p0 * w * w;
-      if (prism::window_big(w)) {
-        LAUNCH(p, st, "window_big_cbed",
-               prism::launch_window_big(pw.window, np, w, pw.twW, f, bins, nullptr, dst, oa, st));
-      } else {
-        LAUNCH(p, st, "window_cbed", prism::launch_window_cbed(pw.window, np, w, pw.twW, dst, oa, st));
+            "copy active beams");
+    if (!f32)
+      LAUNCH(r.p, st, "s16_scale",
+             prism::launch_s16_scale(r.S, pw.act, r.n_act, r.ns, pw.scale_part, pw.scale, st));
+    LAUNCH(r.p, st, f32 ? "s32_pack" : "s16_pack",
+           prism::launch_s16_pack(r.S, pw.act, r.n_act, r.n_actp, r.ns, pw.scale, pw.s16, pr, st));
+  }
+  std::vector<Piece> pc;
+  int used = 0;
+  auto flush = [&]() -> int {
+    prism::ContractSegs cs{};
+    cs.n = (int)pc.size();
+    size_t a16_off = 0;
+    int g = 0;
+    for (size_t k = 0; k < pc.size(); ++k) {
+      const Piece& x = pc[k];
+      const Req& r = rq[x.req];
+      const PackWs& pw = bw.packs[sb.pack_of[x.sub_idx]];
+      const int nblk = r.n_actp / prism::prec_block_beams(pr);
+      const int ngrp = (x.np + G - 1) / G;
+      uint32_t* a16 = bw.a16 + a16_off;
+      LAUNCH(r.p, st, f32 ? "alpha" : "alpha16",
+             prism::launch_alpha16(r.xy, x.q0, x.np, pw.act, r.n_act, r.n_actp, r.f, r.ns, w, r.po,
+                                   pw.scale, G, a16, bw.origin + x.begin, pr, st));
+      cs.s[k] = prism::ContractSeg{pw.s16, a16, bw.origin + x.begin, bw.window + x.begin * w2,
+                                   r.n_actp * prism::prec_words(pr), r.ns, x.np, g, r.out_scale};
+      g += ngrp;
+      a16_off += (size_t)ngrp * nblk * 2 * G * prism::kC16KB;
+    }
+    cs.groups = g;
+    LAUNCH(lp, st, f32 ? "contract" : "contract16",
+           prism::launch_contract16(cs, w, G, pr, r0.tile_div, st));
+    // window FFT, |Psi|^2 and detector sums (or the CBED)
+    if (big) {
+      for (const Piece& x : pc) {
+        const Req& r = rq[x.req];
+        float2* win = bw.window + x.begin * w2;
+        if (r.cbed_out) {
+          LAUNCH(r.p, st, "window_big_cbed",
+                 prism::launch_window_big(win, x.np, w, bw.twW, r.f, r.bins, nullptr,
+                                          r.cbed + (size_t)x.q0 * w2, r.oa, st));
+        } else {
+          LAUNCH(r.p, st, "window_big",
+                 prism::launch_window_big(win, x.np, w, bw.twW, r.f, r.bins, bw.partial, nullptr,
+                                          prism::OutAcc{0, 1.0}, st));
+          LAUNCH(r.p, st, "reduce_partials",
+                 prism::launch_reduce_partials(bw.partial, x.np, prism::window_big_tiles(w),
+                                               r.bins.n, r.out + (size_t)x.q0 * r.bins.n, r.oa,
+                                               st));
+        }
       }
-      return PRISM_OK;
-    }
-    double* dst = out + (size_t)p0 * bins.n;
-    if (prism::window_big(w)) {
-      LAUNCH(p, st, "window_big",
-             prism::launch_window_big(pw.window, np, w, pw.twW, f, bins, pw.partial, nullptr,
-                                      prism::OutAcc{0, 1.0}, st));
-      LAUNCH(p, st, "reduce_partials",
-             prism::launch_reduce_partials(pw.partial, np, prism::window_big_tiles(w), bins.n,
-                                           dst, oa, st));
     } else {
-      LAUNCH(p, st, "window_detect",
-             prism::launch_window_detect(pw.window, np, w, pw.twW, pw.pix, pl->lists, dst, oa, st));
+      prism::WindowSegs ws{};
+      ws.n = (int)pc.size();
+      ws.total = used;
+      for (size_t k = 0; k < pc.size(); ++k) {
+        const Piece& x = pc[k];
+        const Req& r = rq[x.req];
+        const int l = sb.lists_of[x.sub_idx];
+        ws.s[k] = prism::WindowSeg{l >= 0 ? bw.pix[l] : nullptr, l >= 0 ? bw.lists[l] : nullptr,
+                                   r.cbed_out ? nullptr : r.out + (size_t)x.q0 * r.bins.n,
+                                   r.cbed_out ? r.cbed + (size_t)x.q0 * w2 : nullptr, r.oa,
+                                   x.begin};
+      }
+      if (r0.cbed_out) {
+        LAUNCH(lp, st, "window_cbed", prism::launch_window_cbed(bw.window, ws, w, bw.twW, st));
+      } else {
+        LAUNCH(lp, st, "window_detect", prism::launch_window_detect(bw.window, ws, w, bw.twW, st));
+      }
     }
+    pc.clear();
+    used = 0;
     return PRISM_OK;
   };
-  const prism::Prec pr = packed_prec(prec);
-  const int n_actp = padded_beams(n_act, pr);
-  const float out_scale = (float)po.norm;
-  po.norm = 1.0;
-  if (pr != prism::Prec::kF32)
-    LAUNCH(p, st, "s16_scale", prism::launch_s16_scale(Sd, pw.act, n_act, ns, pw.scale_part, pw.scale, st));
-  LAUNCH(p, st, pr == prism::Prec::kF32 ? "s32_pack" : "s16_pack",
-         prism::launch_s16_pack(Sd, pw.act, n_act, n_actp, ns, pw.scale, pw.s16, pr, st));
-  for (int p0 = 0; p0 < P; p0 += chunk) {
-    const int np = std::min(chunk, P - p0);
-    LAUNCH(p, st, pr == prism::Prec::kF32 ? "alpha" : "alpha16",
-           prism::launch_alpha16(xy, p0, np, pw.act, n_act, n_actp, f, ns, w, po, pw.scale, G,
-                                 pw.a16, pw.origin, pr, st));
-    LAUNCH(p, st, pr == prism::Prec::kF32 ? "contract" : "contract16",
-           prism::launch_contract16(pw.s16, n_actp, pw.a16, pw.origin, np, ns, w, G, out_scale,
-                                    pw.window, pr, p->tune.window_tile_div, st));
-    if (int r = window_stage(np, p0)) return r;
+  for (size_t i = 0; i < sb.reqs.size(); ++i) {
+    const Req& r = rq[sb.reqs[i]];
+    for (int q = 0; q < r.P;) {
+      const int take = std::min(r.P - q, chunk - used);
+      pc.push_back(Piece{sb.reqs[i], (int)i, q, take, used});
+      used += take;
+      q += take;
+      if (used == chunk || (int)pc.size() == prism::kMaxSeg)
+        if (int e = flush()) return e;
+    }
+  }
+  if (!pc.empty())
+    if (int e = flush()) return e;
+  return PRISM_OK;
+}
+
+// The requests of one launch class, in order, in as few workspace fills as
+// the workspace allows.
+int run_class(std::vector<Req>& rq, const std::vector<int>& members, void* ws, size_t ws_bytes,
+              hipStream_t st) {
+  void* base = aligned_base(ws);
+  const int G = rq[members[0]].G;
+  const int pref = pref_probe_chunk(rq[members[0]].w, G);
+  auto chunk_for = [&](long long probes) {
+    return (int)std::max<long long>(G, std::min<long long>(pref, (probes + G - 1) / G * G));
+  };
+  ProbeBatchWs probe_ws;
+  size_t i = 0;
+  while (i < members.size()) {
+    Sub sb;
+    int chunk = 0;
+    for (size_t j = i; j < members.size(); ++j) {
+      Sub t = sb;
+      t.add(rq, members[j]);
+      const int c = chunk_for(t.probes);
+      if (t.layout(rq, c, &probe_ws, nullptr) > ws_bytes) break;
+      sb = std::move(t);
+      chunk = c;
+    }
+    if (sb.reqs.empty()) {
+      // the next request alone, on fewer probes per chunk
+      sb.add(rq, members[i]);
+      chunk = chunk_for(sb.probes);
+      while (chunk >= G && sb.layout(rq, chunk, &probe_ws, nullptr) > ws_bytes)
+        chunk = chunk > 8 * G ? (chunk * 3 / 4) / G * G : chunk - G;
+      if (chunk < G) return fail(PRISM_ENOSPACE, "workspace smaller than the probe-step minimum");
+    }
+    if (int e = run_sub(rq, sb, chunk, base, st)) return e;
+    i += sb.reqs.size();
   }
   return PRISM_OK;
+}
+
+// Launch classes in order of first appearance; requests without probes run
+// nothing.
+int run_batch(std::vector<Req>& rq, void* ws, size_t ws_bytes, hipStream_t st) {
+  std::vector<std::vector<int>> classes;
+  for (int i = 0; i < (int)rq.size(); ++i) {
+    if (rq[i].P == 0) continue;
+    size_t c = 0;
+    while (c < classes.size() && !same_class(rq[classes[c][0]], rq[i])) ++c;
+    if (c == classes.size()) classes.emplace_back();
+    classes[c].push_back(i);
+  }
+  if (classes.empty()) return PRISM_OK;
+  if (!ws) return fail(PRISM_EINVAL, "null workspace");
+  for (const auto& members : classes)
+    if (int e = run_class(rq, members, ws, ws_bytes, st)) return e;
+  return PRISM_OK;
+}
+
+int probe_step(prism_plan* p, int f, double amax_mrad, const void* S, size_t S_bytes,
+               const double* xy, int P, const prism_optics* o, const prism_detector* d,
+               double* out, float* cbed, prism::OutAcc oa, void* ws, size_t ws_bytes,
+               void* stream) {
+  std::vector<Req> rq(1);
+  if (int e = check_request(p, f, amax_mrad, S, S_bytes, xy, P, o, d, out, cbed, oa, true, &rq[0]))
+    return e;
+  return run_batch(rq, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 // Multislice STEM (Fig. 1a-c): one full-grid wave per probe, H slice steps,
@@ -771,6 +1006,20 @@ int prism_multislice_workspace_bytes(const prism_plan* p, int n_det, size_t* pre
   return PRISM_OK;
 }
 
+int prism_probe_class(const prism_plan* p, int f, unsigned long long* key) {
+  if (!p || !key) return fail(PRISM_EINVAL, "null argument");
+  if (int r = check_f(p, f)) return r;
+  const int w = p->n / (2 * f);
+  if (!prism::window_side_ok(w))
+    return fail(PRISM_EINVAL,
+                "window side n/(2f) must be a power of two in 8..256 or one of 12, 18, 24, 36, "
+                "48, 72, 96, 144, 192");
+  *key = (unsigned long long)w | (unsigned long long)group_of(p, w) << 16 |
+         (unsigned long long)p->tune.window_tile_div << 32 |
+         (unsigned long long)packed_prec(p->prec) << 48;
+  return PRISM_OK;
+}
+
 int prism_probe_group(const prism_plan* p, int f, int* group, int* tx, int* ty) {
   if (!p || !group || !tx || !ty) return fail(PRISM_EINVAL, "null argument");
   if (int r = check_f(p, f)) return r;
@@ -821,10 +1070,13 @@ int prism_probe_workspace_bytes(const prism_plan* cp, int f, double amax_mrad,
                 "48, 72, 96, 144, 192");
   const auto* act = get_active(p, f, amax_mrad, *mn, o);
   const int G = group_of(p, w);
-  ProbeWs pw;
-  const int ns = p->n / 2;
-  *pref = probe_layout(w, ns, (int)act->size(), pref_probe_chunk(w, G), p->prec, &pw, nullptr);
-  *minimum = probe_layout(w, ns, (int)act->size(), G, p->prec, &pw, nullptr);
+  const prism::Prec pk = packed_prec(p->prec);
+  const int n_act = (int)act->size();
+  const std::vector<PackShape> shapes{PackShape{n_act, padded_beams(n_act, pk), p->n / 2}};
+  const int n_lists = prism::window_big(w) ? 0 : 1;
+  ProbeBatchWs bw;
+  *pref = probe_batch_layout(w, G, pk, shapes, n_lists, 1, pref_probe_chunk(w, G), &bw, nullptr);
+  *minimum = probe_batch_layout(w, G, pk, shapes, n_lists, 1, G, &bw, nullptr);
   return PRISM_OK;
 }
 
@@ -1029,6 +1281,67 @@ int prism_probe_cbed_accumulate(prism_plan* p, int f, double amax_mrad, const vo
   if (int r = out_mode(true, weight, &oa)) return r;
   return probe_step(p, f, amax_mrad, S, S_bytes, xy, P, o, nullptr, nullptr, cbed, oa, ws,
                     ws_bytes, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Checked requests of a batch call (buffers: also the device pointers).
+int check_batch(const prism_probe_request* rqs, int count, bool buffers, std::vector<Req>* rq) {
+  if (count < 0) return fail(PRISM_EINVAL, "negative request count");
+  if (count > 0 && !rqs) return fail(PRISM_EINVAL, "null requests");
+  rq->resize(count);
+  for (int i = 0; i < count; ++i) {
+    const prism_probe_request& q = rqs[i];
+    prism::OutAcc oa;
+    int e = out_mode(q.accumulate != 0, q.weight, &oa);
+    if (!e)
+      e = check_request(q.plan, q.f, q.alpha_max_mrad, q.smatrix_dev, q.smatrix_bytes,
+                        q.probe_xy_dev, q.n_probes, q.optics, q.detector, q.out_dev, q.cbed_dev,
+                        oa, buffers, &(*rq)[i]);
+    if (e) return fail(e, "request " + std::to_string(i) + ": " + g_err);
+  }
+  return PRISM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int prism_probe_batch_workspace_bytes(const prism_probe_request* requests, int count,
+                                      size_t* pref, size_t* minimum) {
+  if (!pref || !minimum) return fail(PRISM_EINVAL, "null argument");
+  std::vector<Req> rq;
+  if (int e = check_batch(requests, count, false, &rq)) return e;
+  *pref = 0;
+  *minimum = 0;
+  ProbeBatchWs bw;
+  std::vector<bool> done(rq.size(), false);
+  for (size_t i = 0; i < rq.size(); ++i) {
+    Sub one;
+    one.add(rq, (int)i);
+    *minimum = std::max(*minimum, one.layout(rq, rq[i].G, &bw, nullptr));
+    if (done[i]) continue;
+    Sub cls;  // every request of i's launch class
+    for (size_t j = i; j < rq.size(); ++j)
+      if (!done[j] && same_class(rq[i], rq[j])) {
+        cls.add(rq, (int)j);
+        done[j] = true;
+      }
+    const long long G = rq[i].G;
+    const int chunk = (int)std::max<long long>(
+        G, std::min<long long>(pref_probe_chunk(rq[i].w, rq[i].G), (cls.probes + G - 1) / G * G));
+    *pref = std::max(*pref, cls.layout(rq, chunk, &bw, nullptr));
+  }
+  return PRISM_OK;
+}
+
+int prism_probe_batch(const prism_probe_request* requests, int count, void* ws, size_t ws_bytes,
+                      void* stream) {
+  std::vector<Req> rq;
+  if (int e = check_batch(requests, count, true, &rq)) return e;
+  return run_batch(rq, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

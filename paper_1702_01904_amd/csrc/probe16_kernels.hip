@@ -353,21 +353,28 @@ __device__ __forceinline__ void contract16_tile(const uint32_t* __restrict__ s16
   }
 }
 
+// Grid: x walks the union tiles of a group, y the probe groups of every
+// segment (segment k owns groups g_begin .. g_begin + ceil(np / G)).
 template <int G, Prec P>
 __global__ __launch_bounds__(kNT16) __attribute__((amdgpu_waves_per_eu(2))) void k_contract16(
-    const uint32_t* __restrict__ s16, int rowlen, const uint32_t* __restrict__ a16,
-    const int2* __restrict__ origin, int np, int ns, int w, float out_scale,
-    float2* __restrict__ window) {
+    const ContractSegs segs, int w) {
   constexpr int LDS = 2 * (2 * G * kPitch16) + 2 * (kTile16 * kPitch16);
   __shared__ uint32_t smem[LDS];
   __shared__ int offx[G], offy[G];
   __shared__ int zero[G];
   __shared__ int ginfo[6];
   const int tid = threadIdx.x;
-  const int p_base = blockIdx.y * G;
+  int k = 0;  // segment of this group (uniform)
+  while (k + 1 < segs.n && (int)blockIdx.y >= segs.s[k + 1].g_begin) ++k;
+  const ContractSeg& sg = segs.s[k];
+  const uint32_t* __restrict__ s16 = sg.s16;
+  const int2* __restrict__ origin = sg.origin;
+  const int rowlen = sg.rowlen, ns = sg.ns, np = sg.np;
+  const int grp = (int)blockIdx.y - sg.g_begin;
+  const int p_base = grp * G;
   const int gcount = min(G, np - p_base);
   const int nblk = rowlen / kC16KB;
-  const uint32_t* a16g = a16 + (size_t)blockIdx.y * nblk * (2 * G) * kC16KB;
+  const uint32_t* a16g = sg.a16 + (size_t)grp * nblk * (2 * G) * kC16KB;
   if (tid < 64) {
     // group geometry in wave 0, one lane per probe (G <= 64): offsets of
     // each window from the first, their extent, and the union origin
@@ -409,14 +416,14 @@ __global__ __launch_bounds__(kNT16) __attribute__((amdgpu_waves_per_eu(2))) void
     const UnionGeom16 U{ginfo[1], ginfo[2], ginfo[3], ginfo[4]};
     for (int tile = blockIdx.x; tile * kTile16 < U.uy * U.ux; tile += gridDim.x)
       contract16_tile<G, P>(s16, rowlen, a16g, np, p_base, gcount, ns, w, U, tile, offx, offy,
-                            -1, out_scale, smem, window);
+                            -1, sg.out_scale, smem, sg.window);
   } else {
     for (int tile = blockIdx.x; tile * kTile16 < w * w; tile += gridDim.x) {
       for (int g = 0; g < gcount; ++g) {
         const int2 o = origin[p_base + g];
         const UnionGeom16 U{o.y, o.x, w, w};
         contract16_tile<G, P>(s16, rowlen, a16g, np, p_base, gcount, ns, w, U, tile, zero, zero,
-                              g, out_scale, smem, window);
+                              g, sg.out_scale, smem, sg.window);
       }
     }
   }
@@ -472,17 +479,12 @@ hipError_t launch_alpha16(const double* probe_xy, int p0, int np, const ActiveBe
   return hipGetLastError();
 }
 
-hipError_t launch_contract16(const void* s16, int n_actp, const void* a16, const int2* origin,
-                             int np, int ns, int w, int group, float out_scale, float2* window,
-                             Prec prec, int window_tile_div, hipStream_t st) {
-  const dim3 grid((unsigned)contract_tile_slots(w, window_tile_div),
-                  (unsigned)((np + group - 1) / group));
-  const uint32_t* s = static_cast<const uint32_t*>(s16);
-  const uint32_t* a = static_cast<const uint32_t*>(a16);
-  const int rowlen = n_actp * prec_words(prec);  // 32-bit words per packed pixel row
-#define C16(GG, PP)                                                                           \
-  hipLaunchKernelGGL((k_contract16<GG, PP>), grid, dim3(kNT16), 0, st, s, rowlen, a, origin, np, \
-                     ns, w, out_scale, window)
+hipError_t launch_contract16(const ContractSegs& segs, int w, int group, Prec prec,
+                             int window_tile_div, hipStream_t st) {
+  if (segs.n < 1 || segs.n > kMaxSeg || segs.groups < 1) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)contract_tile_slots(w, window_tile_div), (unsigned)segs.groups);
+#define C16(GG, PP) \
+  hipLaunchKernelGGL((k_contract16<GG, PP>), grid, dim3(kNT16), 0, st, segs, w)
 #define C16G(PP)                          \
   switch (group) {                        \
     case 16: C16(16, PP); break;          \

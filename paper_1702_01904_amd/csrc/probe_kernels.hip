@@ -207,9 +207,6 @@ __global__ __launch_bounds__(kBigNT) void k_window_cols_lds(const float2* __rest
 }
 
 // ---------------------------------------------------------------------------
-#ifndef PRISM_WD_PREFETCH
-#define PRISM_WD_PREFETCH 0  // window kernel: load the next probe during the current one
-#endif
 #ifndef PRISM_WD_GRID
 #define PRISM_WD_GRID 1048576  // window kernel: most workgroups (each then walks probes)
 #endif
@@ -226,11 +223,9 @@ __host__ __device__ constexpr int wd_nt(int w) {
 // 2D FFT of each W x W window in LDS, then either I(kw) = |Psi(kw)|^2 / W^2
 // summed over each bin's pixel list in FP64 (the lists encode the angle test
 // at full-grid frequency f kw), or (CBED) I written out in full. Workgroups
-// walk probes p = blockIdx.x, + gridDim.x, ... (one probe each unless there
-// are more than PRISM_WD_GRID); with PRISM_WD_PREFETCH the first row stage
-// of the next probe is loaded into registers while the current one is
-// transformed (one window fills most of a compute unit's LDS, so this is the
-// only overlap there is within a workgroup).
+// walk windows p = blockIdx.x, + gridDim.x, ... (one window each unless
+// there are more than PRISM_WD_GRID); window p belongs to the segment whose
+// range holds it (its own outputs and, for the sums, its own pixel lists).
 //
 // Bin sums: the lists are cut into chunks of kWdListChunk = 64 entries (one
 // per lane, kNoPix padding at the end of each bin); chunk k belongs to the
@@ -243,13 +238,8 @@ __host__ __device__ constexpr int wd_nt(int w) {
 // per group of chunks.
 template <int W, bool CBED>
 __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __restrict__ window,
-                                                            int np,
                                                             const float2* __restrict__ twW,
-                                                            const uint16_t* __restrict__ pix,
-                                                            BinLists lists,
-                                                            double* __restrict__ out,
-                                                            float* __restrict__ cbed,
-                                                            OutAcc oa) {
+                                                            const WindowSegs segs) {
   constexpr int NT = wd_nt(W);
   constexpr int NW = NT / 64;
   // first row stage, applied from registers: radix 8 where W allows, else
@@ -263,50 +253,49 @@ __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __rest
   __shared__ double red[CBED ? 1 : kMaxDet][NW];
   const int tid = threadIdx.x;
   load_twiddles<W, NT>(tw, twW, tid);
-  float2 nxt[S8::PER][R0];
-  auto load = [&](int p) {  // first row stage of window p
-    const float2* src = window + (size_t)p * W * W;
-#pragma unroll
-    for (int q = 0; q < S8::PER; ++q) {
-      const int b = tid + q * NT;
-      if (!S8::GUARD || b < S8::TOT) {
-        int row, j;
-        stage_coords<Rows, S8::NB>(b, row, j);
-#pragma unroll
-        for (int r = 0; r < R0; ++r) nxt[q][r] = src[row * W + j + r * (W / R0)];
-      }
-    }
-  };
-  if (PRISM_WD_PREFETCH) load(blockIdx.x);
   const double inv_w2 = 1.0 / ((double)W * (double)W);
 #pragma unroll 1
-  for (int p = blockIdx.x; p < np; p += gridDim.x) {
+  for (int p = blockIdx.x; p < segs.total; p += gridDim.x) {
+    int k = 0;  // segment of window p (uniform)
+    while (k + 1 < segs.n && p >= segs.s[k + 1].begin) ++k;
+    const WindowSeg& sg = segs.s[k];
+    const int q = p - sg.begin;  // probe within the segment
     float2 v[S8::PER][R0];
-    if (!PRISM_WD_PREFETCH) load(p);
+    {
+      const float2* src = window + (size_t)p * W * W;
 #pragma unroll
-    for (int q = 0; q < S8::PER; ++q)
+      for (int c = 0; c < S8::PER; ++c) {
+        const int b = tid + c * NT;
+        if (!S8::GUARD || b < S8::TOT) {
+          int row, j;
+          stage_coords<Rows, S8::NB>(b, row, j);
 #pragma unroll
-      for (int r = 0; r < R0; ++r) v[q][r] = nxt[q][r];
-    if (PRISM_WD_PREFETCH)
-      load(min(p + (int)gridDim.x, np - 1));  // the last round re-reads its own window
+          for (int r = 0; r < R0; ++r) v[c][r] = src[row * W + j + r * (W / R0)];
+        }
+      }
+    }
     stage_out<Rows, R0, 1, NT, false>(lds, tid, v);
     __syncthreads();
     fft_from<Rows, NT, false, R0>(lds, tw, tid);
     fft_lds<Cols, NT, false>(lds, tw, tid);
     if constexpr (CBED) {
-      float* dst = cbed + (size_t)p * W * W;
+      float* dst = sg.cbed + (size_t)q * W * W;
       for (int e = tid; e < W * W; e += NT) {
         const float2 z = lds[lpad(e)];
-        put_out(dst + e, ((double)z.x * z.x + (double)z.y * z.y) * inv_w2, oa);
+        put_out(dst + e, ((double)z.x * z.x + (double)z.y * z.y) * inv_w2, sg.oa);
       }
     } else {
-      const int K = lists.off[lists.n];  // chunks of kWdListChunk entries
+      const uint16_t* __restrict__ pix = sg.pix;
+      const BinLists* __restrict__ lists = sg.lists;  // uniform: scalar loads
+      const int nb = lists->n;
+      const int* off = lists->off;
+      const int K = off[nb];  // chunks of kWdListChunk entries
       const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-      for (int i = tid; i < lists.n * NW; i += NT) red[i / NW][i % NW] = 0.0;
+      for (int i = tid; i < nb * NW; i += NT) red[i / NW][i % NW] = 0.0;
       __syncthreads();
       const int c0 = (int)((long long)K * wv / NW), c1 = (int)((long long)K * (wv + 1) / NW);
       int j = 0;  // bin of the current chunk (uniform in the wave)
-      while (j < lists.n && c0 >= lists.off[j + 1]) ++j;
+      while (j < nb && c0 >= off[j + 1]) ++j;
       double acc = 0.0;
       for (int k0 = c0; k0 < c1; k0 += kWdChunks) {
         int px[kWdChunks];
@@ -315,19 +304,20 @@ __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __rest
           px[c] = k0 + c < c1 ? (int)pix[(size_t)(k0 + c) * kWdListChunk + lane] : (int)kNoPix;
 #pragma unroll
         for (int c = 0; c < kWdChunks; ++c) {
-          const int k = k0 + c;
-          if (k >= c1) break;
-          if (k >= lists.off[j + 1]) {  // bin j ends: its wave sum, then the bin of chunk k
-            const double sm = wave_sum(acc);
-            if (lane == 0) red[j][wv] = sm;
-            acc = 0.0;
-            do ++j;
-            while (k >= lists.off[j + 1]);
+          const int kk = k0 + c;
+          if (kk < c1) {
+            if (kk >= off[j + 1]) {  // bin j ends: its wave sum, then the bin of chunk kk
+              const double sm = wave_sum(acc);
+              if (lane == 0) red[j][wv] = sm;
+              acc = 0.0;
+              do ++j;
+              while (kk >= off[j + 1]);
+            }
+            const bool ok = px[c] != (int)kNoPix;
+            const float2 z = lds[lpad(ok ? px[c] : 0)];
+            const double I = (double)z.x * z.x + (double)z.y * z.y;
+            acc += ok ? I : 0.0;
           }
-          const bool ok = px[c] != (int)kNoPix;
-          const float2 z = lds[lpad(ok ? px[c] : 0)];
-          const double I = (double)z.x * z.x + (double)z.y * z.y;
-          acc += ok ? I : 0.0;
         }
       }
       if (c1 > c0) {
@@ -335,13 +325,13 @@ __global__ __launch_bounds__(wd_nt(W)) void k_window_detect(const float2* __rest
         if (lane == 0) red[j][wv] = sm;
       }
       __syncthreads();
-      if (tid < lists.n) {
+      if (tid < nb) {
         double sm = 0.0;
         for (int w = 0; w < NW; ++w) sm += red[tid][w];
-        put_out(out + (size_t)p * lists.n + tid, sm * inv_w2, oa);
+        put_out(sg.out + (size_t)q * nb + tid, sm * inv_w2, sg.oa);
       }
     }
-    __syncthreads();  // LDS free for the next probe
+    __syncthreads();  // LDS free for the next window
   }
 }
 
@@ -376,7 +366,21 @@ hipError_t launch_window_big(float2* window, int np, int w, const float2* twW, i
                          bins, partial, (float*)nullptr, OutAcc{});
     return hipGetLastError();
   }
-#define WBIG(WW)                                                                                 case WW: {                                                                                       hipLaunchKernelGGL(k_window_rows_lds<WW>, dim3((unsigned)((size_t)np * WW / kBigRows)),                           dim3(kBigNT), 0, st, window, twW);                                          hipError_t e = hipGetLastError();                                                              if (e != hipSuccess) return e;                                                                 const dim3 grid((unsigned)((size_t)np * (WW / kBigTC)));                                       if (want_cbed)                                                                                   hipLaunchKernelGGL((k_window_cols_lds<WW, true>), grid, dim3(kBigNT), 0, st, window, twW,                          f, bins, (double*)nullptr, cbed, acc);                                    else                                                                                             hipLaunchKernelGGL((k_window_cols_lds<WW, false>), grid, dim3(kBigNT), 0, st, window,                             twW, f, bins, partial, (float*)nullptr, OutAcc{});                        break;                                                                                       }
+#define WBIG(WW)                                                                           \
+  case WW: {                                                                               \
+    hipLaunchKernelGGL(k_window_rows_lds<WW>, dim3((unsigned)((size_t)np * WW / kBigRows)), \
+                       dim3(kBigNT), 0, st, window, twW);                                  \
+    hipError_t e = hipGetLastError();                                                      \
+    if (e != hipSuccess) return e;                                                         \
+    const dim3 grid((unsigned)((size_t)np * (WW / kBigTC)));                               \
+    if (want_cbed)                                                                         \
+      hipLaunchKernelGGL((k_window_cols_lds<WW, true>), grid, dim3(kBigNT), 0, st, window, \
+                         twW, f, bins, (double*)nullptr, cbed, acc);                       \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_window_cols_lds<WW, false>), grid, dim3(kBigNT), 0, st, window, \
+                         twW, f, bins, partial, (float*)nullptr, OutAcc{});                \
+    break;                                                                                 \
+  }
   switch (w) {
     WBIG(144)
     WBIG(192)
@@ -391,14 +395,14 @@ hipError_t launch_window_big(float2* window, int np, int w, const float2* twW, i
 // each walks several probes.
 static unsigned window_grid(int np) { return (unsigned)std::min(np, PRISM_WD_GRID); }
 
-hipError_t launch_window_detect(const float2* window, int np, int w, const float2* twW,
-                                const uint16_t* pix, const BinLists& lists, double* out,
-                                OutAcc acc, hipStream_t st) {
-  if (np <= 0) return hipSuccess;
-#define WD(WW)                                                                                  \
-  case WW:                                                                                      \
-    hipLaunchKernelGGL((k_window_detect<WW, false>), dim3(window_grid(np)), dim3(wd_nt(WW)), 0, \
-                       st, window, np, twW, pix, lists, out, (float*)nullptr, acc);             \
+hipError_t launch_window_detect(const float2* window, const WindowSegs& segs, int w,
+                                const float2* twW, hipStream_t st) {
+  if (segs.total <= 0) return hipSuccess;
+  if (segs.n < 1 || segs.n > kMaxSeg) return hipErrorInvalidValue;
+#define WD(WW)                                                                          \
+  case WW:                                                                              \
+    hipLaunchKernelGGL((k_window_detect<WW, false>), dim3(window_grid(segs.total)),     \
+                       dim3(wd_nt(WW)), 0, st, window, twW, segs);                      \
     break;
   switch (w) {
     WD(8)
@@ -420,15 +424,14 @@ hipError_t launch_window_detect(const float2* window, int np, int w, const float
   return hipGetLastError();
 }
 
-hipError_t launch_window_cbed(const float2* window, int np, int w, const float2* twW,
-                              float* cbed, OutAcc acc, hipStream_t st) {
-  if (np <= 0) return hipSuccess;
-  BinLists none{};
-#define WC(WW)                                                                                 \
-  case WW:                                                                                     \
-    hipLaunchKernelGGL((k_window_detect<WW, true>), dim3(window_grid(np)), dim3(wd_nt(WW)), 0, \
-                       st, window, np, twW, (const uint16_t*)nullptr, none, (double*)nullptr,  \
-                       cbed, acc);                                                             \
+hipError_t launch_window_cbed(const float2* window, const WindowSegs& segs, int w,
+                              const float2* twW, hipStream_t st) {
+  if (segs.total <= 0) return hipSuccess;
+  if (segs.n < 1 || segs.n > kMaxSeg) return hipErrorInvalidValue;
+#define WC(WW)                                                                          \
+  case WW:                                                                              \
+    hipLaunchKernelGGL((k_window_detect<WW, true>), dim3(window_grid(segs.total)),      \
+                       dim3(wd_nt(WW)), 0, st, window, twW, segs);                      \
     break;
   switch (w) {
     WC(8)

@@ -10,13 +10,16 @@
 //   * builds in arrival order on the server's build stream, each admitted
 //     once its bytes fit the budget; with LRU eviction on, the least
 //     recently used idle S-matrices are released to make room;
-//   * every queued query of one (specimen, optics, detector) merged into as
-//     few probe-step calls as the staging space allows, each call sent to
-//     the first query slot (stream) that has finished its earlier work, or
-//     else to the slot with the fewest calls in flight; a query of a
-//     specimen whose build is still queued waits for that build, and a
-//     query's stream waits for its S-matrix's build event on the device, so
-//     builds and queries of other specimens overlap on the GPU.
+//   * the queued queries of every specimen whose build has been dispatched,
+//     bucketed by probe-step launch class (prism_probe_class) in arrival
+//     order: one prism_probe_batch call per bucket and max_probes
+//     positions, so that queries of different specimens (and optics) share
+//     the window-sum and window launches, with the queries of one
+//     (specimen, optics, detector) staged into one request. Each call goes
+//     to the first query slot (stream) that has finished its earlier work,
+//     or else to the slot with the fewest calls in flight, and its stream
+//     waits on the device for the build events of the S-matrices it reads,
+//     so builds and queries of other specimens overlap on the GPU.
 // The server is a client of the public entry points only.
 #include <hip/hip_runtime.h>
 
@@ -71,10 +74,10 @@ struct Build {
 
 struct Batch {
   hipEvent_t done;
-  int pending;    // tickets of this batch not yet reported
-  int spec;       // specimen it reads (or builds)
-  int slot;       // query slot, or -1 for the build stream
-  bool finished;  // done event seen complete (specimen and slot counts released)
+  int pending;             // tickets of this batch not yet reported
+  std::vector<int> specs;  // specimens it reads (or the one it builds)
+  int slot;                // query slot, or -1 for the build stream
+  bool finished;           // done event seen complete (specimen and slot counts released)
 };
 
 uint64_t bits(double x) {
@@ -104,6 +107,7 @@ struct prism_server {
   std::vector<int> free_batches;  // retired batch slots
   std::vector<hipEvent_t> event_pool;
   std::vector<int> evicted;  // released by LRU eviction, not yet reported
+  long long merged_calls = 0, multi_specimen_calls = 0;  // dispatched probe calls
 
   ~prism_server() {
     for (auto s : streams) (void)hipStreamSynchronize(s);
@@ -162,7 +166,7 @@ int hip_err(hipError_t e, const char* where) {
 void finish(prism_server* s, Batch& bt) {
   if (bt.finished) return;
   bt.finished = true;
-  s->specs[bt.spec].inflight--;
+  for (int sp : bt.specs) s->specs[sp].inflight--;
   if (bt.slot >= 0) s->slot_inflight[bt.slot]--;
 }
 
@@ -189,9 +193,9 @@ void recycle(prism_server* s, int b) {
   }
 }
 
-int new_batch(prism_server* s, hipEvent_t done, int pending, int spec, int slot) {
-  Batch bt{done, pending, spec, slot, false};
-  s->specs[spec].inflight++;
+int new_batch(prism_server* s, hipEvent_t done, int pending, std::vector<int> specs, int slot) {
+  for (int sp : specs) s->specs[sp].inflight++;
+  Batch bt{done, pending, std::move(specs), slot, false};
   if (slot >= 0) s->slot_inflight[slot]++;
   if (!s->free_batches.empty()) {
     const int b = s->free_batches.back();
@@ -264,84 +268,146 @@ int dispatch_builds(prism_server* s) {
     hipEvent_t done = s->event();
     if (!done) return set_error(PRISM_EHIP, "create event");
     if (hipError_t e = hipEventRecord(done, st); e != hipSuccess) return hip_err(e, "record event");
-    s->ticket_batch[bd.ticket] = new_batch(s, done, 1, bd.spec, -1);
+    s->ticket_batch[bd.ticket] = new_batch(s, done, 1, {bd.spec}, -1);
   }
   return PRISM_OK;
 }
 
+// One request of a merged call: consecutive queued queries (indices into
+// pending) of one (specimen, optics, detector), staged contiguously.
+struct Run {
+  std::vector<size_t> qs;
+  int probes = 0;
+};
+
 int flush_queries(prism_server* s, std::vector<char>* sent) {
-  // merge key: specimen, optics, detector; queries keep their arrival order
+  // buckets: launch class, in arrival order; within a bucket, runs of one
+  // (specimen, optics, detector)
   using Key = std::tuple<int, uint64_t, uint64_t, uint64_t, uint64_t, uint64_t, std::vector<uint64_t>>;
-  std::map<Key, std::vector<size_t>> groups;
-  std::vector<Key> order;
+  std::vector<unsigned long long> cls;
+  std::vector<std::vector<Key>> bucket_keys;
+  std::vector<std::map<Key, std::vector<size_t>>> buckets;
   for (size_t i = 0; i < s->pending.size(); ++i) {
     const Query& q = s->pending[i];
-    if (s->specs[q.spec].state != SpecState::kResident) continue;  // its build is still queued
+    const Specimen& sp = s->specs[q.spec];
+    if (sp.state != SpecState::kResident) continue;  // its build is still queued
+    unsigned long long c;
+    if (int r = prism_probe_class(sp.plan, sp.f, &c)) return r;
+    size_t b = 0;
+    while (b < cls.size() && cls[b] != c) ++b;
+    if (b == cls.size()) {
+      cls.push_back(c);
+      bucket_keys.emplace_back();
+      buckets.emplace_back();
+    }
     std::vector<uint64_t> eb;
     for (double e : q.edges) eb.push_back(bits(e));
     Key k{q.spec, bits(q.optics.alpha_mrad), bits(q.optics.C1_A), bits(q.optics.C3_A),
           bits(q.optics.tilt_x_mrad), bits(q.optics.tilt_y_mrad), eb};
-    auto it = groups.find(k);
-    if (it == groups.end()) {
-      order.push_back(k);
-      groups[k] = {i};
+    auto it = buckets[b].find(k);
+    if (it == buckets[b].end()) {
+      bucket_keys[b].push_back(k);
+      buckets[b][k] = {i};
     } else {
       it->second.push_back(i);
     }
   }
-  for (const Key& k : order) {
-    const std::vector<size_t>& qs = groups[k];
-    size_t a = 0;
-    while (a < qs.size()) {
-      // one merged call: consecutive queries up to max_probes positions
-      size_t b = a;
+  for (size_t b = 0; b < cls.size(); ++b) {
+    // the bucket's runs, cut so that a call holds at most max_probes positions
+    std::vector<Run> runs;
+    for (const Key& k : bucket_keys[b]) {
+      Run cur;
+      for (size_t i : buckets[b][k]) {
+        const int P = s->pending[i].P;
+        if (cur.probes + P > s->max_probes && !cur.qs.empty()) {
+          runs.push_back(std::move(cur));
+          cur = Run{};
+        }
+        cur.qs.push_back(i);
+        cur.probes += P;
+      }
+      if (!cur.qs.empty()) runs.push_back(std::move(cur));
+    }
+    size_t r0 = 0;
+    while (r0 < runs.size()) {
+      // one call: consecutive runs up to max_probes positions
+      size_t r1 = r0;
       int total = 0;
-      while (b < qs.size() && total + s->pending[qs[b]].P <= s->max_probes) total += s->pending[qs[b++]].P;
-      const Query& q0 = s->pending[qs[a]];
-      Specimen& sp = s->specs[q0.spec];
-      const int n_det = (int)(q0.edges.size() / 2);
+      while (r1 < runs.size() && total + runs[r1].probes <= s->max_probes) total += runs[r1++].probes;
       const int k_st = pick_slot(s);
       hipStream_t st = s->streams[k_st];
       const Region rg = region_of(s, k_st);
-      if (hipError_t e = hipStreamWaitEvent(st, sp.ready, 0); e != hipSuccess) return hip_err(e, "wait S-matrix");
-      int off = 0;
-      for (size_t i = a; i < b; ++i) {
-        const Query& q = s->pending[qs[i]];
-        if (q.P > 0)
-          if (hipError_t e = hipMemcpyAsync(rg.xy + 2 * (size_t)off, q.xy, 2 * (size_t)q.P * sizeof(double),
-                                            hipMemcpyDeviceToDevice, st);
-              e != hipSuccess)
-            return hip_err(e, "stage probe positions");
-        off += q.P;
+      std::vector<int> specs;
+      for (size_t r = r0; r < r1; ++r) {
+        const int sid = s->pending[runs[r].qs[0]].spec;
+        if (std::find(specs.begin(), specs.end(), sid) == specs.end()) specs.push_back(sid);
       }
-      prism_detector det{n_det, q0.edges.data()};
+      for (int sid : specs)
+        if (hipError_t e = hipStreamWaitEvent(st, s->specs[sid].ready, 0); e != hipSuccess)
+          return hip_err(e, "wait S-matrix");
+      // stage positions, then one request per run
+      std::vector<prism_detector> dets(r1 - r0);
+      std::vector<prism_probe_request> req(r1 - r0);
+      int off = 0;  // staged positions so far (output rows follow them at max_det each)
+      std::vector<int> offs;
+      for (size_t r = r0; r < r1; ++r) {
+        offs.push_back(off);
+        const Query& q0 = s->pending[runs[r].qs[0]];
+        const Specimen& sp = s->specs[q0.spec];
+        int o = off;
+        for (size_t i : runs[r].qs) {
+          const Query& q = s->pending[i];
+          if (q.P > 0)
+            if (hipError_t e = hipMemcpyAsync(rg.xy + 2 * (size_t)o, q.xy,
+                                              2 * (size_t)q.P * sizeof(double),
+                                              hipMemcpyDeviceToDevice, st);
+                e != hipSuccess)
+              return hip_err(e, "stage probe positions");
+          o += q.P;
+        }
+        const int n_det = (int)(q0.edges.size() / 2);
+        dets[r - r0] = prism_detector{n_det, q0.edges.data()};
+        req[r - r0] = prism_probe_request{sp.plan, sp.f, sp.amax, sp.S, sp.S_bytes,
+                                          rg.xy + 2 * (size_t)off, runs[r].probes, &q0.optics,
+                                          &dets[r - r0], rg.out + (size_t)off * s->max_det,
+                                          nullptr, 0, 1.0};
+        off += runs[r].probes;
+      }
       if (total > 0)
-        if (int r = prism_probe_outputs(sp.plan, sp.f, sp.amax, sp.S, sp.S_bytes, rg.xy, total,
-                                        &q0.optics, &det, rg.out, rg.probe_ws, rg.probe_ws_bytes,
-                                        st))
-          return r;
-      off = 0;
-      for (size_t i = a; i < b; ++i) {
-        const Query& q = s->pending[qs[i]];
-        if (q.P > 0)
-          if (hipError_t e = hipMemcpyAsync(q.out, rg.out + (size_t)off * n_det,
-                                            (size_t)q.P * n_det * sizeof(double),
-                                            hipMemcpyDeviceToDevice, st);
-              e != hipSuccess)
-            return hip_err(e, "return outputs");
-        off += q.P;
+        if (int e = prism_probe_batch(req.data(), (int)req.size(), rg.probe_ws, rg.probe_ws_bytes,
+                                      st))
+          return e;
+      for (size_t r = r0; r < r1; ++r) {
+        const int n_det = dets[r - r0].n_det;
+        int o = 0;
+        for (size_t i : runs[r].qs) {
+          const Query& q = s->pending[i];
+          if (q.P > 0)
+            if (hipError_t e = hipMemcpyAsync(
+                    q.out, rg.out + (size_t)offs[r - r0] * s->max_det + (size_t)o * n_det,
+                    (size_t)q.P * n_det * sizeof(double), hipMemcpyDeviceToDevice, st);
+                e != hipSuccess)
+              return hip_err(e, "return outputs");
+          o += q.P;
+        }
       }
       hipEvent_t done = s->event();
       if (!done) return set_error(PRISM_EHIP, "create event");
       if (hipError_t e = hipEventRecord(done, st); e != hipSuccess) return hip_err(e, "record event");
-      const int bi = new_batch(s, done, (int)(b - a), q0.spec, k_st);
-      sp.last_use = ++s->seq;
-      for (size_t i = a; i < b; ++i) {
-        s->ticket_batch[s->pending[qs[i]].ticket] = bi;
-        (*sent)[qs[i]] = 1;
-        sp.queued--;
-      }
-      a = b;
+      int n_q = 0;
+      for (size_t r = r0; r < r1; ++r) n_q += (int)runs[r].qs.size();
+      const int bi = new_batch(s, done, n_q, specs, k_st);
+      ++s->seq;
+      for (int sid : specs) s->specs[sid].last_use = s->seq;
+      for (size_t r = r0; r < r1; ++r)
+        for (size_t i : runs[r].qs) {
+          s->ticket_batch[s->pending[i].ticket] = bi;
+          (*sent)[i] = 1;
+          s->specs[s->pending[i].spec].queued--;
+        }
+      s->merged_calls++;
+      if (specs.size() > 1) s->multi_specimen_calls++;
+      r0 = r1;
     }
   }
   return PRISM_OK;
@@ -584,6 +650,14 @@ int prism_server_stats(const prism_server* s, size_t* smatrix_bytes_used, int* q
   if (smatrix_bytes_used) *smatrix_bytes_used = s->used;
   if (queued) *queued = (int)(s->pending.size() + s->builds.size());
   if (in_flight) *in_flight = (int)s->ticket_batch.size();
+  return PRISM_OK;
+}
+
+int prism_server_call_stats(const prism_server* s, long long* probe_calls,
+                            long long* multi_specimen_calls) {
+  if (!s) return set_error(PRISM_EINVAL, "null server");
+  if (probe_calls) *probe_calls = s->merged_calls;
+  if (multi_specimen_calls) *multi_specimen_calls = s->multi_specimen_calls;
   return PRISM_OK;
 }
 

@@ -511,3 +511,77 @@ def test_tuning_roundtrip_and_validation():
         with pytest.raises(PrismError):
             p.set_tuning(bad)
     assert p.tuning() == t                          # a refused setting changes nothing
+
+
+def _req(p, f, amax, P, optics=None, det=None, S=SBIG):
+    o = _native.PrismOptics(20.0, 0.0, 0.0, 0.0, 0.0) if optics is None else optics
+    dummy = ctypes.c_void_p(0x1000)   # never dereferenced: every case fails validation first
+    return _native.PrismProbeRequest(p._h, f, amax, dummy, S, dummy, P, ctypes.pointer(o),
+                                     ctypes.pointer(det) if det is not None else None, dummy,
+                                     dummy, 0, 1.0), o
+
+
+def test_probe_batch_validation_before_any_launch():
+    L = _native.lib()
+    p = _plan(256, 25.6)
+    edges = np.array([[0.0, 20.0], [20.0, 40.0]])
+    det = _native.PrismDetector(2, edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    amax = p.alpha_max_default(20.0, 4)
+    arr = (_native.PrismProbeRequest * 3)()
+    keep = []
+    for k, (f, a) in enumerate(((4, amax), (4, amax), (4, amax))):
+        arr[k], o = _req(p, f, a, 10, det=det)
+        keep.append(o)
+    ws = ctypes.c_void_p(0x1000)
+    assert L.prism_probe_batch(arr, -1, ws, 1 << 30, None) == _native.PRISM_EINVAL
+    assert L.prism_probe_batch(None, 2, ws, 1 << 30, None) == _native.PRISM_EINVAL
+    assert L.prism_probe_batch(arr, 0, None, 0, None) == _native.PRISM_OK
+    # request 1: n not divisible by 2 f; nothing runs, the message names it
+    arr[1].f = 5
+    assert L.prism_probe_batch(arr, 3, ws, 1 << 30, None) == _native.PRISM_EINVAL
+    assert b"request 1" in L.prism_last_error()
+    arr[1].f = 4
+    # request 2: undersized S-matrix
+    arr[2].smatrix_bytes = 8
+    assert L.prism_probe_batch(arr, 3, ws, 1 << 30, None) == _native.PRISM_EINVAL
+    assert b"request 2" in L.prism_last_error() and b"S-matrix" in L.prism_last_error()
+    arr[2].smatrix_bytes = SBIG
+    # request 0: accumulate with a non-finite weight
+    arr[0].accumulate, arr[0].weight = 1, float("nan")
+    assert L.prism_probe_batch(arr, 3, ws, 1 << 30, None) == _native.PRISM_EINVAL
+    assert b"request 0" in L.prism_last_error()
+    arr[0].accumulate, arr[0].weight = 0, 1.0
+    # null workspace with probes to run
+    assert L.prism_probe_batch(arr, 3, None, 0, None) == _native.PRISM_EINVAL
+
+
+def test_probe_batch_workspace_and_class():
+    L = _native.lib()
+    p = _plan(256, 25.6)
+    q = _plan(128, 12.8)
+    p.set_tuning({})
+    q.set_tuning({})
+    edges = np.array([[0.0, 20.0]])
+    det = _native.PrismDetector(1, edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    a4, a2 = p.alpha_max_default(20.0, 4), q.alpha_max_default(20.0, 2)
+    # one request with many probes: the sizes of the single call's query
+    arr = (_native.PrismProbeRequest * 2)()
+    arr[0], o0 = _req(p, 4, a4, 1 << 20, det=det)
+    pref, mn = ctypes.c_size_t(), ctypes.c_size_t()
+    _native.check(L.prism_probe_batch_workspace_bytes(arr, 1, ctypes.byref(pref), ctypes.byref(mn)))
+    sp, sm = p.probe_workspace_bytes(4, a4, dict(alpha_mrad=20.0))
+    assert (pref.value, mn.value) == (sp, sm)
+    # two specimens of one class: the preferred fill holds both packed S-matrices
+    arr[1], o1 = _req(q, 2, a2, 1 << 20, det=det)
+    assert p.probe_class(4) == q.probe_class(2) != p.probe_class(2)
+    _native.check(L.prism_probe_batch_workspace_bytes(arr, 2, ctypes.byref(pref), ctypes.byref(mn)))
+    assert mn.value == max(sm, q.probe_workspace_bytes(2, a2, dict(alpha_mrad=20.0))[1])
+    assert pref.value > sp
+    # the class key follows the plan's tuning and precision
+    p.set_tuning({"window_tile_div": 2})
+    assert p.probe_class(4) != q.probe_class(2)
+    p.set_tuning({})
+    p.set_probe_precision("bf16")
+    assert p.probe_class(4) != q.probe_class(2)
+    with pytest.raises(PrismError):
+        p.probe_class(3)          # 256 not divisible by 6

@@ -1,0 +1,185 @@
+"""Probe steps of several specimens in one call (prism_probe_batch): every
+request's output equals its own prism_probe_outputs / prism_probe_cbed call
+bit for bit, whatever shares its launches, and matches the FP64 oracle;
+the serving layer merges queries of different specimens into such calls.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import build_inputs
+from paper_1702_01904_amd import Server, probe_batch, probe_batch_workspace_bytes
+
+import _gpu as G
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _amax(d, f):
+    lam = O.wavelength(d["energy_keV"])
+    return O.default_alpha_max(d["optics"]["alpha_mrad"] * 1e-3, f, lam, 1.0 / d["cell"]) * 1e3
+
+
+def _spec(name, seed, f):
+    d = build_inputs(name, seed)
+    plan = G.make_plan(d)
+    plan.set_tuning({})   # library defaults: the launch classes below do not depend on the table
+    amax = _amax(d, f)
+    S = G.build_smatrix(plan, f, amax)
+    return dict(d=d, plan=plan, f=f, amax=amax, S=S)
+
+
+@pytest.fixture(scope="module")
+def specs():
+    # A, B: 256^2 at f = 4 and C: 128^2 at f = 2 have 32-pixel windows and
+    # the same probe group: one launch class over two grid sizes. D: A's
+    # specimen at f = 2 (64-pixel windows), a class of its own.
+    A = _spec("mid256", 2, 4)
+    B = _spec("mid256", 5, 4)
+    C = _spec("tiny", 0, 2)
+    D = dict(A, f=2, amax=_amax(A["d"], 2))
+    D["S"] = G.build_smatrix(D["plan"], 2, D["amax"])
+    return A, B, C, D
+
+
+def _alone(e, xy, optics, edges, out0=None, weight=None, cbed=False):
+    import torch
+    plan, f, amax = e["plan"], e["f"], e["amax"]
+    ws = G.workspace(plan.probe_workspace_bytes(f, amax, optics)[0])
+    if cbed:
+        w = plan.n // (2 * f)
+        out = torch.zeros((xy.shape[0], w, w), dtype=torch.float32, device=G.device())
+        plan.probe_cbed(f, amax, e["S"], xy, optics, out, ws)
+    else:
+        out = out0.clone() if out0 is not None else torch.zeros(
+            (xy.shape[0], len(edges)), dtype=torch.float64, device=G.device())
+        if weight is None:
+            plan.probe_outputs(f, amax, e["S"], xy, optics, edges, out, ws)
+        else:
+            plan.probe_outputs_accumulate(f, amax, e["S"], xy, optics, edges, weight, out, ws)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_batch_equals_separate_calls_and_oracle(specs):
+    import torch
+    A, B, C, D = specs
+    rng = np.random.default_rng(3)
+    defocus = dict(alpha_mrad=18.0, C1_A=35.0, C3_A=0.0)
+
+    def pick(e, P):
+        sel = rng.choice(len(e["d"]["probes"]), P, replace=False)
+        return sel, G.upload(e["d"]["probes"][sel])
+
+    reqs = []
+    plan_of = []
+    for e, P, optics, kind in ((A, 61, A["d"]["optics"], "det"), (B, 40, B["d"]["optics"], "det"),
+                               (C, 17, defocus, "acc"), (D, 23, D["d"]["optics"], "det"),
+                               (B, 9, B["d"]["optics"], "cbed"), (A, 33, defocus, "det"),
+                               (C, 0, C["d"]["optics"], "det")):
+        sel, xy = pick(e, P) if P else (np.zeros(0, dtype=int), G.upload(np.zeros((0, 2))))
+        edges = e["d"]["edges"]
+        r = dict(plan=e["plan"], f=e["f"], alpha_max_mrad=e["amax"], smatrix=e["S"], probe_xy=xy,
+                 optics=optics, edges_mrad=edges)
+        if kind == "cbed":
+            w = e["plan"].n // (2 * e["f"])
+            r["edges_mrad"] = None
+            r["out"] = torch.full((P, w, w), float("nan"), dtype=torch.float32, device=G.device())
+        else:
+            r["out"] = torch.full((P, len(edges)), float("nan"), dtype=torch.float64,
+                                  device=G.device())
+        if kind == "acc":
+            r["out"] = torch.from_numpy(rng.random((P, len(edges)))).to(G.device())
+            r["weight"] = 0.5
+            r["out0"] = r["out"].clone()
+        reqs.append(r)
+        plan_of.append((e, sel, kind))
+    keys = [e["plan"].probe_class(e["f"]) for e in (A, B, C, D)]
+    assert keys[0] == keys[1] == keys[2] != keys[3]
+    pref, mn = probe_batch_workspace_bytes(reqs)
+    assert pref >= mn > 0
+    G.say(f"probe_batch {len(reqs)} requests, ws={pref}")
+    probe_batch([{k: v for k, v in r.items() if k != "out0"} for r in reqs], G.workspace(pref))
+    torch.cuda.synchronize()
+    for r, (e, sel, kind) in zip(reqs, plan_of):
+        if len(sel) == 0:
+            continue
+        G.say(f"separate call n={e['plan'].n} f={e['f']} P={len(sel)} {kind}")
+        alone = _alone(e, r["probe_xy"], r["optics"], r["edges_mrad"], out0=r.get("out0"),
+                       weight=r.get("weight"), cbed=kind == "cbed")
+        assert torch.equal(r["out"], alone), f"{kind} n={e['plan'].n} f={e['f']}"
+    # the 128^2 request of the mixed launch against the oracle
+    r, (e, sel, kind) = reqs[2], plan_of[2]
+    d = e["d"]
+    beams, Sref = O.smatrix(d["phase"], d["thickness"], d["cell"], d["energy_keV"], e["f"],
+                            e["amax"])
+    ref = O.prism_outputs(Sref, beams, e["f"], d["cell"], d["energy_keV"], r["optics"],
+                          d["probes"][sel], d["edges"])
+    got = (r["out"].cpu().numpy() - r["out0"].cpu().numpy()) / 0.5   # out = out0 + 0.5 result
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"batched 128^2 accumulate request vs oracle: eps_rel {err:.3e}")
+    assert err <= TOL
+
+
+def test_batch_many_requests_small_workspace(specs):
+    # 20 requests on two specimens (more segments than one launch takes) in
+    # a workspace of the batch minimum: several fills, several launches per
+    # chunk, each result equal to its own call
+    import torch
+    A, B, _, _ = specs
+    rng = np.random.default_rng(8)
+    reqs = []
+    for k in range(20):
+        e = A if k % 3 else B
+        P = int(rng.integers(1, 40))
+        sel = rng.choice(len(e["d"]["probes"]), P, replace=False)
+        optics = dict(alpha_mrad=float(rng.uniform(12.0, 20.0)), C1_A=float(rng.uniform(-50, 50)),
+                      C3_A=0.0)
+        reqs.append(dict(plan=e["plan"], f=e["f"], alpha_max_mrad=e["amax"], smatrix=e["S"],
+                         probe_xy=G.upload(e["d"]["probes"][sel]), optics=optics,
+                         edges_mrad=e["d"]["edges"],
+                         out=torch.full((P, len(e["d"]["edges"])), float("nan"),
+                                        dtype=torch.float64, device=G.device()), e=e))
+    pref, mn = probe_batch_workspace_bytes(reqs)
+    G.say(f"probe_batch 20 requests in the minimum workspace {mn} (preferred {pref})")
+    probe_batch(reqs, G.workspace(mn))
+    torch.cuda.synchronize()
+    for k, r in enumerate(reqs):
+        alone = _alone(r["e"], r["probe_xy"], r["optics"], r["edges_mrad"])
+        assert torch.equal(r["out"], alone), f"request {k}"
+
+
+def test_server_merges_specimens_into_one_call(specs):
+    import torch
+    A, B, C, _ = specs
+    ents = (A, B, C)
+    probe_ws = max(e["plan"].probe_workspace_bytes(e["f"], e["amax"], e["d"]["optics"])[0]
+                   for e in ents)
+    ws = G.workspace(Server.workspace_bytes(2, 4096, 4, probe_ws))
+    srv = Server(sum(e["S"].numel() * 8 for e in ents), ws, n_streams=2, max_probes=4096,
+                 max_det=4)
+    for e in ents:
+        e["id"] = srv.admit(e["plan"], e["f"], e["amax"], e["S"])
+    rng = np.random.default_rng(21)
+    qs = []
+    for k in range(9):
+        e = ents[k % 3]
+        P = int(rng.integers(1, 60))
+        sel = rng.choice(len(e["d"]["probes"]), P, replace=False)
+        xy = G.upload(e["d"]["probes"][sel])
+        out = torch.full((P, len(e["d"]["edges"])), float("nan"), dtype=torch.float64,
+                         device=G.device())
+        qs.append(dict(e=e, xy=xy, out=out, t=srv.submit(e["id"], xy, e["d"]["optics"],
+                                                         e["d"]["edges"], out)))
+    G.say("server flush of 9 queries over three specimens of one launch class")
+    srv.flush()
+    calls, multi = srv.call_stats()
+    assert calls == 1 and multi == 1, (calls, multi)
+    for q in qs:
+        srv.wait(q["t"])
+    for q in qs:
+        e = q["e"]
+        alone = _alone(e, q["xy"], e["d"]["optics"], e["d"]["edges"])
+        assert torch.equal(q["out"], alone)
