@@ -411,7 +411,7 @@ def run_batch(args, dev):
     import torch
     from synth import batch_workload
     from paper_1702_01904_amd import (Plan, build_batch_workspace_bytes, build_smatrix_batch,
-                                      tile_order)
+                                      probe_batch, probe_batch_workspace_bytes, tile_order)
     t0 = time.perf_counter()
     specs = batch_workload(args.batch, args.seed)
     log(f"batch {args.batch}: {len(specs)} specimens generated in {time.perf_counter() - t0:.1f} s")
@@ -451,6 +451,17 @@ def run_batch(args, dev):
     ms_probe = ev_ms(lambda: [e["plan"].probe_outputs(e["f"], e["amax"], e["S"], e["xy"],
                                                       e["d"]["optics"], e["d"]["edges"],
                                                       e["out"], wsp) for e in ents])
+    # every specimen's probe step in one call: specimens of one launch class
+    # share the window-sum and window launches
+    reqs = [dict(plan=e["plan"], f=e["f"], alpha_max_mrad=e["amax"], smatrix=e["S"],
+                 probe_xy=e["xy"], optics=e["d"]["optics"], edges_mrad=e["d"]["edges"],
+                 out=torch.empty_like(e["out"])) for e in ents]
+    pb_pref, pb_min = probe_batch_workspace_bytes(reqs)
+    wspb = torch.empty(max(pb_min, min(pb_pref, 32 << 30)), dtype=torch.uint8, device=dev)
+    ms_probe_batched = ev_ms(lambda: probe_batch(reqs, wspb))
+    probe_batch_equal = all(bool(torch.equal(r["out"], e["out"])) for r, e in zip(reqs, ents))
+    classes = len({e["plan"].probe_class(e["f"]) for e in ents})
+    del reqs, wspb
     per_n = {}
     for n in sorted({e["d"]["n"] for e in ents}):
         sub = [e for e in ents if e["d"]["n"] == n]
@@ -467,7 +478,8 @@ def run_batch(args, dev):
     bsl = sum(e["B"] * len(e["d"]["thickness"]) for e in ents)
     P = sum(len(e["d"]["probes"]) for e in ents)
     log(f"batch: batched build {ms_batched:.1f} ms, one call per specimen {ms_single:.1f} ms, "
-        f"probe steps {ms_probe:.1f} ms")
+        f"probe steps {ms_probe:.1f} ms (one batched call {ms_probe_batched:.1f} ms, "
+        f"{classes} launch classes, equal {probe_batch_equal})")
     del ents, items, wsb, ws1, wsp
     torch.cuda.synchronize()
     return {
@@ -480,7 +492,11 @@ def run_batch(args, dev):
         "beam_slices_per_s_per_specimen": round(bsl / (ms_single * 1e-3), 1),
         "probe_steps_ms": round(ms_probe, 3),
         "probes_per_s_probe_steps": round(P / (ms_probe * 1e-3), 1),
-        "probes_per_s_end_to_end": round(P / ((ms_batched + ms_probe) * 1e-3), 1),
+        "probe_batch_ms": round(ms_probe_batched, 3),
+        "probes_per_s_probe_batch": round(P / (ms_probe_batched * 1e-3), 1),
+        "probe_batch_launch_classes": classes,
+        "probe_batch_equals_per_specimen_calls": probe_batch_equal,
+        "probes_per_s_end_to_end": round(P / ((ms_batched + min(ms_probe, ms_probe_batched)) * 1e-3), 1),
         "by_grid": per_n,
         "outputs_finite": finite,
     }
@@ -627,6 +643,7 @@ def run_serving(args, plan_fcc, d_fcc, dev):
         torch.cuda.synchronize()
         kind_of, arrive, done_at = {}, {}, {}
         flushes, qi = 0, 0
+        calls0 = srv.call_stats()
         t0 = time.perf_counter()
         ev = 0
         while ev < len(events) or len(done_at) < len(arrive):
@@ -667,8 +684,11 @@ def run_serving(args, plan_fcc, d_fcc, dev):
         span = max(done_at.values())
         if warm:
             return None
+        calls1 = srv.call_stats()
         res = {"offered_queries_per_s": rate, "offered_builds_per_s": build_rate,
-               "flushes": flushes, "resident_GB_end": round(srv.stats()[0] / 1e9, 2)}
+               "flushes": flushes, "resident_GB_end": round(srv.stats()[0] / 1e9, 2),
+               "probe_calls": calls1[0] - calls0[0],
+               "probe_calls_over_several_specimens": calls1[1] - calls0[1]}
         for kind in ("query", "build"):
             ts = [t for t in arrive if kind_of[t][0] == kind]
             if not ts:

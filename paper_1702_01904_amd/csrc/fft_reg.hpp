@@ -60,6 +60,32 @@ __host__ __device__ __forceinline__ float2 rot(float2 a, int m) {
   return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
 }
 
+// a + b w^m and a - b w^m (w = exp(-+2 pi i / R)) with the rotation folded
+// into the sum: for |cos| >= |sin|, b w^m = cos (b.x - b.y tan, b.y + b.x tan)
+// (else sin times the cotangent form), so each output component is one
+// multiply-add of a prepared term instead of a product and a sum. m is a
+// compile-time constant after unrolling; quarter turns cost no arithmetic.
+template <int R, bool INV>
+__host__ __device__ __forceinline__ void rot_pm(float2 a, float2 b, int m, float2& plus,
+                                                float2& minus) {
+  const int q = (m * (64 / R)) & 63;
+  if (q % 16 == 0) {
+    const float2 r = rot<R, INV>(b, m);
+    plus = make_float2(a.x + r.x, a.y + r.y);
+    minus = make_float2(a.x - r.x, a.y - r.y);
+    return;
+  }
+  const float c = cos64(q), s = INV ? sin64(q) : -sin64(q);
+  const bool cdom = (c < 0 ? -c : c) >= (s < 0 ? -s : s);
+  const float k = cdom ? c : s;          // factored-out scale
+  const float t = cdom ? s / c : c / s;  // tangent or cotangent
+  // u = b w^m / k
+  const float2 u = cdom ? make_float2(b.x - b.y * t, b.y + b.x * t)
+                        : make_float2(b.x * t - b.y, b.y * t + b.x);
+  plus = make_float2(a.x + k * u.x, a.y + k * u.y);
+  minus = make_float2(a.x - k * u.x, a.y - k * u.y);
+}
+
 template <int R>
 struct RegSplit {
   static constexpr int R2 = R <= 32 ? 4 : 8;  // inner transforms run over a (length R1)
@@ -79,17 +105,35 @@ __host__ __device__ __forceinline__ void dft_reg(float2 (&v)[R]) {
 #pragma unroll
       for (int a = 0; a < R1; ++a) y[b][a] = v[R2 * a + b];
       dft<R1, INV>(y[b]);
-#pragma unroll
-      for (int c = 1; c < R1; ++c) y[b][c] = rot<R, INV>(y[b][c], b * c);
     }
+    if constexpr (R2 == 4) {
+      // length-4 DFTs over b with the twiddles w_R^{bc} folded into their
+      // first butterflies (rot_pm)
 #pragma unroll
-    for (int c = 0; c < R1; ++c) {
-      float2 z[R2];
+      for (int c = 0; c < R1; ++c) {
+        float2 t0, t1, t2, tm;
+        rot_pm<R, INV>(y[0][c], y[2][c], 2 * c, t0, t1);
+        rot_pm<R, INV>(rot<R, INV>(y[1][c], c), y[3][c], 3 * c, t2, tm);
+        const float2 t3 = mul_mi<INV>(tm);
+        v[c] = cadd(t0, t2);
+        v[c + R1] = cadd(t1, t3);
+        v[c + 2 * R1] = csub(t0, t2);
+        v[c + 3 * R1] = csub(t1, t3);
+      }
+    } else {
 #pragma unroll
-      for (int b = 0; b < R2; ++b) z[b] = y[b][c];
-      dft<R2, INV>(z);
+      for (int b = 1; b < R2; ++b)
 #pragma unroll
-      for (int d = 0; d < R2; ++d) v[c + R1 * d] = z[d];
+        for (int c = 1; c < R1; ++c) y[b][c] = rot<R, INV>(y[b][c], b * c);
+#pragma unroll
+      for (int c = 0; c < R1; ++c) {
+        float2 z[R2];
+#pragma unroll
+        for (int b = 0; b < R2; ++b) z[b] = y[b][c];
+        dft<R2, INV>(z);
+#pragma unroll
+        for (int d = 0; d < R2; ++d) v[c + R1 * d] = z[d];
+      }
     }
   }
 }
