@@ -7,7 +7,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libprism.so")
+# PRISM_LIBRARY names another build of the same library (the host-sanitizer
+# build used by the CPU tests); the default is the in-tree libprism.so.
+LIB_PATH = os.environ.get("PRISM_LIBRARY") or os.path.join(_HERE, "libprism.so")
 
 PRISM_OK = 0
 PRISM_EINVAL = -1

@@ -3,6 +3,11 @@
 Usage: ``python -m paper_1702_01904_amd.build`` or ``build()`` from Python.
 Objects go to ``_build/`` at the repository root; the shared library is
 written next to this file, where the binding loads it from.
+
+``build_sanitized()`` links the same device objects with the host sources
+(plan, serving layer) built with AddressSanitizer and UndefinedBehavior-
+Sanitizer into ``_build/san/libprism_san.so``, for the CPU-side ABI tests
+(run with the ASan runtime preloaded and PRISM_LIBRARY naming that file).
 """
 import os
 import subprocess
@@ -33,6 +38,50 @@ def _cmd(src, obj):
     # host-only C++ against the HIP runtime API (no device code in these files)
     return [HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", *COMMON, "-c",
             os.path.join(SRC, src), "-o", obj]
+
+
+HOST_SOURCES = ["plan.cpp", "server.cpp"]
+SAN_DIR = os.path.join(OUT_DIR, "san")
+SAN_LIB = os.path.join(SAN_DIR, "libprism_san.so")
+# host code only: each sanitizer flag applies to the host compilation
+SAN_FLAGS = ["-O1", "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def asan_runtime():
+    """Path of the ASan runtime of the HIP toolchain (to preload), or None."""
+    import glob
+    hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    return hits[-1] if hits else None
+
+
+def build_sanitized(verbose=False):
+    """Host sources with ASan + UBSan, linked with the device objects of
+    build() (run build() first). Returns the library path."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    objs = []
+    for src in SOURCES:
+        if src in HOST_SOURCES:
+            obj = os.path.join(SAN_DIR, os.path.splitext(src)[0] + ".o")
+            cmd = [HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-std=c++17",
+                   "-fPIC", f"-I{INC}", f"-I{SRC}", *SAN_FLAGS, "-c", os.path.join(SRC, src),
+                   "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+            if res.returncode != 0:
+                raise RuntimeError(f"sanitized build of {src} failed:\n" +
+                                   res.stdout.decode(errors="replace"))
+        else:
+            obj = os.path.join(OUT_DIR, os.path.splitext(src)[0] + ".o")
+            if not os.path.exists(obj):
+                raise RuntimeError(f"{obj} missing: run build() first")
+        objs.append(obj)
+    link = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", SAN_LIB, *objs]
+    res = subprocess.run(link, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if res.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n" + res.stdout.decode(errors="replace"))
+    return SAN_LIB
 
 
 def build(verbose=False):
