@@ -565,6 +565,9 @@ def run_serving(args, plan_fcc, d_fcc, dev):
     budget = int(args.serve_resident_gb * 1e9)
     srv = Server(budget, ws, n_streams=n_streams, max_probes=max_probes, max_det=max_det)
     srv.set_lru_eviction(True)
+    # one call in flight per slot: queries that arrive while every slot is
+    # busy wait and leave together (merged by launch class) when one frees
+    srv.set_dispatch_limit(1)
     free_bufs = {}      # (n, f) shape -> S buffers released by eviction
     live = {}           # specimen id -> entry
 
@@ -723,7 +726,8 @@ def run_serving(args, plan_fcc, d_fcc, dev):
                        "a run of the (n/4)^2 scan raster in probe-tile order",
             "builds": f"Poisson arrivals at {args.serve_build_rate:g}/s, n in {{512, 1024, "
                       f"2048}}, f in {{4, 8, 16}}, admitted by the server's byte budget",
-            "slots": f"{n_streams} query streams (first free slot) + 1 build stream",
+            "slots": f"{n_streams} query streams (first free slot, one call in flight each; "
+                     f"queries arriving meanwhile merge into the next call) + 1 build stream",
             "sweep": sweep}
 
 

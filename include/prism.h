@@ -435,6 +435,12 @@ int prism_server_submit_build(prism_server* server, prism_plan* plan, int f,
 /* LRU eviction (enable != 0): admission may release idle S-matrices, least
  * recently used first (off by default: admission then fails or waits). */
 int prism_server_set_lru_eviction(prism_server* server, int enable);
+/* Dispatch limit (calls_per_slot > 0): a flush sends queries only while
+ * some slot holds fewer than calls_per_slot probe-step calls in flight;
+ * the rest stay queued and are merged with later arrivals at a later flush
+ * (continuous batching: queries join the next call as slots free up).
+ * 0 (the default): every flush dispatches everything it can. */
+int prism_server_set_dispatch_limit(prism_server* server, int calls_per_slot);
 /* Specimens released by LRU eviction since the previous call: up to
  * capacity ids into ids, *count of them. Their S-matrix buffers are the
  * caller's again. */

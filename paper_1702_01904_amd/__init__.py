@@ -515,6 +515,10 @@ class Server:
         """Let admission release idle S-matrices, least recently used first."""
         _native.check(self._L.prism_server_set_lru_eviction(self._h, 1 if enable else 0))
 
+    def set_dispatch_limit(self, calls_per_slot):
+        """Queries wait queued while every slot holds this many calls (0: no limit)."""
+        _native.check(self._L.prism_server_set_dispatch_limit(self._h, int(calls_per_slot)))
+
     def evictions(self, capacity=1024):
         """Ids released by LRU eviction since the last call (their buffers are dropped here)."""
         buf = (ctypes.c_int * int(capacity))()

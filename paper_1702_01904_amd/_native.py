@@ -35,7 +35,7 @@ EXPORTS = (
     "prism_multislice_outputs_accumulate", "prism_build_batch_workspace_bytes",
     "prism_build_smatrix_batch", "prism_server_workspace_bytes", "prism_server_create",
     "prism_server_destroy", "prism_server_admit", "prism_server_submit_build",
-    "prism_server_set_lru_eviction", "prism_server_evictions", "prism_server_evict",
+    "prism_server_set_lru_eviction", "prism_server_set_dispatch_limit", "prism_server_evictions", "prism_server_evict",
     "prism_server_submit",
     "prism_server_flush", "prism_server_poll", "prism_server_wait", "prism_server_stats",
     "prism_server_call_stats",
@@ -160,6 +160,7 @@ def lib():
         "prism_server_submit_build": (I, [P, P, I, D, P, ctypes.c_size_t, P, ctypes.c_size_t,
                                           ctypes.POINTER(I), ctypes.POINTER(ctypes.c_longlong)]),
         "prism_server_set_lru_eviction": (I, [P, I]),
+        "prism_server_set_dispatch_limit": (I, [P, I]),
         "prism_server_evictions": (I, [P, ctypes.POINTER(I), I, ctypes.POINTER(I)]),
         "prism_server_evict": (I, [P, I]),
         "prism_server_submit": (I, [P, I, P, I, ctypes.POINTER(PrismOptics),

@@ -17,9 +17,11 @@
 //     the window-sum and window launches, with the queries of one
 //     (specimen, optics, detector) staged into one request. Each call goes
 //     to the first query slot (stream) that has finished its earlier work,
-//     or else to the slot with the fewest calls in flight, and its stream
-//     waits on the device for the build events of the S-matrices it reads,
-//     so builds and queries of other specimens overlap on the GPU.
+//     or else to the slot with the fewest calls in flight (with a dispatch
+//     limit, queries wait in the queue while every slot holds that many
+//     calls, and merge with later arrivals when a slot frees up), and its
+//     stream waits on the device for the build events of the S-matrices it
+//     reads, so builds and queries of other specimens overlap on the GPU.
 // The server is a client of the public entry points only.
 #include <hip/hip_runtime.h>
 
@@ -108,6 +110,7 @@ struct prism_server {
   std::vector<hipEvent_t> event_pool;
   std::vector<int> evicted;  // released by LRU eviction, not yet reported
   long long merged_calls = 0, multi_specimen_calls = 0;  // dispatched probe calls
+  int dispatch_limit = 0;  // calls in flight per slot before queries wait (0: no limit)
 
   ~prism_server() {
     for (auto s : streams) (void)hipStreamSynchronize(s);
@@ -241,13 +244,15 @@ bool make_room(prism_server* s, size_t need) {
 }
 
 // Query slot for the next call: the first one whose earlier calls have all
-// finished, else the one with the fewest calls in flight.
+// finished, else the one with the fewest calls in flight; -1 when every
+// slot holds dispatch_limit calls (the queries wait for the next flush).
 int pick_slot(const prism_server* s) {
   int best = 0;
   for (int k = 0; k < (int)s->streams.size(); ++k) {
     if (s->slot_inflight[k] == 0) return k;
     if (s->slot_inflight[k] < s->slot_inflight[best]) best = k;
   }
+  if (s->dispatch_limit > 0 && s->slot_inflight[best] >= s->dispatch_limit) return -1;
   return best;
 }
 
@@ -335,6 +340,7 @@ int flush_queries(prism_server* s, std::vector<char>* sent) {
       int total = 0;
       while (r1 < runs.size() && total + runs[r1].probes <= s->max_probes) total += runs[r1++].probes;
       const int k_st = pick_slot(s);
+      if (k_st < 0) return PRISM_OK;  // every slot busy: the rest stays queued
       hipStream_t st = s->streams[k_st];
       const Region rg = region_of(s, k_st);
       std::vector<int> specs;
@@ -550,6 +556,13 @@ int prism_server_evict(prism_server* s, int id) {
   if (hipError_t e = hipStreamSynchronize(s->build_stream); e != hipSuccess) return hip_err(e, "drain");
   if (int r = refresh(s)) return r;
   release(s, id);
+  return PRISM_OK;
+}
+
+int prism_server_set_dispatch_limit(prism_server* s, int calls_per_slot) {
+  if (!s) return set_error(PRISM_EINVAL, "null server");
+  if (calls_per_slot < 0) return set_error(PRISM_EINVAL, "calls_per_slot must be >= 0");
+  s->dispatch_limit = calls_per_slot;
   return PRISM_OK;
 }
 

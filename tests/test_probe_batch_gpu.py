@@ -183,3 +183,48 @@ def test_server_merges_specimens_into_one_call(specs):
         e = q["e"]
         alone = _alone(e, q["xy"], e["d"]["optics"], e["d"]["edges"])
         assert torch.equal(q["out"], alone)
+
+
+def test_server_dispatch_limit_merges_queries_that_wait(specs):
+    # one slot, one call in flight at a time: the queries that arrive while
+    # the first call runs (or right after it) wait and leave in one merged
+    # call over two specimens
+    import torch
+    A, B, C, _ = specs
+    ents = (A, B, C)
+    probe_ws = max(e["plan"].probe_workspace_bytes(e["f"], e["amax"], e["d"]["optics"])[0]
+                   for e in ents)
+    ws = G.workspace(Server.workspace_bytes(1, 4096, 4, probe_ws))
+    srv = Server(sum(e["S"].numel() * 8 for e in ents), ws, n_streams=1, max_probes=4096,
+                 max_det=4)
+    srv.set_dispatch_limit(1)
+    for e in ents:
+        e["id"] = srv.admit(e["plan"], e["f"], e["amax"], e["S"])
+    rng = np.random.default_rng(4)
+    qs = []
+
+    def submit(e):
+        P = int(rng.integers(20, 80))
+        sel = rng.choice(len(e["d"]["probes"]), P, replace=False)
+        xy = G.upload(e["d"]["probes"][sel])
+        out = torch.full((P, len(e["d"]["edges"])), float("nan"), dtype=torch.float64,
+                         device=G.device())
+        q = dict(e=e, xy=xy, out=out, t=srv.submit(e["id"], xy, e["d"]["optics"],
+                                                   e["d"]["edges"], out))
+        qs.append(q)
+        return q
+
+    G.say("server dispatch limit 1: first query, then two that wait")
+    q1 = submit(A)
+    srv.flush()
+    q2, q3 = submit(B), submit(C)
+    srv.flush()
+    srv.wait(q1["t"])
+    srv.flush()
+    srv.wait(q2["t"])
+    srv.wait(q3["t"])
+    assert srv.call_stats() == (2, 1)
+    for q in qs:
+        e = q["e"]
+        alone = _alone(e, q["xy"], e["d"]["optics"], e["d"]["edges"])
+        assert torch.equal(q["out"], alone)
