@@ -238,7 +238,8 @@ __device__ __forceinline__ void contract16_tile(const uint32_t* __restrict__ s16
                                                 const uint32_t* __restrict__ a16g, int np,
                                                 int p_base, int gcount, int ns, int w,
                                                 const UnionGeom16& U, int tile, const int* offx,
-                                                const int* offy, int only, float out_scale,
+                                                const int* offy, const int* rylo,
+                                                const int* ryhi, int only, float out_scale,
                                                 uint32_t* __restrict__ smem,
                                                 float2* __restrict__ window) {
   constexpr int RT = G / 8;
@@ -246,9 +247,30 @@ __device__ __forceinline__ void contract16_tile(const uint32_t* __restrict__ s16
   constexpr int ABUF = AROWS * kPitch16, BBUF = kTile16 * kPitch16;
   constexpr int NAQ = AROWS * 8 / kNT16;     // u32x4 of the A block per thread
   constexpr int NBQ = kTile16 * 8 / kNT16;   // u32x4 of the B block per thread
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int npix = U.uy * U.ux;
   const int nblk = rowlen / kC16KB;
+
+  // Row tiles (8 probes each) this wave multiplies: those holding a probe
+  // whose window meets a union row of the wave's 32 pixels. The skipped
+  // products only reach outputs the epilogue never stores, so the stored
+  // sums are the same. FP32 only: the 16-bit sums wait on operand fetch,
+  // and the branches cost them more than the skipped products save.
+  unsigned rmask = 0;
+  if constexpr (P != Prec::kF32) {
+    rmask = (1u << RT) - 1u;
+  } else if (only >= 0) {
+    rmask = 1u << (only / 8);
+  } else {
+    const int up0 = tile * kTile16 + 16 * kCT16 * wv;
+    if (up0 < npix) {
+      const int a0 = up0 / U.ux, a1 = (min(up0 + 16 * kCT16, npix) - 1) / U.ux;
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+        if (rylo[r] <= a1 && ryhi[r] >= a0) rmask |= 1u << r;
+    }
+  }
 
   // S pixels this thread stages: tile column (tid + 256 i) / 8. Columns
   // past the union read pixel 0 instead; their outputs are never stored,
@@ -306,14 +328,16 @@ __device__ __forceinline__ void contract16_tile(const uint32_t* __restrict__ s16
       u32x4 av[RT], bv[kCT16];
 #pragma unroll
       for (int r = 0; r < RT; ++r)
-        av[r] = *reinterpret_cast<const u32x4*>(A + 16 * r * kPitch16 + 16 * ks);
+        if (rmask >> r & 1u)
+          av[r] = *reinterpret_cast<const u32x4*>(A + 16 * r * kPitch16 + 16 * ks);
 #pragma unroll
       for (int c = 0; c < kCT16; ++c)
         bv[c] = *reinterpret_cast<const u32x4*>(Bm + 16 * c * kPitch16 + 16 * ks);
 #pragma unroll
       for (int r = 0; r < RT; ++r)
+        if (rmask >> r & 1u)
 #pragma unroll
-        for (int c = 0; c < kCT16; ++c) acc[r][c] = mfma16<P>(av[r], bv[c], acc[r][c]);
+          for (int c = 0; c < kCT16; ++c) acc[r][c] = mfma16<P>(av[r], bv[c], acc[r][c]);
     }
   };
 
@@ -363,6 +387,7 @@ __global__ __launch_bounds__(kNT16) __attribute__((amdgpu_waves_per_eu(2))) void
   __shared__ int offx[G], offy[G];
   __shared__ int zero[G];
   __shared__ int ginfo[6];
+  __shared__ int rylo[G / 8], ryhi[G / 8];  // union rows each row tile's windows span
   const int tid = threadIdx.x;
   int k = 0;  // segment of this group (uniform)
   while (k + 1 < segs.n && (int)blockIdx.y >= segs.s[k + 1].g_begin) ++k;
@@ -411,19 +436,32 @@ __global__ __launch_bounds__(kNT16) __attribute__((amdgpu_waves_per_eu(2))) void
   }
   for (int g = tid; g < G; g += kNT16) zero[g] = 0;
   __syncthreads();
+  if (tid < G / 8) {
+    int lo = 1 << 30, hi = -1;
+    for (int j = 0; j < 8; ++j) {
+      const int g = 8 * tid + j;
+      if (g < gcount) {
+        lo = min(lo, offy[g]);
+        hi = max(hi, offy[g] + w - 1);
+      }
+    }
+    rylo[tid] = lo;
+    ryhi[tid] = hi;
+  }
+  __syncthreads();
   // the workgroups of a group share its tiles round-robin
   if (ginfo[0] == 0) {
     const UnionGeom16 U{ginfo[1], ginfo[2], ginfo[3], ginfo[4]};
     for (int tile = blockIdx.x; tile * kTile16 < U.uy * U.ux; tile += gridDim.x)
       contract16_tile<G, P>(s16, rowlen, a16g, np, p_base, gcount, ns, w, U, tile, offx, offy,
-                            -1, sg.out_scale, smem, sg.window);
+                            rylo, ryhi, -1, sg.out_scale, smem, sg.window);
   } else {
     for (int tile = blockIdx.x; tile * kTile16 < w * w; tile += gridDim.x) {
       for (int g = 0; g < gcount; ++g) {
         const int2 o = origin[p_base + g];
         const UnionGeom16 U{o.y, o.x, w, w};
         contract16_tile<G, P>(s16, rowlen, a16g, np, p_base, gcount, ns, w, U, tile, zero, zero,
-                              g, sg.out_scale, smem, sg.window);
+                              rylo, ryhi, g, sg.out_scale, smem, sg.window);
       }
     }
   }
