@@ -228,3 +228,40 @@ def test_server_dispatch_limit_merges_queries_that_wait(specs):
         e = q["e"]
         alone = _alone(e, q["xy"], e["d"]["optics"], e["d"]["edges"])
         assert torch.equal(q["out"], alone)
+
+
+def test_batch_two_pass_windows_equal_separate_calls():
+    # W = 192 (two passes over the window buffer, per piece): two 384^2
+    # specimens at f = 1 in one class, detector sums, an accumulating request
+    # and a CBED request, each equal to its own call
+    import torch
+    E = [_spec("mid384", 0, 1), _spec("mid384", 3, 1)]
+    rng = np.random.default_rng(12)
+    reqs, meta = [], []
+    for k, (e, kind) in enumerate(((E[0], "det"), (E[1], "det"), (E[0], "acc"), (E[1], "cbed"))):
+        P = int(rng.integers(5, 30))
+        sel = rng.choice(len(e["d"]["probes"]), P, replace=False)
+        xy = G.upload(e["d"]["probes"][sel])
+        edges = e["d"]["edges"]
+        r = dict(plan=e["plan"], f=1, alpha_max_mrad=e["amax"], smatrix=e["S"], probe_xy=xy,
+                 optics=e["d"]["optics"], edges_mrad=edges)
+        if kind == "cbed":
+            w = e["plan"].n // 2
+            r["edges_mrad"] = None
+            r["out"] = torch.full((P, w, w), float("nan"), dtype=torch.float32, device=G.device())
+        else:
+            r["out"] = torch.from_numpy(rng.random((P, len(edges)))).to(G.device())
+        if kind == "acc":
+            r["weight"] = 0.25
+        meta.append((e, kind, r["out"].clone()))
+        reqs.append(r)
+    pref, mn = probe_batch_workspace_bytes(reqs)
+    G.say(f"probe_batch W=192: {len(reqs)} requests, ws={pref}")
+    probe_batch(reqs, G.workspace(pref))
+    torch.cuda.synchronize()
+    for r, (e, kind, out0) in zip(reqs, meta):
+        G.say(f"separate call W=192 {kind}")
+        alone = _alone(e, r["probe_xy"], r["optics"], r["edges_mrad"],
+                       out0=out0 if kind == "acc" else None,
+                       weight=r.get("weight"), cbed=kind == "cbed")
+        assert torch.equal(r["out"], alone), kind
