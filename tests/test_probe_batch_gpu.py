@@ -265,3 +265,28 @@ def test_batch_two_pass_windows_equal_separate_calls():
                        out0=out0 if kind == "acc" else None,
                        weight=r.get("weight"), cbed=kind == "cbed")
         assert torch.equal(r["out"], alone), kind
+
+
+def test_batch_cbed_segments_of_two_specimens(specs):
+    # CBED requests of two specimens (W = 32) share the window launch: each
+    # segment's patterns land in its own output, equal to its own call
+    import torch
+    A, B, C, _ = specs
+    rng = np.random.default_rng(17)
+    reqs, meta = [], []
+    for e in (A, C, B):
+        P = int(rng.integers(3, 25))
+        sel = rng.choice(len(e["d"]["probes"]), P, replace=False)
+        w = e["plan"].n // (2 * e["f"])
+        reqs.append(dict(plan=e["plan"], f=e["f"], alpha_max_mrad=e["amax"], smatrix=e["S"],
+                         probe_xy=G.upload(e["d"]["probes"][sel]), optics=e["d"]["optics"],
+                         edges_mrad=None,
+                         out=torch.full((P, w, w), float("nan"), dtype=torch.float32,
+                                        device=G.device())))
+        meta.append(e)
+    G.say("probe_batch: three CBED requests over two grid sizes")
+    probe_batch(reqs, G.workspace(probe_batch_workspace_bytes(reqs)[0]))
+    torch.cuda.synchronize()
+    for r, e in zip(reqs, meta):
+        alone = _alone(e, r["probe_xy"], r["optics"], None, cbed=True)
+        assert torch.equal(r["out"], alone)
