@@ -338,7 +338,7 @@ const prism_plan::PixLists* get_pixlists(prism_plan* p, int w, int f, const pris
 
 // ---------------------------------------------------------------- layouts
 
-constexpr size_t kChunkBytes = size_t(1) << 28;  // preferred probe-window bytes per chunk
+constexpr size_t kChunkBytes = size_t(1) << 30;  // preferred probe-window bytes per chunk
 
 size_t state_bytes(int n) { return (size_t)n * (n / 2) * sizeof(float2); }
 
