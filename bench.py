@@ -40,10 +40,10 @@ CONFIG = "fcc1024"
 # write x1.0), as in the HBM-traffic summary under profiles/. Valid only for
 # the kernel sources with this hash (of their code, comments aside); reported
 # as null otherwise.
-TRAFFIC_SRC_SHA = "39a8cf94b95489f4"
-TRAFFIC_BYTES = {"row_pass": 545669950, "col_pass": 521795169, "contract": 2378244872,
-                 "s32_pack": 1310733584, "window_detect": 270446010, "contract16": 996907465,
-                 "s16_pack": 975209336}
+TRAFFIC_SRC_SHA = "db6e99562114a49d"
+TRAFFIC_BYTES = {"row_pass": 545111555, "col_pass": 521786651, "contract": 9209755723,
+                 "s32_pack": 1310708319, "window_detect": 1079277747, "contract16": 4108455472,
+                 "s16_pack": 975189531}
 
 
 # Sources that decide the profiled kernels and their launch shapes (the
