@@ -192,8 +192,10 @@ int prism_build_smatrix(prism_plan* plan, int f, double alpha_max_mrad, void* sm
  * common slices form one group: the waves of all their beams run through the
  * same launches, slice by slice, each wave multiplying by its own specimen's
  * transmission (specimens with fewer slices drop out of later launches);
- * groups run one after another. The results equal prism_build_smatrix of
- * each item alone, bit for bit.
+ * groups run one after another. An item with at least four such launches'
+ * worth of beams gains nothing from sharing and is built on its own (as
+ * prism_build_smatrix, with its plan's launch shapes). The results equal
+ * prism_build_smatrix of each item alone, bit for bit.
  * Workspace (prism_build_batch_workspace_bytes): per group the
  * transmissions of every member (sum of H n^2 complex64), the beam lists and
  * up to 256 MiB of wave state per launch (larger launches lose the cache

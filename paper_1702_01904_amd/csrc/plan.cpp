@@ -1369,14 +1369,35 @@ bool same_medium(const prism_plan* a, const prism_plan* b) {
   return true;
 }
 
-int batch_groups(const prism_build_item* items, int count, std::vector<BatchGroup>* groups) {
+// Members whose own chunks are full gain nothing from sharing launches: an
+// item with at least kAloneChunks batched launches' worth of beams is built
+// on its own (its plan's launch shapes, no per-wave transmission table, no
+// members dropping out of shared launches); the others share launches.
+constexpr int kAloneChunks = 4;
+
+int batch_pref_chunk(int n, int total);
+
+bool builds_alone(const prism_build_item& it) {
+  const int B = (int)(it.plan->beams.at({it.f, dbits(it.alpha_max_mrad)}).size() / 2);
+  return B >= kAloneChunks * batch_pref_chunk(it.plan->n, 1 << 30);
+}
+
+// Items that share launches, grouped by medium (checked first); *alone
+// receives the others.
+int batch_groups(const prism_build_item* items, int count, std::vector<BatchGroup>* groups,
+                 std::vector<int>* alone) {
   groups->clear();
+  alone->clear();
   for (int i = 0; i < count; ++i) {
     const prism_plan* p = items[i].plan;
     if (!p) return fail(PRISM_EINVAL, "batch item " + std::to_string(i) + ": null plan");
     const std::vector<int32_t>* mn;
     if (int r = beams_checked(p, items[i].f, items[i].alpha_max_mrad, &mn))
       return fail(r, "batch item " + std::to_string(i) + ": " + g_err);
+    if (builds_alone(items[i])) {
+      alone->push_back(i);
+      continue;
+    }
     BatchGroup* g = nullptr;
     for (auto& cand : *groups) {
       bool ok = true;
@@ -1556,13 +1577,22 @@ int prism_build_batch_workspace_bytes(const prism_build_item* items, int count, 
   if (!pref || !minimum || (count > 0 && !items)) return fail(PRISM_EINVAL, "null argument");
   if (count < 0) return fail(PRISM_EINVAL, "negative item count");
   std::vector<BatchGroup> groups;
-  if (int r = batch_groups(items, count, &groups)) return r;
+  std::vector<int> alone;
+  if (int r = batch_groups(items, count, &groups, &alone)) return r;
   *pref = *minimum = 0;
   for (const auto& g : groups) {
     BatchWs w;
     const int total = batch_total_waves(items, g);
     *pref = std::max(*pref, batch_layout(items, g, batch_pref_chunk(g.ref->n, total), &w, nullptr));
     *minimum = std::max(*minimum, batch_layout(items, g, 1, &w, nullptr));
+  }
+  for (int i : alone) {
+    size_t p1, m1;
+    if (int r = prism_build_workspace_bytes(items[i].plan, items[i].f, items[i].alpha_max_mrad, &p1,
+                                            &m1))
+      return r;
+    *pref = std::max(*pref, p1);
+    *minimum = std::max(*minimum, m1);
   }
   return PRISM_OK;
 }
@@ -1573,7 +1603,8 @@ int prism_build_smatrix_batch(const prism_build_item* items, int count, void* ws
   if (count == 0) return PRISM_OK;
   if (!items) return fail(PRISM_EINVAL, "null argument");
   std::vector<BatchGroup> groups;
-  if (int r = batch_groups(items, count, &groups)) return r;
+  std::vector<int> alone;
+  if (int r = batch_groups(items, count, &groups, &alone)) return r;
   for (int i = 0; i < count; ++i) {
     if (!items[i].smatrix_dev) return fail(PRISM_EINVAL, "batch item " + std::to_string(i) + ": null S-matrix");
     const std::vector<int32_t>& mn =
@@ -1590,7 +1621,20 @@ int prism_build_smatrix_batch(const prism_build_item* items, int count, void* ws
     if (batch_layout(items, g, 1, &w, nullptr) > ws_bytes)
       return fail(PRISM_ENOSPACE, "workspace smaller than the batched build minimum");
   }
+  for (int i : alone) {
+    size_t p1, m1;
+    if (int r = prism_build_workspace_bytes(items[i].plan, items[i].f, items[i].alpha_max_mrad, &p1,
+                                            &m1))
+      return r;
+    if (m1 > ws_bytes) return fail(PRISM_ENOSPACE, "workspace smaller than the batched build minimum");
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int i : alone) {
+    const prism_build_item& it = items[i];
+    if (int r = prism_build_smatrix(it.plan, it.f, it.alpha_max_mrad, it.smatrix_dev,
+                                    it.smatrix_bytes, ws, ws_bytes, stream))
+      return fail(r, "batch item " + std::to_string(i) + ": " + g_err);
+  }
   for (const auto& g : groups)
     if (int r = batch_build_group(items, g, ws, ws_bytes, st)) return r;
   return PRISM_OK;
