@@ -40,10 +40,10 @@ CONFIG = "fcc1024"
 # write x1.0), as in the HBM-traffic summary under profiles/. Valid only for
 # the kernel sources with this hash (of their code, comments aside); reported
 # as null otherwise.
-TRAFFIC_SRC_SHA = "db6e99562114a49d"
-TRAFFIC_BYTES = {"row_pass": 545111555, "col_pass": 521786651, "contract": 9209755723,
-                 "s32_pack": 1310708319, "window_detect": 1079277747, "contract16": 4108455472,
-                 "s16_pack": 975189531}
+TRAFFIC_SRC_SHA = "e3515d977c351543"
+TRAFFIC_BYTES = {"row_pass": 545767749, "col_pass": 521787833, "contract": 9209854990,
+                 "s32_pack": 1310712053, "window_detect": 1079265528, "contract16": 4109981973,
+                 "s16_pack": 975189404}
 
 
 # Sources that decide the profiled kernels and their launch shapes (the
