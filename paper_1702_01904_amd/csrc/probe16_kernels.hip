@@ -19,6 +19,11 @@
 //    steps; K' is visited as 4 (l/16) + 16 ks + s on both operands, a
 //    permutation of the block's 32 real K' indices, so the sum is the same.
 //    The scale is 1.
+//  * Staging: 16-bit K blocks pass through registers into padded LDS rows,
+//    two blocks ahead (these sums wait on operand fetch); FP32 K blocks go
+//    straight from global memory into XOR-swizzled LDS rows
+//    (global_load_lds_dwordx4), one block ahead, which frees the staging
+//    registers for reading both K steps' operands before their products.
 //  * The 1 / (W sqrt(B_A)) normalisation is applied in FP32 at the end.
 #include "fft_lds.hpp"
 #include "kernels.hpp"
@@ -240,8 +245,8 @@ __device__ __forceinline__ void contract16_tile(const uint32_t* __restrict__ s16
                                                 const UnionGeom16& U, int tile, const int* offx,
                                                 const int* offy, const int* rylo,
                                                 const int* ryhi, int only, float out_scale,
-                                                uint32_t* __restrict__ smem,
-                                                float2* __restrict__ window) {
+                                                uint32_t* __restrict__ smem, uint32_t* buf0,
+                                                uint32_t* buf1, float2* __restrict__ window) {
   constexpr int RT = G / 8;
   constexpr int AROWS = 2 * G;
   constexpr int ABUF = AROWS * kPitch16, BBUF = kTile16 * kPitch16;
@@ -289,70 +294,143 @@ __device__ __forceinline__ void contract16_tile(const uint32_t* __restrict__ s16
   }
   const uint32_t* s16q = s16 + 4 * (tid & 7);
 
-  u32x4 ga[2][NAQ], gb[2][NBQ];
-  auto fetch = [&](int set, int blk) {
-    const u32x4* ab = reinterpret_cast<const u32x4*>(a16g + (size_t)blk * AROWS * kC16KB);
-#pragma unroll
-    for (int i = 0; i < NAQ; ++i) ga[set][i] = ab[tid + kNT16 * i];
-#pragma unroll
-    for (int i = 0; i < NBQ; ++i)
-      gb[set][i] = *reinterpret_cast<const u32x4*>(s16q + (size_t)spix[i] * rowlen + blk * kC16KB);
-  };
-  auto stash = [&](int set) {
-    uint32_t* A = smem + set * ABUF;
-    uint32_t* Bm = smem + 2 * ABUF + set * BBUF;
-#pragma unroll
-    for (int i = 0; i < NAQ; ++i) {
-      const int idx = tid + kNT16 * i;
-      *reinterpret_cast<u32x4*>(A + (idx >> 3) * kPitch16 + 4 * (idx & 7)) = ga[set][i];
-    }
-#pragma unroll
-    for (int i = 0; i < NBQ; ++i) {
-      const int idx = tid + kNT16 * i;
-      *reinterpret_cast<u32x4*>(Bm + (idx >> 3) * kPitch16 + 4 * (idx & 7)) = gb[set][i];
-    }
-  };
-
   floatx4 acc[RT][kCT16];
 #pragma unroll
   for (int r = 0; r < RT; ++r)
 #pragma unroll
     for (int c = 0; c < kCT16; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-
   const int krow = lane >> 4, mcol = lane & 15;
-  auto compute = [&](int buf) {
-    const uint32_t* A = smem + buf * ABUF + mcol * kPitch16 + 4 * krow;
-    const uint32_t* Bm = smem + 2 * ABUF + buf * BBUF + (16 * kCT16 * wv + mcol) * kPitch16 + 4 * krow;
+
+  if constexpr (P == Prec::kF32) {
+    // Operands go from global memory straight into LDS
+    // (global_load_lds_dwordx4: lane i of a wave's instruction writes its 16
+    // bytes at the wave's LDS base + 16 i), one K block ahead of the
+    // products, into two buffers that are separate LDS arrays (so the
+    // compiler sees that reads of one never wait for loads into the other);
+    // no registers stage them. An LDS row holds the 8 16-byte segments of
+    // one A row or of one pixel's K block, segment s stored at s ^ (row & 7),
+    // so the rows that one read instruction's lanes meet fall in different
+    // banks.
+    constexpr int P32 = kC16KB;  // LDS row: 32 words, no padding
+    constexpr int AOFF = 0, BOFF = AROWS * P32;
+    typedef __attribute__((address_space(3))) void* lds_ptr;
+    auto issue = [&](uint32_t* buf, int blk) {
+      const uint32_t* ab = a16g + (size_t)blk * AROWS * kC16KB;
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      u32x4 av[RT], bv[kCT16];
+      for (int i = 0; i < NAQ; ++i) {
+        const int row = (tid + kNT16 * i) >> 3;
+        const int seg = (tid & 7) ^ (row & 7);
+        __builtin_amdgcn_global_load_lds(ab + (size_t)row * kC16KB + 4 * seg,
+                                         (lds_ptr)(buf + AOFF + 4 * (kNT16 * i + 64 * wv)), 16, 0,
+                                         0);
+      }
 #pragma unroll
-      for (int r = 0; r < RT; ++r)
-        if (rmask >> r & 1u)
+      for (int i = 0; i < NBQ; ++i) {
+        const int row = (tid + kNT16 * i) >> 3;
+        const int seg = (tid & 7) ^ (row & 7);
+        __builtin_amdgcn_global_load_lds(s16 + (size_t)spix[i] * rowlen + blk * kC16KB + 4 * seg,
+                                         (lds_ptr)(buf + BOFF + 4 * (kNT16 * i + 64 * wv)), 16, 0,
+                                         0);
+      }
+    };
+    // both K steps' operands are read before the products, so the second
+    // step's reads overlap the first step's products
+    auto compute = [&](const uint32_t* buf) {
+      const uint32_t* A = buf + AOFF + mcol * P32;
+      const uint32_t* Bm = buf + BOFF + (16 * kCT16 * wv + mcol) * P32;
+      u32x4 av[2][RT], bv[2][kCT16];
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const int seg = 4 * ((krow + 4 * ks) ^ (mcol & 7));
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+          av[ks][r] = *reinterpret_cast<const u32x4*>(A + 16 * r * P32 + seg);
+#pragma unroll
+        for (int c = 0; c < kCT16; ++c)
+          bv[ks][c] = *reinterpret_cast<const u32x4*>(Bm + 16 * c * P32 + seg);
+      }
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+          if (rmask >> r & 1u)
+#pragma unroll
+            for (int c = 0; c < kCT16; ++c) acc[r][c] = mfma16<P>(av[ks][r], bv[ks][c], acc[r][c]);
+    };
+    // rows hold a whole number of K-block pairs: block 2j in buf0, 2j + 1
+    // in buf1
+    issue(buf0, 0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's loads are in LDS
+    __syncthreads();
+    for (int blk = 0; blk < nblk; blk += 2) {
+      issue(buf1, blk + 1);
+      compute(buf0);
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+      // every wave's block blk + 1 is in LDS and no wave still reads buf0
+      __syncthreads();
+      if (blk + 2 < nblk) issue(buf0, blk + 2);
+      compute(buf1);
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+      __syncthreads();
+    }
+  } else {
+    u32x4 ga[2][NAQ], gb[2][NBQ];
+    auto fetch = [&](int set, int blk) {
+      const u32x4* ab = reinterpret_cast<const u32x4*>(a16g + (size_t)blk * AROWS * kC16KB);
+#pragma unroll
+      for (int i = 0; i < NAQ; ++i) ga[set][i] = ab[tid + kNT16 * i];
+#pragma unroll
+      for (int i = 0; i < NBQ; ++i)
+        gb[set][i] =
+            *reinterpret_cast<const u32x4*>(s16q + (size_t)spix[i] * rowlen + blk * kC16KB);
+    };
+    auto stash = [&](int set) {
+      uint32_t* A = smem + set * ABUF;
+      uint32_t* Bm = smem + 2 * ABUF + set * BBUF;
+#pragma unroll
+      for (int i = 0; i < NAQ; ++i) {
+        const int idx = tid + kNT16 * i;
+        *reinterpret_cast<u32x4*>(A + (idx >> 3) * kPitch16 + 4 * (idx & 7)) = ga[set][i];
+      }
+#pragma unroll
+      for (int i = 0; i < NBQ; ++i) {
+        const int idx = tid + kNT16 * i;
+        *reinterpret_cast<u32x4*>(Bm + (idx >> 3) * kPitch16 + 4 * (idx & 7)) = gb[set][i];
+      }
+    };
+    auto compute = [&](int buf) {
+      const uint32_t* A = smem + buf * ABUF + mcol * kPitch16 + 4 * krow;
+      const uint32_t* Bm =
+          smem + 2 * ABUF + buf * BBUF + (16 * kCT16 * wv + mcol) * kPitch16 + 4 * krow;
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        u32x4 av[RT], bv[kCT16];
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
           av[r] = *reinterpret_cast<const u32x4*>(A + 16 * r * kPitch16 + 16 * ks);
 #pragma unroll
-      for (int c = 0; c < kCT16; ++c)
-        bv[c] = *reinterpret_cast<const u32x4*>(Bm + 16 * c * kPitch16 + 16 * ks);
+        for (int c = 0; c < kCT16; ++c)
+          bv[c] = *reinterpret_cast<const u32x4*>(Bm + 16 * c * kPitch16 + 16 * ks);
 #pragma unroll
-      for (int r = 0; r < RT; ++r)
-        if (rmask >> r & 1u)
+        for (int r = 0; r < RT; ++r)
 #pragma unroll
           for (int c = 0; c < kCT16; ++c) acc[r][c] = mfma16<P>(av[r], bv[c], acc[r][c]);
-    }
-  };
+      }
+    };
 
-  // rows hold a whole number of K-block pairs
-  fetch(0, 0);
-  fetch(1, 1);
-  for (int blk = 0; blk < nblk; blk += 2) {
-    stash(0);
-    __syncthreads();
-    fetch(0, min(blk + 2, nblk - 2));
-    compute(0);
-    stash(1);
-    __syncthreads();
-    fetch(1, min(blk + 3, nblk - 1));
-    compute(1);
+    // rows hold a whole number of K-block pairs
+    fetch(0, 0);
+    fetch(1, 1);
+    for (int blk = 0; blk < nblk; blk += 2) {
+      stash(0);
+      __syncthreads();
+      fetch(0, min(blk + 2, nblk - 2));
+      compute(0);
+      stash(1);
+      __syncthreads();
+      fetch(1, min(blk + 3, nblk - 1));
+      compute(1);
+    }
   }
   __syncthreads();
 
@@ -382,8 +460,13 @@ __device__ __forceinline__ void contract16_tile(const uint32_t* __restrict__ s16
 template <int G, Prec P>
 __global__ __launch_bounds__(kNT16) __attribute__((amdgpu_waves_per_eu(2))) void k_contract16(
     const ContractSegs segs, int w) {
-  constexpr int LDS = 2 * (2 * G * kPitch16) + 2 * (kTile16 * kPitch16);
+  // 16-bit operands: one array for both register-staged buffers; FP32: two
+  // arrays, one per buffer (A block, then B block)
+  constexpr bool F32 = P == Prec::kF32;
+  constexpr int LDS = F32 ? 1 : 2 * (2 * G * kPitch16) + 2 * (kTile16 * kPitch16);
+  constexpr int LDSB = F32 ? (2 * G + kTile16) * kC16KB : 1;
   __shared__ uint32_t smem[LDS];
+  __shared__ uint32_t sbuf0[LDSB], sbuf1[LDSB];
   __shared__ int offx[G], offy[G];
   __shared__ int zero[G];
   __shared__ int ginfo[6];
@@ -454,14 +537,14 @@ __global__ __launch_bounds__(kNT16) __attribute__((amdgpu_waves_per_eu(2))) void
     const UnionGeom16 U{ginfo[1], ginfo[2], ginfo[3], ginfo[4]};
     for (int tile = blockIdx.x; tile * kTile16 < U.uy * U.ux; tile += gridDim.x)
       contract16_tile<G, P>(s16, rowlen, a16g, np, p_base, gcount, ns, w, U, tile, offx, offy,
-                            rylo, ryhi, -1, sg.out_scale, smem, sg.window);
+                            rylo, ryhi, -1, sg.out_scale, smem, sbuf0, sbuf1, sg.window);
   } else {
     for (int tile = blockIdx.x; tile * kTile16 < w * w; tile += gridDim.x) {
       for (int g = 0; g < gcount; ++g) {
         const int2 o = origin[p_base + g];
         const UnionGeom16 U{o.y, o.x, w, w};
         contract16_tile<G, P>(s16, rowlen, a16g, np, p_base, gcount, ns, w, U, tile, zero, zero,
-                              rylo, ryhi, g, sg.out_scale, smem, sg.window);
+                              rylo, ryhi, g, sg.out_scale, smem, sbuf0, sbuf1, sg.window);
       }
     }
   }
