@@ -40,10 +40,10 @@ CONFIG = "fcc1024"
 # write x1.0), as in the HBM-traffic summary under profiles/. Valid only for
 # the kernel sources with this hash (of their code, comments aside); reported
 # as null otherwise.
-TRAFFIC_SRC_SHA = "e3515d977c351543"
-TRAFFIC_BYTES = {"row_pass": 545767749, "col_pass": 521787833, "contract": 9209854990,
-                 "s32_pack": 1310712053, "window_detect": 1079265528, "contract16": 4109981973,
-                 "s16_pack": 975189404}
+TRAFFIC_SRC_SHA = "628782447520b4ad"
+TRAFFIC_BYTES = {"row_pass": 545768432, "col_pass": 521785452, "contract": 9361560844,
+                 "s32_pack": 1310708518, "window_detect": 1079227180, "contract16": 4118933733,
+                 "s16_pack": 975186402}
 
 
 # Sources that decide the profiled kernels and their launch shapes (the
