@@ -19,6 +19,10 @@
  *     checks run on the host before anything is enqueued. prism_last_error()
  *     returns a thread-local message for the last failing call.
  *   - Complex values are interleaved float pairs (re, im) ("c64").
+ *   - A plan fills host-side caches (beam sets, aperture rows, detector pixel
+ *     lists) on first use and never rewrites an entry: calls on one plan
+ *     from several host threads at once must be serialised by the caller;
+ *     different plans are independent.
  *   - Every call that takes an S-matrix pointer also takes the byte size of
  *     the caller's buffer and rejects one smaller than prism_smatrix_bytes
  *     for its f and alpha_max (PRISM_EINVAL), so no kernel can read or write
