@@ -40,10 +40,10 @@ CONFIG = "fcc1024"
 # write x1.0), as in the HBM-traffic summary under profiles/. Valid only for
 # the kernel sources with this hash (of their code, comments aside); reported
 # as null otherwise.
-TRAFFIC_SRC_SHA = "c5cfc0b5561b82f3"
-TRAFFIC_BYTES = {"row_pass": 563293615, "col_pass": 521796511, "contract": 9355365875,
-                 "s32_pack": 1310732779, "window_detect": 1079298665, "contract16": 4112960455,
-                 "s16_pack": 975211753}
+TRAFFIC_SRC_SHA = "e12e9f7330dbe939"
+TRAFFIC_BYTES = {"row_pass": 563570899, "col_pass": 521795857, "contract": 9360449319,
+                 "s32_pack": 1310731654, "window_detect": 1079354783, "contract16": 4675091071,
+                 "s16_pack": 975210392}
 
 
 # Sources that decide the profiled kernels and their launch shapes (the

@@ -229,9 +229,20 @@ __global__ void k_alpha16(const double* __restrict__ probe_xy, int p0, int np,
   }
 }
 
-constexpr int kNT16 = 256;
-constexpr int kCT16 = 2;                 // 16-pixel column tiles per wave
-constexpr int kTile16 = 4 * 16 * kCT16;  // union pixels per workgroup
+// Workgroup shape per group size and operand form. Both shapes cover 128
+// union pixels. FP32 (bound by the matrix cores) gives each of 4 waves two
+// 16-pixel column tiles at two waves per SIMD; the 16-bit forms (bound by
+// operand fetch) give each of 8 waves one tile at four waves per SIMD, so
+// more waves cover each other's waits, for groups whose A block (2G rows of
+// 8 16-byte segments) has at least one segment per thread (G >= 32).
+template <int G, Prec P>
+struct C16Shape {
+  static constexpr bool kWide = P != Prec::kF32 && G >= 32;
+  static constexpr int NT = kWide ? 512 : 256;  // threads per workgroup
+  static constexpr int CT = kWide ? 1 : 2;      // 16-pixel column tiles per wave
+  static constexpr int WPE = kWide ? 4 : 2;     // waves per SIMD (register budget)
+};
+constexpr int kTile16 = 128;  // union pixels per workgroup
 constexpr int kPitch16 = 36;             // uint32 per LDS row (32 + 4 pad)
 
 struct UnionGeom16 {
@@ -247,6 +258,10 @@ __device__ __forceinline__ void contract16_tile(const uint32_t* __restrict__ s16
                                                 const int* ryhi, int only, float out_scale,
                                                 uint32_t* __restrict__ smem, uint32_t* buf0,
                                                 uint32_t* buf1, float2* __restrict__ window) {
+  constexpr int kNT16 = C16Shape<G, P>::NT, kCT16 = C16Shape<G, P>::CT;
+  static_assert(kNT16 / 64 * 16 * kCT16 == kTile16, "a workgroup covers one union tile");
+  static_assert(2 * G * 8 % kNT16 == 0 && kTile16 * 8 % kNT16 == 0,
+                "every thread stages whole 16-byte segments of A and B");
   constexpr int RT = G / 8;
   constexpr int AROWS = 2 * G;
   constexpr int ABUF = AROWS * kPitch16, BBUF = kTile16 * kPitch16;
@@ -458,7 +473,8 @@ __device__ __forceinline__ void contract16_tile(const uint32_t* __restrict__ s16
 // Grid: x walks the union tiles of a group, y the probe groups of every
 // segment (segment k owns groups g_begin .. g_begin + ceil(np / G)).
 template <int G, Prec P>
-__global__ __launch_bounds__(kNT16) __attribute__((amdgpu_waves_per_eu(2))) void k_contract16(
+__global__ __launch_bounds__((C16Shape<G, P>::NT))
+__attribute__((amdgpu_waves_per_eu(C16Shape<G, P>::WPE))) void k_contract16(
     const ContractSegs segs, int w) {
   // 16-bit operands: one array for both register-staged buffers; FP32: two
   // arrays, one per buffer (A block, then B block)
@@ -517,7 +533,7 @@ __global__ __launch_bounds__(kNT16) __attribute__((amdgpu_waves_per_eu(2))) void
       ginfo[4] = w + (maxx - minx);
     }
   }
-  for (int g = tid; g < G; g += kNT16) zero[g] = 0;
+  for (int g = tid; g < G; g += C16Shape<G, P>::NT) zero[g] = 0;
   __syncthreads();
   if (tid < G / 8) {
     int lo = 1 << 30, hi = -1;
@@ -605,7 +621,7 @@ hipError_t launch_contract16(const ContractSegs& segs, int w, int group, Prec pr
   if (segs.n < 1 || segs.n > kMaxSeg || segs.groups < 1) return hipErrorInvalidValue;
   const dim3 grid((unsigned)contract_tile_slots(w, window_tile_div), (unsigned)segs.groups);
 #define C16(GG, PP) \
-  hipLaunchKernelGGL((k_contract16<GG, PP>), grid, dim3(kNT16), 0, st, segs, w)
+  hipLaunchKernelGGL((k_contract16<GG, PP>), grid, dim3(C16Shape<GG, PP>::NT), 0, st, segs, w)
 #define C16G(PP)                          \
   switch (group) {                        \
     case 16: C16(16, PP); break;          \
