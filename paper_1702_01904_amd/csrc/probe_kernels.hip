@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void k_window_rows256(float2* __restrict__ win
   for (int d = 0; d < R; ++d) row[j + R * d] = v[d];
 }
 
-template <bool CBED>
+template <bool CBED, int NB>
 __global__ __launch_bounds__(256) void k_window_cols256_detect(const float2* __restrict__ window,
                                                                const float2* __restrict__ twW,
                                                                int f, DetBins bins,
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void k_window_cols256_detect(const float2* __r
   constexpr int CS = R * LS + 1;  // column stride: 16 columns on distinct banks
   __shared__ float2 twl[R * R];
   __shared__ float2 lds[TC * CS];
-  __shared__ double red[kMaxDet][4];
+  __shared__ double red[NB][4];
   const int tid = threadIdx.x, c = tid % TC, b = tid / TC;
   load_tw16(twl, twW, tid);
   __syncthreads();
@@ -100,9 +100,9 @@ __global__ __launch_bounds__(256) void k_window_cols256_detect(const float2* __r
     return;
   }
   const long long kx = col < kW4 / 2 ? col : col - kW4;
-  double acc[kMaxDet];
+  double acc[NB];
 #pragma unroll
-  for (int q = 0; q < kMaxDet; ++q) acc[q] = 0.0;
+  for (int q = 0; q < NB; ++q) acc[q] = 0.0;
 #pragma unroll
   for (int k2 = 0; k2 < R; ++k2) {
     const int kyi = b + R * k2;
@@ -110,11 +110,11 @@ __global__ __launch_bounds__(256) void k_window_cols256_detect(const float2* __r
     const long long kk = (long long)f * f * (kx * kx + ky * ky);
     const double I = ((double)v[k2].x * v[k2].x + (double)v[k2].y * v[k2].y) * inv_w2;
 #pragma unroll
-    for (int q = 0; q < kMaxDet; ++q)
+    for (int q = 0; q < NB; ++q)
       if (q < bins.n && kk >= bins.lo[q] && kk < bins.hi[q]) acc[q] += I;
   }
 #pragma unroll
-  for (int q = 0; q < kMaxDet; ++q) {
+  for (int q = 0; q < NB; ++q) {
     if (q < bins.n) {  // uniform
       const double sum = wave_sum(acc[q]);
       if ((tid & 63) == 0) red[q][tid >> 6] = sum;
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kBigNT) void k_window_rows_lds(float2* __restrict__
   for (int e = tid; e < kBigRows * W; e += kBigNT) rows[e] = lds[lpad(e)];
 }
 
-template <int W, bool CBED>
+template <int W, bool CBED, int NB>
 __global__ __launch_bounds__(kBigNT) void k_window_cols_lds(const float2* __restrict__ window,
                                                             const float2* __restrict__ twW, int f,
                                                             DetBins bins,
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kBigNT) void k_window_cols_lds(const float2* __rest
   using B = Batch<W, kBigTC, kBigTC, 0, 1, kBigTC, true>;  // [y][c], column c is sequence c
   __shared__ float2 lds[lds_padded(W * kBigTC)];
   __shared__ float2 tw[W];
-  __shared__ double red[CBED ? 1 : kMaxDet][kBigNT / 64];
+  __shared__ double red[CBED ? 1 : NB][kBigNT / 64];
   const int tid = threadIdx.x;
   load_twiddles<W, kBigNT>(tw, twW, tid);
   const size_t p = blockIdx.x / TILES;
@@ -178,9 +178,9 @@ __global__ __launch_bounds__(kBigNT) void k_window_cols_lds(const float2* __rest
     }
     return;
   }
-  double acc[kMaxDet];
+  double acc[NB];
 #pragma unroll
-  for (int q = 0; q < kMaxDet; ++q) acc[q] = 0.0;
+  for (int q = 0; q < NB; ++q) acc[q] = 0.0;
   for (int e = tid; e < W * kBigTC; e += kBigNT) {
     const int kyi = e / kBigTC, col = tile * kBigTC + e % kBigTC;
     const long long kx = col < W / 2 ? col : col - W, ky = kyi < W / 2 ? kyi : kyi - W;
@@ -188,11 +188,11 @@ __global__ __launch_bounds__(kBigNT) void k_window_cols_lds(const float2* __rest
     const float2 z = lds[lpad(e)];
     const double I = ((double)z.x * z.x + (double)z.y * z.y) * inv_w2;
 #pragma unroll
-    for (int q = 0; q < kMaxDet; ++q)
+    for (int q = 0; q < NB; ++q)
       if (q < bins.n && kk >= bins.lo[q] && kk < bins.hi[q]) acc[q] += I;
   }
 #pragma unroll
-  for (int q = 0; q < kMaxDet; ++q) {
+  for (int q = 0; q < NB; ++q) {
     if (q < bins.n) {  // uniform
       const double sum = wave_sum(acc[q]);
       if ((tid & 63) == 0) red[q][tid >> 6] = sum;
@@ -348,6 +348,12 @@ int contract_tile_slots(int w, int window_tile_div) {
 
 int window_big_tiles(int w) { return w / 16; }
 
+// Accumulator slots of the per-element binning kernels for n bins: the
+// smallest of 4, 8, 16 and kMaxDet that holds them (the kernels test each
+// element against every slot below n, so fewer slots mean less work per
+// element; the sums are the same).
+static int bin_slots(int n) { return n <= 4 ? 4 : (n <= 8 ? 8 : (n <= 16 ? 16 : kMaxDet)); }
+
 hipError_t launch_window_big(float2* window, int np, int w, const float2* twW, int f,
                              const DetBins& bins, double* partial, float* cbed, OutAcc acc,
                              hipStream_t st) {
@@ -358,14 +364,26 @@ hipError_t launch_window_big(float2* window, int np, int w, const float2* twW, i
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)((size_t)np * window_big_tiles(w)));
-    if (want_cbed)
-      hipLaunchKernelGGL(k_window_cols256_detect<true>, grid, dim3(256), 0, st, window, twW, f,
-                         bins, (double*)nullptr, cbed, acc);
-    else
-      hipLaunchKernelGGL(k_window_cols256_detect<false>, grid, dim3(256), 0, st, window, twW, f,
-                         bins, partial, (float*)nullptr, OutAcc{});
+    if (want_cbed) {
+      hipLaunchKernelGGL((k_window_cols256_detect<true, 1>), grid, dim3(256), 0, st, window, twW,
+                         f, bins, (double*)nullptr, cbed, acc);
+      return hipGetLastError();
+    }
+#define C256(NBB)                                                                          \
+  hipLaunchKernelGGL((k_window_cols256_detect<false, NBB>), grid, dim3(256), 0, st, window, \
+                     twW, f, bins, partial, (float*)nullptr, OutAcc{})
+    switch (bin_slots(bins.n)) {
+      case 4: C256(4); break;
+      case 8: C256(8); break;
+      case 16: C256(16); break;
+      default: C256(kMaxDet); break;
+    }
+#undef C256
     return hipGetLastError();
   }
+#define WCOLS(WW, NBB)                                                                     \
+  hipLaunchKernelGGL((k_window_cols_lds<WW, false, NBB>), grid, dim3(kBigNT), 0, st, window, \
+                     twW, f, bins, partial, (float*)nullptr, OutAcc{})
 #define WBIG(WW)                                                                           \
   case WW: {                                                                               \
     hipLaunchKernelGGL(k_window_rows_lds<WW>, dim3((unsigned)((size_t)np * WW / kBigRows)), \
@@ -373,12 +391,17 @@ hipError_t launch_window_big(float2* window, int np, int w, const float2* twW, i
     hipError_t e = hipGetLastError();                                                      \
     if (e != hipSuccess) return e;                                                         \
     const dim3 grid((unsigned)((size_t)np * (WW / kBigTC)));                               \
-    if (want_cbed)                                                                         \
-      hipLaunchKernelGGL((k_window_cols_lds<WW, true>), grid, dim3(kBigNT), 0, st, window, \
-                         twW, f, bins, (double*)nullptr, cbed, acc);                       \
-    else                                                                                   \
-      hipLaunchKernelGGL((k_window_cols_lds<WW, false>), grid, dim3(kBigNT), 0, st, window, \
-                         twW, f, bins, partial, (float*)nullptr, OutAcc{});                \
+    if (want_cbed) {                                                                       \
+      hipLaunchKernelGGL((k_window_cols_lds<WW, true, 1>), grid, dim3(kBigNT), 0, st,      \
+                         window, twW, f, bins, (double*)nullptr, cbed, acc);               \
+      break;                                                                               \
+    }                                                                                      \
+    switch (bin_slots(bins.n)) {                                                           \
+      case 4: WCOLS(WW, 4); break;                                                         \
+      case 8: WCOLS(WW, 8); break;                                                         \
+      case 16: WCOLS(WW, 16); break;                                                       \
+      default: WCOLS(WW, kMaxDet); break;                                                  \
+    }                                                                                      \
     break;                                                                                 \
   }
   switch (w) {
@@ -388,6 +411,7 @@ hipError_t launch_window_big(float2* window, int np, int w, const float2* twW, i
       return hipErrorInvalidValue;
   }
 #undef WBIG
+#undef WCOLS
   return hipGetLastError();
 }
 
