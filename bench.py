@@ -40,10 +40,10 @@ CONFIG = "fcc1024"
 # write x1.0), as in the HBM-traffic summary under profiles/. Valid only for
 # the kernel sources with this hash (of their code, comments aside); reported
 # as null otherwise.
-TRAFFIC_SRC_SHA = "e12e9f7330dbe939"
-TRAFFIC_BYTES = {"row_pass": 563570899, "col_pass": 521795857, "contract": 9360449319,
-                 "s32_pack": 1310731654, "window_detect": 1079354783, "contract16": 4675091071,
-                 "s16_pack": 975210392}
+TRAFFIC_SRC_SHA = "a81852979c72bdc3"
+TRAFFIC_BYTES = {"row_pass": 563499446, "col_pass": 521796428, "contract": 9375558529,
+                 "s32_pack": 1310732154, "window_detect": 1079331347, "contract16": 4706686928,
+                 "s16_pack": 975213709}
 
 
 # Sources that decide the profiled kernels and their launch shapes (the
