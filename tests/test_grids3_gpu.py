@@ -166,3 +166,30 @@ def test_window_12_cbed(m384):
     e = eps(C, Cref)
     print(f"n=384 f=16 W=12 cbed eps_rel={e:.3e}")
     assert e <= TOL
+
+
+@pytest.mark.parametrize("case", ["mid384", "s512"])
+def test_binning_slots_w192_w256(case):
+    # The W = 144 .. 256 window kernels bin each element in registers, with
+    # accumulator slots sized to the detector (4, 8, 16 or 32). A bin's sum
+    # does not depend on how many bins there are, so 3, 6 and 12 bins equal
+    # the first columns of the 32-bin outputs bit for bit; the first six
+    # (overlapping) bins are also checked against the oracle, since PRISM at
+    # f = 1 (W = 192 on 384^2, 256 on 512^2) is multislice.
+    d = build_inputs(case, 0)
+    plan = G.make_plan(d)
+    f = 1
+    amax = _amax(d, f)
+    S = G.build_smatrix(plan, f, amax)
+    pr = d["probes"][:6]
+    edges = np.array([(5.0 * j, 5.0 * (j + 1) + (2.5 if j % 5 == 0 else 0.0))
+                      for j in range(32)])
+    D32 = G.probe_outputs(plan, f, amax, S, pr, d["optics"], edges)
+    for k in (3, 6, 12):
+        Dk = G.probe_outputs(plan, f, amax, S, pr, d["optics"], edges[:k])
+        assert np.array_equal(Dk, D32[:, :k]), f"{k} bins differ from the 32-bin columns"
+    ref = O.multislice_stem(d["phase"], d["thickness"], d["cell"], d["energy_keV"], d["optics"],
+                            pr, edges[:6])
+    e = eps(D32[:, :6], ref)
+    print(f"{case} W={plan.n // 2} bin slots 4/8/16/32 equal; 6 bins eps_rel={e:.3e}")
+    assert e <= TOL
